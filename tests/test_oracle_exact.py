@@ -1,0 +1,70 @@
+"""Pins for the exact f(A)b oracles (closed forms vs dense evaluation) and for the inputs."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as wl
+from oracle import exact
+
+
+def test_sine_basis_is_eigenbasis():
+    N = 17
+    Phi, lam = exact.sine_basis(N)
+    T = exact.laplace_factor(N)
+    assert np.allclose(T @ Phi, Phi * lam[None, :], rtol=0, atol=1e-9 * lam.max())
+    assert np.allclose(Phi @ Phi, np.eye(N), atol=1e-13)
+
+
+@pytest.mark.parametrize("kind,N,kw,fun,t", [
+    ("laplacian_2d", 11, {}, "exp", 1e-3),
+    ("anisotropic_2d", 9, {"cy": 0.01}, "exp", 1e-3),
+    ("shifted_laplacian_3d", 5, {"shift": 1.0}, "invsqrt", 1.0),
+    ("shifted_laplacian_3d", 5, {"shift": 1.0}, "exp", 1e-2),
+])
+def test_sine_closed_form_vs_dense(kind, N, kw, fun, t):
+    factors, shift = exact.problem_factors(kind, N, **kw)
+    A = exact.assemble_dense(factors, shift)
+    b = wl.gaussian_vector(A.shape[0], 0)
+    coefs = {"laplacian_2d": [1, 1], "anisotropic_2d": [1, kw.get("cy")],
+             "shifted_laplacian_3d": [1, 1, 1]}[kind]
+    x1 = exact.sine_fab(fun, b, N, coefs, shift, t)
+    x2 = (sla.expm(-t * A) if fun == "exp" else np.linalg.inv(sla.sqrtm(A)).real) @ b
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_kron_exp_nonsymmetric_vs_dense(transpose):
+    N = 6
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=20.0)
+    A = exact.assemble_dense(factors)
+    assert np.linalg.norm(A - A.T) > 1.0           # genuinely non-symmetric
+    b = wl.gaussian_vector(N ** 3, 1)
+    t = 2e-3
+    x1 = exact.kron_exp_fab(b, factors, t, transpose=transpose)
+    x2 = sla.expm(-t * (A.T if transpose else A)) @ b
+    assert np.linalg.norm(x1 - x2) <= 1e-13 * np.linalg.norm(x2)
+
+
+@pytest.mark.parametrize("build,kind,kw", [
+    (lambda N: wl.laplacian_2d(N), "laplacian_2d", {}),
+    (lambda N: wl.anisotropic_2d(N, 0.01), "anisotropic_2d", {"cy": 0.01}),
+    (lambda N: wl.convdiff_3d(N, 50.0), "convdiff_3d", {"peclet": 50.0}),
+    (lambda N: wl.shifted_laplacian_3d(N, 1.0), "shifted_laplacian_3d", {"shift": 1.0}),
+])
+def test_csr_inputs_equal_operator_definition(build, kind, kw):
+    """The CSR generator and the oracle's own factors describe the same operator."""
+    N = 5
+    A = build(N)
+    factors, shift = exact.problem_factors(kind, N, **kw)
+    D = exact.assemble_dense(factors, shift)
+    assert np.array_equal(A.to_scipy().toarray(), D) or np.allclose(A.to_scipy().toarray(), D, rtol=1e-15, atol=0)
+    rp = A.rowptr
+    for i in range(A.n):                                       # sorted, in-range columns
+        c = A.colind[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(c) > 0) and c.min() >= 0 and c.max() < A.n
+
+
+def test_published_sizes():
+    assert (wl.laplacian_2d(64).n, wl.laplacian_2d(64).nnz) == (4096, 20224)
+    A = wl.convdiff_3d(96, 20.0)
+    assert (A.n, A.nnz) == (884736, 6137856)

@@ -1,0 +1,175 @@
+"""Pins for the Krylov twins: reductions, exactness results and identities of the paper."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads as wl
+from oracle import exact, krylov, sketch
+
+
+def _rand_nonsym(n, seed):
+    rng = np.random.default_rng(seed)
+    A = sp.random(n, n, density=0.08, random_state=seed, format="csr") + sp.diags(rng.uniform(1, 3, n))
+    return sp.csr_matrix(A)
+
+
+def test_polynomial_exactness_one_cycle():
+    """Proposition (eq. rand_arnoldi_polynomial): f of degree < m is reproduced exactly, any S and k."""
+    A = _rand_nonsym(300, 0)
+    b = wl.gaussian_vector(300, 1)
+    S = sketch.sketch_matrix(300, 24, 4, seed=5)
+    sq = lambda M: M @ M
+    x, info = krylov.restart_solve(A, b, sq, m=6, k=2, S=S, max_cycles=1, evaluation="growing")
+    ref = A @ (A @ b)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_full_dimension_is_exact():
+    """m >= dim K(A, b) gives f(A) b exactly (here via a breakdown at the dimension)."""
+    A = wl.laplacian_2d(5)
+    As = A.to_scipy()
+    b = wl.gaussian_vector(25, 2)
+    S = sketch.sketch_matrix(25, 26, 25, seed=1)
+    x, info = krylov.restart_solve(As, b, "exp", t=0.01, m=25, k=2, S=S, tol=1e-14, evaluation="growing")
+    ref = sla.expm(-0.01 * As.toarray()) @ b
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_window_at_least_m_gives_identity_whitening():
+    """k >= m: RGS keeps S W orthonormal, so T = I, X = R_m and h = r_{m+1,m} (restart-rand)."""
+    A = wl.convdiff_3d(8, 20.0).to_scipy()
+    b = wl.gaussian_vector(A.shape[0], 3)
+    S = sketch.sketch_matrix(A.shape[0], 120, 8, seed=4)
+    c = krylov.sketched_cycle(A, S, b, m=20, k=20)
+    assert np.linalg.norm(c.T - np.eye(21)) < 1e-12
+    assert np.linalg.norm(c.X - c.R[:20, :20]) < 1e-12 * np.linalg.norm(c.R)
+    assert abs(c.h - c.R[20, 19]) < 1e-12 * abs(c.h)
+
+
+def test_identity_sketch_reduces_to_arnoldi():
+    """S = I_n with k >= m: randomized Arnoldi is classical (MGS) Arnoldi."""
+    A = _rand_nonsym(60, 4)
+    b = wl.gaussian_vector(60, 5)
+    S = sp.identity(60, format="csr")
+    c1 = krylov.sketched_cycle(A, S, b, m=12, k=12)
+    c2 = krylov.arnoldi_cycle(A, b, m=12)
+    assert np.allclose(c1.W[:, :13], c2.W[:, :13], atol=1e-12)
+    assert np.allclose(c1.X, c2.X, atol=1e-11)
+    assert abs(c1.h - c2.h) < 1e-11
+
+
+def test_similarity_lemma():
+    """Lemma (eq. similarity): Z R Z^-1 = H - (r/z_mm) c e_m^T with W = V Z, c = V^T w_{m+1}."""
+    A = _rand_nonsym(80, 6)
+    b = wl.gaussian_vector(80, 7)
+    S = sketch.sketch_matrix(80, 40, 8, seed=8)
+    W, U, R, alpha, m_eff, brk = krylov.randomized_arnoldi_window(A, S, b, 8, 8)
+    m = 8
+    V, Z = np.linalg.qr(W[:, :m])
+    s = np.sign(np.diag(Z))
+    V, Z = V * s, Z * s[:, None]
+    H = V.T @ (A @ V)
+    c = V.T @ W[:, m]
+    lhs = Z @ R[:m, :m] @ np.linalg.inv(Z)
+    rhs = H - (R[m, m - 1] / Z[m - 1, m - 1]) * np.outer(c, np.eye(m)[m - 1])
+    assert np.linalg.norm(lhs - rhs) < 1e-10 * np.linalg.norm(H)
+
+
+def test_whitened_arnoldi_relation():
+    """A V = V X + h v_hat e_m^T and S v_hat has unit norm after whitening (truncated k)."""
+    A = wl.convdiff_3d(10, 50.0).to_scipy()
+    b = wl.gaussian_vector(A.shape[0], 9)
+    S = sketch.sketch_matrix(A.shape[0], 80, 8, seed=1)
+    c = krylov.sketched_cycle(A, S, b, m=20, k=2)
+    V = c.W[:, :20] @ c.Tinv
+    res = A @ V - V @ c.X - c.h * np.outer(c.vhat, np.eye(20)[19])
+    assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(A @ V)
+    assert abs(np.linalg.norm(S @ c.vhat) - 1.0) < 1e-10
+    assert np.linalg.norm(b - c.beta * V[:, 0]) < 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0)])
+def test_quadrature_restart_equals_growing_matrix(fun, t):
+    """The quadrature recursion reproduces block c of f(M_c) e_1 over many cycles."""
+    if fun == "exp":
+        A = wl.convdiff_3d(12, 20.0).to_scipy()
+        spec = None
+    else:
+        A = wl.shifted_laplacian_3d(12, 1.0).to_scipy()
+        spec = (3 * np.pi ** 2 + 1, 12 * 13 ** 2 + 1)
+    b = wl.gaussian_vector(A.shape[0], 10)
+    S = sketch.sketch_matrix(A.shape[0], 40, 8, seed=2)
+    kw = dict(m=8, k=2, S=S, tol=0.0, max_cycles=6, spec=spec)
+    xq, iq = krylov.restart_solve(A, b, fun, t, evaluation="quadrature", **kw)
+    xg, ig = krylov.restart_solve(A, b, fun, t, evaluation="growing", **kw)
+    for hq, hg in zip(iq.history, ig.history):
+        assert np.linalg.norm(hq["g"] - hg["g"]) <= 1e-11 * np.linalg.norm(xg) + 1e-300
+    assert np.linalg.norm(xq - xg) <= 1e-11 * np.linalg.norm(xg)
+
+
+def test_scaling_invariance():
+    A = wl.laplacian_2d(20).to_scipy()
+    b = wl.gaussian_vector(400, 11)
+    S = sketch.sketch_matrix(400, 40, 8, seed=3)
+    x1, _ = krylov.restart_solve(A, b, "exp", 1e-3, m=10, k=2, S=S, tol=1e-12)
+    x3, _ = krylov.restart_solve(A, 3.0 * b, "exp", 1e-3, m=10, k=2, S=S, tol=1e-12)
+    assert np.linalg.norm(x3 - 3.0 * x1) <= 1e-13 * np.linalg.norm(x3)
+
+
+def test_breakdown_on_eigenvector_is_exact():
+    N = 16
+    Phi, lam = exact.sine_basis(N)
+    v = np.kron(Phi[:, 2], Phi[:, 4])                 # eigenvector of the 2-D Laplacian
+    A = wl.laplacian_2d(N).to_scipy()
+    S = sketch.sketch_matrix(N * N, 40, 8, seed=1)
+    x, info = krylov.restart_solve(A, v, "exp", 1e-3, m=10, k=2, S=S, tol=1e-12)
+    assert info.status == "breakdown" and info.cycles == 1
+    ref = np.exp(-1e-3 * (lam[2] + lam[4])) * v
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_laplacian_2d_64_closed_form():
+    """The 4096-row workload: tol 1e-10, relative error against the sine closed form."""
+    A = wl.laplacian_2d(64)
+    b = wl.gaussian_vector(A.n, 0)
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    ref = exact.sine_fab("exp", b, 64, [1, 1], t=1e-3)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "exp", 1e-3, m=20, k=2, S=S, tol=1e-10)
+    assert info.status == "ok"
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert info.quad_disagreement < 1e-11
+
+
+@pytest.mark.parametrize("method", ["sketched", "plain"])
+def test_convdiff_small_vs_kronecker(method):
+    N = 24
+    A = wl.convdiff_3d(N, 50.0)
+    b = wl.gaussian_vector(A.n, 0)
+    t = 20.0 / (12 * (N + 1) ** 2)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=50.0)
+    ref = exact.kron_exp_fab(b, factors, t)
+    S = sketch.sketch_matrix(A.n, 200, 8, seed=1)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=50, k=4, S=S, tol=1e-8, method=method)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_invsqrt_shifted_laplacian_closed_form():
+    N = 16
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    b = wl.gaussian_vector(A.n, 0)
+    ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], 1.0)
+    spec = (3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2 + 1, 12 * (N + 1) ** 2 + 1)
+    S = sketch.sketch_matrix(A.n, 120, 8, seed=1)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "invsqrt", m=30, k=2, S=S, tol=1e-10,
+                                   spec=spec, max_cycles=200)
+    assert info.status == "ok", info.cycles
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_unrestarted_arnoldi_matches_closed_form():
+    A = wl.laplacian_2d(30)
+    b = wl.gaussian_vector(A.n, 4)
+    ref = exact.sine_fab("exp", b, 30, [1, 1], t=1e-3)
+    x = krylov.arnoldi_full(A.to_scipy(), b, 60, "exp", 1e-3)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)

@@ -1,0 +1,90 @@
+"""Pins for the dense matrix functions and the quadrature rules of the oracle."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import matfun, quadrature
+
+
+@pytest.mark.parametrize("theta", [0.3, 2.0, 50.0])
+def test_expm_rotation_closed_form(theta):
+    G = np.array([[0.0, -theta], [theta, 0.0]])
+    E = matfun.expm(G)
+    R = np.array([[np.cos(theta), -np.sin(theta)], [np.sin(theta), np.cos(theta)]])
+    assert np.max(np.abs(E - R)) < 1e-13 * max(1.0, theta)
+
+
+def test_expm_nilpotent_and_diagonal():
+    N = np.triu(np.random.default_rng(0).standard_normal((4, 4)), 1)
+    assert np.allclose(matfun.expm(N), np.eye(4) + N + N @ N / 2 + N @ N @ N / 6, atol=1e-14, rtol=0)
+    d = np.array([-30.0, -1.0, 0.5, 3.0])
+    assert np.allclose(matfun.expm(np.diag(d)), np.diag(np.exp(d)), rtol=1e-14, atol=0)
+
+
+def test_pade13_accuracy_at_threshold():
+    """The [13/13] approximant meets unit roundoff at |x| = theta_13 (the scaling threshold)."""
+    c = matfun.PADE13
+    for x in (matfun.THETA13, -matfun.THETA13, 1.0):
+        num = np.polyval(c[::-1], x)
+        den = np.polyval(c[::-1], -x)
+        assert abs(num / den / np.exp(x) - 1.0) < 2e-15
+
+
+def test_expm_matches_scipy_nonnormal():
+    rng = np.random.default_rng(1)
+    for scale in (0.1, 3.0, 40.0):
+        A = scale * rng.standard_normal((12, 12)) / 4
+        A += np.triu(rng.standard_normal((12, 12)), 1) * scale
+        E1, E2 = matfun.expm(A), sla.expm(A)
+        assert np.linalg.norm(E1 - E2) <= 1e-12 * np.linalg.norm(E2) * max(1, scale)
+
+
+def test_invsqrt_closed_form_and_identity():
+    rng = np.random.default_rng(2)
+    Q, _ = np.linalg.qr(rng.standard_normal((8, 8)))
+    lam = np.geomspace(0.5, 300.0, 8)
+    A = Q @ np.diag(lam) @ Q.T
+    Y = matfun.invsqrt(A)
+    assert np.allclose(Y, Q @ np.diag(lam ** -0.5) @ Q.T, rtol=0, atol=1e-12)
+    B = A + np.triu(rng.standard_normal((8, 8)), 1)        # non-normal, same spectrum
+    Yb = matfun.invsqrt(B)
+    assert np.linalg.norm(Yb @ Yb @ B - np.eye(8)) < 1e-10
+
+
+def _sector_points(n=400):
+    """Points s = -t z with Re s in [-45, 0.5] and |Im s| <= 0.75 |Re s| + 4 (sketched Ritz region)."""
+    rng = np.random.default_rng(3)
+    re = rng.uniform(-45.0, 0.5, n)
+    im = rng.uniform(-1, 1, n) * (0.75 * np.abs(re) + 4.0)
+    return re + 1j * im
+
+
+@pytest.mark.parametrize("t", [1e-3, 1e-4, 1.0])
+def test_exp_rule_scalar_accuracy(t):
+    s = _sector_points()
+    z = -s / t
+    for (N, P, mu, L) in (quadrature.EXP_MAIN, quadrature.EXP_CHECK):
+        zeta, w = quadrature.exp_rule(t, N, P, mu, L)
+        r = quadrature.rational_scalar(zeta, w, z)
+        err = np.abs(r - np.exp(-t * z))
+        assert err.max() < 1e-12, (N, err.max())
+
+
+def test_exp_rule_conjugate_pairs():
+    zeta, w = quadrature.exp_rule(1e-3)
+    zh, wh = quadrature.conjugate_half(zeta, w)
+    assert len(zh) == len(zeta) // 2
+    z = np.array([50.0, 2000.0, 33000.0])
+    full = quadrature.rational_scalar(zeta, w, z)
+    half = 2 * quadrature.rational_scalar(zh, wh, z).real
+    assert np.allclose(full.real, half, rtol=1e-13, atol=1e-16)
+    assert np.max(np.abs(full.imag)) < 1e-13
+
+
+def test_invsqrt_rule_accuracy():
+    lo, hi = 30.6, 7.93e5
+    zeta, w = quadrature.invsqrt_rule(128, lo, hi)
+    z = np.geomspace(lo, hi, 300)
+    for zz in (z, z * np.exp(0.5j)):
+        r = quadrature.rational_scalar(zeta, w, zz)
+        assert np.max(np.abs(r * np.sqrt(zz) - 1.0)) < 1e-14
