@@ -1,0 +1,141 @@
+/*
+ * fab.h -- C ABI of libfab: the restarted, sketched, window-truncated Krylov
+ * method for the action of a matrix function, x = f(A) b, on one AMD MI355X
+ * (gfx950) GPU.
+ *
+ * Method (Guidotti, Martinsson, Acebron, Monteiro, "Accelerating a restarted
+ * Krylov method for matrix functions with randomization"):
+ *   - each cycle runs the randomized Arnoldi iteration of Algorithm 1, with the
+ *     sketch-space Gram-Schmidt limited to the last k basis vectors;
+ *   - the sketch S is the sparse sign matrix of eq. (sparse_sign_sketch),
+ *     zeta nonzeros of +-1/sqrt(zeta) per column in distinct rows;
+ *   - the basis is whitened by a thin QR of S W (appendix, eq. A.1), which
+ *     keeps the decomposition A V = V X + h v e_m^T Arnoldi-like
+ *     (eq. rand_arnoldi);
+ *   - cycles are chained as in Algorithm 2 / eq. (restart_combined), but f of
+ *     the growing block matrix is evaluated through a fixed quadrature rule
+ *     (the quadrature-based restart Section 4 names), so the per-cycle small
+ *     work stays m x m;
+ *   - the loop stops when ||y_c|| <= tol ||x|| for every time point (the
+ *     successive-difference error estimate after Algorithm 2, relative form).
+ *
+ * Conventions
+ *   - Every pointer is DEVICE memory unless its name starts with h_.
+ *   - Every call returns fab_status and never aborts.  Negative values are
+ *     errors (nothing usable was produced); positive values are results with a
+ *     note (FAB_OK_BREAKDOWN is exact; FAB_W_* are warnings).
+ *   - Work is enqueued on the context's HIP stream.  fab_solve returns after
+ *     h_info is filled (it synchronises the stream once per cycle).
+ *   - Ownership: the caller owns and keeps alive A's arrays, b, x and the
+ *     workspace (typically torch tensors).  The library owns fab_ctx and fab_op
+ *     objects (and nothing else on the device).
+ *   - Thread safety: one context per host thread; calls on one context are
+ *     serialised by the caller.
+ */
+#ifndef FAB_H
+#define FAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FAB_OK = 0,
+  FAB_OK_BREAKDOWN = 1,     /* invariant Krylov subspace found: result exact */
+  FAB_W_NOT_CONVERGED = 2,  /* max_cycles reached; x holds the last iterate  */
+  FAB_W_QUADRATURE = 3,     /* main and check quadrature rules disagree       */
+  FAB_E_INVALID = -1,       /* bad argument (sizes, nulls, parameter ranges)  */
+  FAB_E_UNSUPPORTED = -2,   /* valid but not supported by this build          */
+  FAB_E_HIP = -3,           /* a HIP runtime call failed                      */
+  FAB_E_NONFINITE = -4,     /* NaN/Inf met in the iteration (A or b)          */
+  FAB_E_DIVERGED = -5,      /* estimate grew 10x over two cycles              */
+  FAB_E_WORKSPACE = -6      /* work_bytes smaller than fab_workspace_size     */
+} fab_status;
+
+typedef enum { FAB_F64 = 0, FAB_F32 = 1 } fab_dtype;        /* A values and basis; x is FP64 */
+typedef enum { FAB_EXP_NEG = 0, FAB_INVSQRT = 1 } fab_fun;  /* exp(-t z) ; z^(-1/2)          */
+typedef enum { FAB_SKETCHED = 0, FAB_PLAIN_RESTART = 1 } fab_method;
+
+/* Solver parameters (Algorithm 2's arguments plus the sketch). */
+typedef struct {
+  int32_t m;          /* cycle length (basis size per cycle), 1 <= m <= 64            */
+  int32_t k;          /* truncation window of the Gram-Schmidt, 1 <= k <= m          */
+  int32_t d;          /* sketch rows, m+1 <= d <= 2048                                */
+  int32_t zeta;       /* nonzeros per sketch column, 1 <= zeta <= min(32, d)          */
+  uint64_t seed;      /* defines S (Philox4x32-10 counter-based spec, see fab_sketch_table) */
+  double tol;         /* relative update tolerance, >= 0                              */
+  int32_t max_cycles; /* >= 1                                                          */
+  int32_t method;     /* fab_method; FAB_PLAIN_RESTART ignores k, d, zeta, seed        */
+  int32_t n_quad;     /* 0 = default rule size (128)                                  */
+  double spec_lo;     /* spectral interval for FAB_INVSQRT (required there, > 0)      */
+  double spec_hi;
+} fab_params;
+
+typedef struct {
+  int32_t status;          /* fab_status of the solve                               */
+  int32_t cycles;          /* restart cycles run                                    */
+  int32_t matvecs;         /* products with A                                       */
+  int32_t reserved;
+  double est_rel_update;   /* max_t ||y_t|| / ||x_t|| of the last cycle             */
+  double quad_disagreement;/* max over cycles of ||g_main - g_check|| / ||x||        */
+} fab_info;
+
+typedef struct fab_ctx fab_ctx;
+typedef struct fab_op fab_op;
+
+/* Create a context bound to the current HIP device and to hip_stream (a
+ * hipStream_t; NULL = the null stream).  Errors: FAB_E_INVALID (ctx NULL),
+ * FAB_E_HIP. */
+fab_status fab_create(fab_ctx** ctx, void* hip_stream);
+fab_status fab_destroy(fab_ctx* ctx);
+
+/* Wrap a CSR matrix (n x n) without copying.  rowptr[n+1], colind[nnz] are
+ * int32 (ascending columns per row are not required); vals[nnz] are FP64 or FP32
+ * (dtype).  BORROWS the three arrays: they must outlive the operator.
+ * Errors: FAB_E_INVALID (n <= 0, nnz < 0, nnz >= 2^31, null pointers). */
+fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                          const int32_t* colind, const void* vals, int32_t dtype, fab_op** op);
+fab_status fab_op_destroy(fab_op* op);
+
+/* Bytes of device workspace fab_solve needs for nt time points. */
+fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, size_t* h_bytes);
+
+/* x[:, i] = f_i(A) b for the nt values h_t[i] (exp(-t_i z)), or nt = 1 for
+ * z^(-1/2).  b[n] has A's dtype; x is n x nt FP64, column-major (ldx = n),
+ * overwritten.  work is device memory of at least fab_workspace_size bytes,
+ * 256-byte aligned.  h_info is filled on every return >= FAB_E_HIP. */
+fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt,
+                     const void* b, double* x, const fab_params* p, void* work, size_t work_bytes,
+                     fab_info* h_info);
+
+/* ---- test hooks: the same kernels as fab_solve, exposed for parity tests ---- */
+
+/* y = A x (A's dtype for x and y). */
+fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void* work, size_t work_bytes);
+
+/* Sx[d] (FP64) = S x for the sparse sign matrix defined by (n, d, zeta, seed);
+ * x has dtype. */
+fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed,
+                            int32_t dtype, const void* x, double* Sx, void* work, size_t work_bytes);
+
+/* The sketch specification itself: for columns col0 .. col0+count-1, the rows
+ * (int32, count x zeta, row-major) and signs (int8, +1/-1) of S. */
+fab_status fab_sketch_table(fab_ctx* ctx, int64_t col0, int64_t count, int32_t d, int32_t zeta,
+                            uint64_t seed, int32_t* rows, int8_t* signs);
+
+/* One cycle from start vector v (A's dtype), exposing its intermediates:
+ * W n x (m+1) (A's dtype, column-major), U d x (m+1), R (m+1) x m,
+ * T (m+1) x (m+1), X m x m (all FP64 column-major), h_scal[4] = {alpha, beta, h, m_eff}. */
+fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const fab_params* p,
+                           void* W, double* U, double* R, double* T, double* X, double* h_scal,
+                           void* work, size_t work_bytes);
+
+const char* fab_status_string(fab_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAB_H */

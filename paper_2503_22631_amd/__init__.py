@@ -1,0 +1,198 @@
+"""fab: restarted, sketched, window-truncated Krylov approximation of f(A) b on MI355X.
+
+Thin Python binding of libfab (include/fab.h): argument marshalling over torch device
+tensors, nothing else.  Every step of the method runs in the HIP kernels of the library;
+if ``libfab.so`` is not built, importing the binding's entry points raises.
+
+    ctx = fab.Context()
+    A = fab.CSROperator.from_arrays(ctx, rowptr, colind, vals)     # torch/numpy, copied to the GPU
+    x, info = fab.solve(A, b, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, tol=1e-10)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FabError, fab_info, fab_params
+
+FUN = {"exp": 0, "invsqrt": 1}
+METHOD = {"sketched": 0, "plain": 1}
+DTYPE = {torch.float64: 0, torch.float32: 1}
+
+__all__ = ["Context", "CSROperator", "Params", "solve", "workspace_size", "spmv", "sketch_apply",
+           "sketch_table", "cycle_debug", "FabError", "lib_path"]
+
+
+def lib_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libfab context bound to one GPU and to the current torch stream of that GPU."""
+
+    def __init__(self, device=None, stream: torch.cuda.Stream | None = None):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("fab needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _lib.check(self.lib.fab_create(ctypes.byref(h), ctypes.c_void_p(s.cuda_stream)), "fab_create", ok=(0,))
+        self.handle = h
+        self._ws = {}
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A cached device byte buffer of at least nbytes (256-byte aligned)."""
+        buf = self._ws.get("main")
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            assert buf.data_ptr() % 256 == 0
+            self._ws["main"] = buf
+        return buf
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fab_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CSROperator:
+    """A CSR matrix on the device (int32 indices, FP64 or FP32 values); libfab borrows the arrays."""
+
+    def __init__(self, ctx: Context, rowptr: torch.Tensor, colind: torch.Tensor, vals: torch.Tensor):
+        assert rowptr.dtype == torch.int32 and colind.dtype == torch.int32 and vals.dtype in DTYPE
+        assert rowptr.is_cuda and colind.is_cuda and vals.is_cuda
+        self.ctx, self.rowptr, self.colind, self.vals = ctx, rowptr.contiguous(), colind.contiguous(), vals.contiguous()
+        self.n = rowptr.numel() - 1
+        self.nnz = colind.numel()
+        self.dtype = vals.dtype
+        h = ctypes.c_void_p()
+        _lib.check(ctx.lib.fab_csr_create(ctx.handle, self.n, self.nnz, _ptr(self.rowptr), _ptr(self.colind),
+                                          _ptr(self.vals), DTYPE[self.dtype], ctypes.byref(h)),
+                   "fab_csr_create", ok=(0,))
+        self.handle = h
+
+    @classmethod
+    def from_arrays(cls, ctx: Context, rowptr, colind, vals, dtype=None):
+        dev = ctx.device
+        rp = torch.as_tensor(np.asarray(rowptr, dtype=np.int32)).to(dev)
+        ci = torch.as_tensor(np.asarray(colind, dtype=np.int32)).to(dev)
+        v = torch.as_tensor(np.asarray(vals))
+        if dtype is not None:
+            v = v.to(dtype)
+        return cls(ctx, rp, ci, v.to(dev))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.fab_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def Params(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=100, method="sketched", n_quad=0,
+           spec=None) -> fab_params:
+    lo, hi = (0.0, 0.0) if spec is None else (float(spec[0]), float(spec[1]))
+    return fab_params(int(m), int(k), int(d), int(zeta), int(seed) & (2 ** 64 - 1), float(tol), int(max_cycles),
+                      METHOD[method] if isinstance(method, str) else int(method), int(n_quad), lo, hi)
+
+
+def workspace_size(op: CSROperator, p: fab_params, nt: int = 1) -> int:
+    nb = ctypes.c_size_t()
+    _lib.check(op.ctx.lib.fab_workspace_size(op.handle, ctypes.byref(p), int(nt), ctypes.byref(nb)),
+               "fab_workspace_size", ok=(0,))
+    return int(nb.value)
+
+
+def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.Tensor | None = None,
+          work: torch.Tensor | None = None, check: bool = True, **kw):
+    """x[:, i] = f_i(A) b.  Returns (x, info) with x of shape (n, nt) (FP64) and info a dict.
+
+    ``t`` is a float or a sequence of time points (exp only).  Extra keywords go to ``Params``.
+    Negative statuses raise FabError when ``check`` is true.
+    """
+    ctx = op.ctx
+    p = kw.pop("params", None) or Params(**kw)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    nt = len(ts)
+    assert b.is_cuda and b.dtype == op.dtype and b.numel() == op.n
+    b = b.contiguous()
+    if x is None:
+        x = torch.empty((nt, op.n), dtype=torch.float64, device=ctx.device)
+    assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == nt * op.n
+    nbytes = workspace_size(op, p, nt)
+    if work is None:
+        work = ctx.workspace(nbytes)
+    info = fab_info()
+    tarr = (ctypes.c_double * nt)(*ts.tolist())
+    st = ctx.lib.fab_solve(ctx.handle, op.handle, FUN[fun], tarr, nt, _ptr(b), _ptr(x), ctypes.byref(p),
+                           _ptr(work), work.numel(), ctypes.byref(info))
+    if check:
+        _lib.check(st, "fab_solve")
+    out = {"status": _lib.STATUS.get(info.status, info.status), "code": int(st), "cycles": info.cycles,
+           "matvecs": info.matvecs, "est_rel_update": info.est_rel_update,
+           "quad_disagreement": info.quad_disagreement}
+    return x.view(nt, op.n).t(), out
+
+
+def spmv(op: CSROperator, xv: torch.Tensor) -> torch.Tensor:
+    y = torch.empty_like(xv)
+    _lib.check(op.ctx.lib.fab_spmv(op.ctx.handle, op.handle, _ptr(xv.contiguous()), _ptr(y), None, 0),
+               "fab_spmv", ok=(0,))
+    return y
+
+
+def sketch_apply(ctx: Context, xv: torch.Tensor, d: int, zeta: int, seed: int) -> torch.Tensor:
+    out = torch.empty(d, dtype=torch.float64, device=ctx.device)
+    ws = torch.empty(8 * 8 * d + 256, dtype=torch.uint8, device=ctx.device)
+    _lib.check(ctx.lib.fab_sketch_apply(ctx.handle, xv.numel(), d, zeta, int(seed), DTYPE[xv.dtype],
+                                        _ptr(xv.contiguous()), _ptr(out), _ptr(ws), ws.numel()),
+               "fab_sketch_apply", ok=(0,))
+    return out
+
+
+def sketch_table(ctx: Context, col0: int, count: int, d: int, zeta: int, seed: int):
+    rows = torch.empty((count, zeta), dtype=torch.int32, device=ctx.device)
+    signs = torch.empty((count, zeta), dtype=torch.int8, device=ctx.device)
+    _lib.check(ctx.lib.fab_sketch_table(ctx.handle, col0, count, d, zeta, int(seed), _ptr(rows), _ptr(signs)),
+               "fab_sketch_table", ok=(0,))
+    return rows, signs
+
+
+def cycle_debug(op: CSROperator, v: torch.Tensor, **kw):
+    """One cycle from v; returns the basis and small matrices of the whitened decomposition."""
+    ctx = op.ctx
+    p = Params(**kw)
+    m, d = p.m, p.d
+    dev = ctx.device
+    W = torch.empty((m + 1, op.n), dtype=op.dtype, device=dev)
+    U = torch.zeros((m + 1, d), dtype=torch.float64, device=dev)
+    R = torch.empty((m, m + 1), dtype=torch.float64, device=dev)
+    T = torch.empty((m + 1, m + 1), dtype=torch.float64, device=dev)
+    X = torch.empty((m, m), dtype=torch.float64, device=dev)
+    scal = (ctypes.c_double * 4)()
+    work = ctx.workspace(workspace_size(op, p, 1))
+    st = ctx.lib.fab_cycle_debug(ctx.handle, op.handle, _ptr(v.contiguous()), ctypes.byref(p), _ptr(W), _ptr(U),
+                                 _ptr(R), _ptr(T), _ptr(X), scal, _ptr(work), work.numel())
+    _lib.check(st, "fab_cycle_debug", ok=(0,))
+    meff = int(scal[3])
+    return {"W": W.t(), "U": U.t(), "R": R.t(), "T": T.t(), "X": X.t(), "alpha": scal[0], "beta": scal[1],
+            "h": scal[2], "m": meff}

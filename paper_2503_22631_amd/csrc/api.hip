@@ -1,0 +1,552 @@
+// Host driver and C ABI of libfab (see include/fab.h for the contract).
+//
+// One fab_solve runs the restarted loop of Algorithm 2.  Every cycle is the same sequence of
+// kernel launches (cycle start, m steps of sketch + orthogonalisation + update, cycle-end small
+// work, fused pass, convergence test), so a cycle is captured once as a hipGraph and replayed;
+// the host reads one small report per cycle to decide whether to stop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fab.h"
+#include "fab_internal.h"
+
+namespace fab {
+hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
+                              const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
+                              double* slots, const State* st);
+hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
+                       double* R, State* st);
+hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st);
+hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
+                       double* slots, int want_norm, const State* st);
+hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
+                             double* slots_zero, double* norm_slots, int want_norm, double* R, State* st);
+hipError_t launch_plain_finish(hipStream_t, int j, int m, double* norm_slots, double* R, State* st);
+hipError_t launch_scale_col(hipStream_t, int dtype, int grid, int n, void* v, const double* s_ptr,
+                            const State* st);
+hipError_t launch_zero(hipStream_t, double* p, size_t count);
+hipError_t launch_rule(hipStream_t, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
+                       cplx* rz, cplx* rw, cplx* psi);
+hipError_t launch_copy_in(hipStream_t, int dtype, int grid, int n, const void* b, void* w0);
+hipError_t launch_sqnorm(hipStream_t, int dtype, int grid, int n, const void* v, double* slots);
+hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_start, double* slots_step,
+                        size_t step_len, double* U, double* R, State* st);
+
+hipError_t launch_small(hipStream_t, const SmallArgs& a);
+hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, const double* C, void* W, double* x,
+                       double* norm_slots, const State* st);
+hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep);
+hipError_t launch_reduce_slots(hipStream_t, int len, const double* slots, double* out);
+hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
+                               int8_t* signs);
+}  // namespace fab
+
+using namespace fab;
+
+struct GraphKey {
+  const void* op;
+  const void* work;
+  const void* x;
+  int64_t n;
+  int m, k, d, zeta, nt, fun, method, nq, dtype;
+  uint64_t seed;
+  double tol;
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+struct fab_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t work = nullptr;
+  hipEvent_t ev = nullptr;
+  Report* h_rep = nullptr;
+  double* h_t = nullptr;  // pinned staging for the time points
+  int num_cu = 256;
+  struct Cached {
+    GraphKey key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Cached> graphs;
+};
+
+struct fab_op {
+  fab_ctx* ctx;
+  int64_t n, nnz;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const void* vals;
+  int dtype;
+};
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int rule_nodes(int fun, const fab_params* p) { return (p->n_quad > 0) ? p->n_quad : kRuleMain; }
+
+static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, int nt) {
+  Layout L{};
+  const size_t es = dtype == 0 ? 8 : 4;
+  const int m = p->m;
+  const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
+  const int N = rule_nodes(fun, p);
+  L.nq_main = (fun == FAB_EXP_NEG) ? N / 2 : N;
+  L.nq_chk = (fun == FAB_EXP_NEG) ? ((3 * N) / 4) / 2 : (3 * N) / 4;
+  L.nsys = nt * (L.nq_main + L.nq_chk);
+  L.ldscr = L.nsys;
+  const size_t step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.W = take((size_t)n * (m + 1) * es);
+  L.U = take((size_t)d * (m + 1) * 8);
+  L.R = take((size_t)(m + 1) * m * 8);
+  L.slots_step = take(2 * step_len * 8);
+  L.slots_start = take((size_t)kSlots * std::max(d, kSlots) * 8);
+  L.slots_norm = take((size_t)kSlots * 2 * kMaxNt * 8);
+  L.state = take(sizeof(State));
+  L.T = take((size_t)(m + 1) * (m + 1) * 8);
+  L.Ut = take((size_t)d * (m + 1) * 8);
+  L.X = take((size_t)m * m * 8);
+  L.C = take((size_t)(m + 1) * (nt + 1) * 8);
+  L.rule_z = take((size_t)L.nsys * sizeof(cplx));
+  L.rule_w = take((size_t)L.nsys * sizeof(cplx));
+  L.psi = take((size_t)L.nsys * sizeof(cplx));
+  L.gbuf = take((size_t)2 * nt * m * 8 + (size_t)nt * 8 /* t values */);
+  const size_t per_sys = (size_t)3 * m + (size_t)m * (m + 1) / 2;
+  L.scratch = take(per_sys * L.nsys * sizeof(cplx));
+  L.report = 0;
+  L.total = off;
+  return L;
+}
+
+static fab_status check_params(const fab_op* A, const fab_params* p, int fun, int nt) {
+  if (!A || !p) return FAB_E_INVALID;
+  if (p->m < 1 || p->m > kMaxM) return FAB_E_INVALID;
+  if (p->method != FAB_SKETCHED && p->method != FAB_PLAIN_RESTART) return FAB_E_INVALID;
+  if (p->method == FAB_SKETCHED) {
+    if (p->k < 1 || p->k > p->m) return FAB_E_INVALID;
+    if (p->d < p->m + 1 || p->d > kMaxD) return FAB_E_INVALID;
+    if (p->zeta < 1 || p->zeta > 32 || p->zeta > p->d) return FAB_E_INVALID;
+  }
+  if (!(p->tol >= 0.0) || p->max_cycles < 1) return FAB_E_INVALID;
+  if (p->n_quad != 0 && (p->n_quad < 8 || p->n_quad > 512 || (p->n_quad % 8) != 0)) return FAB_E_INVALID;
+  if (fun == FAB_EXP_NEG) {
+    if (nt < 1 || nt > kMaxNt) return FAB_E_INVALID;
+  } else if (fun == FAB_INVSQRT) {
+    if (nt != 1) return FAB_E_INVALID;
+    if (!(p->spec_lo > 0.0) || !(p->spec_hi >= p->spec_lo) || !std::isfinite(p->spec_hi)) return FAB_E_INVALID;
+  } else {
+    return FAB_E_INVALID;
+  }
+  if (A->n >= (int64_t)1 << 31) return FAB_E_UNSUPPORTED;
+  return FAB_OK;
+}
+
+static int stream_grid(int64_t n, int cap) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  g = std::min<int64_t>(g, cap);
+  g = ((g + kXcds - 1) / kXcds) * kXcds;
+  return (int)std::max<int64_t>(g, kXcds);
+}
+
+struct Ptrs {
+  char* base;
+  void* W;
+  double *U, *R, *slots_step, *slots_start, *slots_norm, *T, *Ut, *X, *C, *gbuf, *tvals;
+  State* st;
+  cplx *rz, *rw, *psi, *scr;
+  size_t step_len;
+};
+
+static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
+  Ptrs q{};
+  q.base = (char*)work;
+  q.W = q.base + L.W;
+  q.U = (double*)(q.base + L.U);
+  q.R = (double*)(q.base + L.R);
+  q.slots_step = (double*)(q.base + L.slots_step);
+  q.slots_start = (double*)(q.base + L.slots_start);
+  q.slots_norm = (double*)(q.base + L.slots_norm);
+  q.st = (State*)(q.base + L.state);
+  q.T = (double*)(q.base + L.T);
+  q.Ut = (double*)(q.base + L.Ut);
+  q.X = (double*)(q.base + L.X);
+  q.C = (double*)(q.base + L.C);
+  q.rz = (cplx*)(q.base + L.rule_z);
+  q.rw = (cplx*)(q.base + L.rule_w);
+  q.psi = (cplx*)(q.base + L.psi);
+  q.gbuf = (double*)(q.base + L.gbuf);
+  q.tvals = q.gbuf + (size_t)2 * nt * p->m;
+  q.scr = (cplx*)(q.base + L.scratch);
+  const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
+  q.step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
+  return q;
+}
+
+#define FAB_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return FAB_E_HIP;   \
+  } while (0)
+
+// Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
+static fab_status enqueue_cycle(hipStream_t s, const fab_op* A, const fab_params* p, int fun, int nt,
+                                const Layout& L, const Ptrs& q, double* x, Report* rep, bool with_pass) {
+  const int n = (int)A->n, m = p->m, dt = A->dtype;
+  const size_t es = dt == 0 ? 8 : 4;
+  const bool plain = p->method == FAB_PLAIN_RESTART;
+  const int d = plain ? 1 : p->d;
+  const int g_spmv = stream_grid(n, 2048);
+  const int g_vec = stream_grid(n, 2048);
+  auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * n * es; };
+  if (!plain) {
+    FAB_TRY(launch_spmv_sketch(s, dt, 1, g_spmv, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
+                               p->seed, q.slots_start, nullptr));
+  } else {
+    FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
+  }
+  FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st));
+  FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st));
+  for (int j = 0; j < m; ++j) {
+    double* set_cur = q.slots_step + (size_t)(j & 1) * q.step_len;
+    double* set_nxt = q.slots_step + (size_t)((j + 1) & 1) * q.step_len;
+    if (!plain) {
+      FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), d,
+                                 p->zeta, p->seed, set_cur, q.st));
+      FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st));
+      FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st));
+    } else {
+      double* set0 = q.slots_step;
+      double* set1 = q.slots_step + q.step_len;
+      FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), 1, 1, 0,
+                                 nullptr, q.st));
+      FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
+      FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
+      FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set1, 0, q.st));
+      FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set1, set0, q.slots_start, 1, q.R, q.st));
+      FAB_TRY(launch_plain_finish(s, j, m, q.slots_start, q.R, q.st));
+      FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(j + 1), &q.st->inv_rho, q.st));
+    }
+  }
+  SmallArgs a{};
+  a.d = d;
+  a.m = m;
+  a.nt = nt;
+  a.plain = plain ? 1 : 0;
+  a.fun = fun;
+  a.nq_main = L.nq_main;
+  a.nq_chk = L.nq_chk;
+  a.ldscr = L.ldscr;
+  a.U = q.U;
+  a.Uq = q.Ut;
+  a.R = q.R;
+  a.Tout = q.T;
+  a.Xout = q.X;
+  a.rz = q.rz;
+  a.rw = q.rw;
+  a.psi = q.psi;
+  a.scr = q.scr;
+  a.gbuf = q.gbuf;
+  a.C = q.C;
+  a.st = q.st;
+  FAB_TRY(launch_small(s, a));
+  if (with_pass) {
+    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, q.slots_norm, q.st));
+    FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep));
+  }
+  return FAB_OK;
+}
+
+static void info_init(fab_info* h, fab_status s) {
+  if (!h) return;
+  std::memset(h, 0, sizeof(*h));
+  h->status = s;
+}
+
+extern "C" {
+
+const char* fab_status_string(fab_status s) {
+  switch (s) {
+    case FAB_OK: return "ok";
+    case FAB_OK_BREAKDOWN: return "ok: breakdown (invariant subspace, exact result)";
+    case FAB_W_NOT_CONVERGED: return "warning: max_cycles reached before the tolerance";
+    case FAB_W_QUADRATURE: return "warning: main and check quadrature rules disagree";
+    case FAB_E_INVALID: return "error: invalid argument";
+    case FAB_E_UNSUPPORTED: return "error: unsupported size or option";
+    case FAB_E_HIP: return "error: HIP runtime failure";
+    case FAB_E_NONFINITE: return "error: non-finite value in the iteration";
+    case FAB_E_DIVERGED: return "error: the restart iteration diverged";
+    case FAB_E_WORKSPACE: return "error: workspace too small";
+  }
+  return "unknown status";
+}
+
+fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
+  if (!ctx) return FAB_E_INVALID;
+  *ctx = nullptr;
+  fab_ctx* c = new (std::nothrow) fab_ctx();
+  if (!c) return FAB_E_HIP;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return FAB_E_HIP;
+  }
+  c->user = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_rep, sizeof(Report), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_t, sizeof(double) * kMaxNt, hipHostMallocDefault) != hipSuccess) {
+    if (c->h_rep) (void)hipHostFree(c->h_rep);
+    if (c->work) (void)hipStreamDestroy(c->work);
+    if (c->ev) (void)hipEventDestroy(c->ev);
+    delete c;
+    return FAB_E_HIP;
+  }
+  *ctx = c;
+  return FAB_OK;
+}
+
+fab_status fab_destroy(fab_ctx* c) {
+  if (!c) return FAB_E_INVALID;
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  (void)hipStreamSynchronize(c->work);
+  (void)hipStreamDestroy(c->work);
+  (void)hipEventDestroy(c->ev);
+  (void)hipHostFree(c->h_rep);
+  (void)hipHostFree(c->h_t);
+  delete c;
+  return FAB_OK;
+}
+
+fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                          const void* vals, int32_t dtype, fab_op** op) {
+  if (!ctx || !op || n <= 0 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !rowptr || (nnz > 0 && (!colind || !vals)))
+    return FAB_E_INVALID;
+  if (dtype != FAB_F64 && dtype != FAB_F32) return FAB_E_INVALID;
+  if (n >= ((int64_t)1 << 31)) return FAB_E_UNSUPPORTED;
+  fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype};
+  if (!o) return FAB_E_HIP;
+  *op = o;
+  return FAB_OK;
+}
+
+fab_status fab_op_destroy(fab_op* op) {
+  if (!op) return FAB_E_INVALID;
+  delete op;
+  return FAB_OK;
+}
+
+fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, size_t* h_bytes) {
+  if (!A || !p || !h_bytes || nt < 1 || nt > kMaxNt || p->m < 1 || p->m > kMaxM) return FAB_E_INVALID;
+  if (p->method == FAB_SKETCHED && (p->d < 1 || p->d > kMaxD)) return FAB_E_INVALID;
+  const int fun = FAB_EXP_NEG;  // the exp layout is the larger of the two
+  Layout L = make_layout(A->n, A->dtype, p, fun, nt);
+  Layout L2 = make_layout(A->n, A->dtype, p, FAB_INVSQRT, nt);
+  *h_bytes = std::max(L.total, L2.total);
+  return FAB_OK;
+}
+
+fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, const void* b,
+                     double* x, const fab_params* p, void* work, size_t work_bytes, fab_info* h_info) {
+  info_init(h_info, FAB_E_INVALID);
+  if (!ctx || !A || !b || !x || !p || !work) return FAB_E_INVALID;
+  if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
+  fab_status ps = check_params(A, p, fun, nt);
+  if (ps != FAB_OK) {
+    info_init(h_info, ps);
+    return ps;
+  }
+  if (fun == FAB_EXP_NEG)
+    for (int i = 0; i < nt; ++i)
+      if (!std::isfinite(h_t[i]) || !(h_t[i] > 0.0)) return FAB_E_INVALID;
+  if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
+  const Layout L = make_layout(A->n, A->dtype, p, fun, nt);
+  if (work_bytes < L.total) {
+    info_init(h_info, FAB_E_WORKSPACE);
+    return FAB_E_WORKSPACE;
+  }
+  info_init(h_info, FAB_E_HIP);
+  const Ptrs q = carve(work, L, p, nt);
+  hipStream_t s = ctx->work;
+  const int n = (int)A->n;
+  // order after the caller's stream
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  // solve set-up: zero accumulators, state and x; quadrature nodes; w_1 <- b
+  FAB_TRY(launch_zero(s, (double*)((char*)work + L.slots_step), (L.T - L.slots_step) / 8));
+  FAB_TRY(launch_zero(s, x, (size_t)n * nt));
+  FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
+  for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
+  FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi));
+  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, b, q.W));
+
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.op = A;
+  key.work = work;
+  key.x = x;
+  key.n = A->n;
+  key.m = p->m;
+  key.k = p->k;
+  key.d = p->d;
+  key.zeta = p->zeta;
+  key.nt = nt;
+  key.fun = fun;
+  key.method = p->method;
+  key.nq = rule_nodes(fun, p);
+  key.dtype = A->dtype;
+  key.seed = p->seed;
+  key.tol = p->tol;
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : ctx->graphs)
+    if (g.key == key) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph;
+    FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    fab_status es = enqueue_cycle(s, A, p, fun, nt, L, q, x, ctx->h_rep, true);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (es != FAB_OK || ce != hipSuccess) return FAB_E_HIP;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return FAB_E_HIP;
+    if (ctx->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, exec});
+  }
+  fab_status status = FAB_W_NOT_CONVERGED;
+  int cycles = 0, matvecs = 0;
+  double est = 0.0, qdis = 0.0;
+  std::vector<double> hist;
+  for (int c = 0; c < p->max_cycles; ++c) {
+    FAB_TRY(hipGraphLaunch(exec, s));
+    FAB_TRY(hipStreamSynchronize(s));
+    const Report r = *ctx->h_rep;
+    cycles = c + 1;
+    matvecs += r.meff;
+    est = r.est;
+    qdis = std::max(qdis, r.qdis_rel);
+    hist.push_back(est);
+    if (r.nonfinite) {
+      status = FAB_E_NONFINITE;
+      break;
+    }
+    if (r.brk) {
+      status = FAB_OK_BREAKDOWN;
+      if (r.meff == 0 && c == 0) status = FAB_OK;  // b = 0: x = 0 exactly
+      break;
+    }
+    if (r.converged) {
+      status = FAB_OK;
+      break;
+    }
+    if (c >= 2 && est >= 1.0 && est >= 10.0 * hist[c - 2]) {
+      status = FAB_E_DIVERGED;
+      break;
+    }
+  }
+  if ((status == FAB_OK || status == FAB_OK_BREAKDOWN) && qdis > std::max(0.1 * p->tol, 1e-11))
+    status = FAB_W_QUADRATURE;
+  if (h_info) {
+    h_info->status = status;
+    h_info->cycles = cycles;
+    h_info->matvecs = matvecs;
+    h_info->est_rel_update = est;
+    h_info->quad_disagreement = qdis;
+  }
+  return status;
+}
+
+fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void* work, size_t work_bytes) {
+  (void)work;
+  (void)work_bytes;
+  if (!ctx || !A || !x || !y) return FAB_E_INVALID;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, stream_grid(A->n, 2048), (int)A->n, A->rowptr, A->colind, A->vals, x, y,
+                             1, 1, 0, nullptr, nullptr));
+  FAB_TRY(hipStreamSynchronize(s));
+  return FAB_OK;
+}
+
+fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed, int32_t dtype,
+                            const void* x, double* Sx, void* work, size_t work_bytes) {
+  if (!ctx || !x || !Sx || !work || n <= 0 || n >= ((int64_t)1 << 31) || d < 1 || d > kMaxD || zeta < 1 ||
+      zeta > 32 || zeta > d || (dtype != FAB_F64 && dtype != FAB_F32))
+    return FAB_E_INVALID;
+  if (work_bytes < (size_t)kSlots * d * 8) return FAB_E_WORKSPACE;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  double* slots = (double*)work;
+  FAB_TRY(launch_zero(s, slots, (size_t)kSlots * d));
+  FAB_TRY(launch_spmv_sketch(s, dtype, 1, stream_grid(n, 2048), (int)n, nullptr, nullptr, nullptr, x, nullptr, d,
+                             zeta, seed, slots, nullptr));
+  FAB_TRY(launch_reduce_slots(s, d, slots, Sx));
+  FAB_TRY(hipStreamSynchronize(s));
+  return FAB_OK;
+}
+
+fab_status fab_sketch_table(fab_ctx* ctx, int64_t col0, int64_t count, int32_t d, int32_t zeta, uint64_t seed,
+                            int32_t* rows, int8_t* signs) {
+  if (!ctx || !rows || !signs || col0 < 0 || count < 1 || d < 1 || d > kMaxD || zeta < 1 || zeta > 32 || zeta > d)
+    return FAB_E_INVALID;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(launch_sketch_table(s, col0, count, d, zeta, seed, rows, signs));
+  FAB_TRY(hipStreamSynchronize(s));
+  return FAB_OK;
+}
+
+fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const fab_params* p, void* W, double* U,
+                           double* R, double* T, double* X, double* h_scal, void* work, size_t work_bytes) {
+  if (!ctx || !A || !v || !p || !W || !U || !R || !T || !X || !h_scal || !work) return FAB_E_INVALID;
+  fab_status ps = check_params(A, p, FAB_EXP_NEG, 1);
+  if (ps != FAB_OK) return ps;
+  const Layout L = make_layout(A->n, A->dtype, p, FAB_EXP_NEG, 1);
+  if (work_bytes < L.total) return FAB_E_WORKSPACE;
+  const Ptrs q = carve(work, L, p, 1);
+  hipStream_t s = ctx->work;
+  const int n = (int)A->n, m = p->m;
+  const bool plain = p->method == FAB_PLAIN_RESTART;
+  const int d = plain ? 1 : p->d;
+  const size_t es = A->dtype == 0 ? 8 : 4;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(launch_zero(s, (double*)((char*)work + L.slots_step), (L.T - L.slots_step) / 8));
+  FAB_TRY(hipStreamSynchronize(s));
+  ctx->h_t[0] = 1.0;
+  FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double), hipMemcpyHostToDevice, s));
+  FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi));
+  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, q.W));
+  fab_status es2 = enqueue_cycle(s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false);
+  if (es2 != FAB_OK) return es2;
+  FAB_TRY(hipMemcpyAsync(W, q.W, (size_t)n * (m + 1) * es, hipMemcpyDeviceToDevice, s));
+  if (!plain) FAB_TRY(hipMemcpyAsync(U, q.U, (size_t)d * (m + 1) * 8, hipMemcpyDeviceToDevice, s));
+  FAB_TRY(hipMemcpyAsync(R, q.R, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToDevice, s));
+  FAB_TRY(hipMemcpyAsync(T, q.T, (size_t)(m + 1) * (m + 1) * 8, hipMemcpyDeviceToDevice, s));
+  FAB_TRY(hipMemcpyAsync(X, q.X, (size_t)m * m * 8, hipMemcpyDeviceToDevice, s));
+  State hst;
+  FAB_TRY(hipMemcpyAsync(&hst, q.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  FAB_TRY(hipStreamSynchronize(s));
+  h_scal[0] = hst.alpha;
+  h_scal[1] = hst.beta;
+  h_scal[2] = hst.h;
+  h_scal[3] = (double)hst.meff;
+  return hst.nonfinite ? FAB_E_NONFINITE : FAB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of libfab (device code for gfx950 and the host driver).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace fab {
+
+constexpr int kThreads = 256;      // threads per block of the streaming kernels
+constexpr int kSlots = 8;          // copies of each sketch accumulator (spreads FP64 atomics)
+constexpr int kMaxM = 64;          // largest cycle length
+constexpr int kMaxD = 2048;        // largest sketch dimension (LDS bins: 16 KB FP64)
+constexpr int kMaxNt = 16;         // largest number of time points per solve
+constexpr int kRuleMain = 128;     // default nodes of the main quadrature rule
+constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
+
+// ----------------------------------------------------------------------------------------------
+// Sparse-sign sketch specification (eq. sparse_sign_sketch): column j of S has zeta distinct
+// rows chosen uniformly (Floyd's sampling algorithm) and Rademacher signs, all drawn from the
+// counter-based generator Philox4x32-10 (Salmon et al., SC'11):
+//   key = (seed lo, seed hi); block b of column j = Philox(counter = (j lo, j hi, b, 0));
+//   draw l = word (l mod 4) of block (l div 4); row J = d-zeta+l candidate r = mulhi(draw, J+1),
+//   replaced by J if already taken; sign bit l of word 0 of block ceil(zeta/4) (1 = negative).
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+// Rows and signs of column `col`; only the first `zeta` (<= ZMAX) entries are meaningful.
+template <int ZMAX>
+__device__ __forceinline__ void sketch_column(uint64_t col, int d, int zeta, uint32_t k0, uint32_t k1,
+                                              int (&rows)[ZMAX], uint32_t& signbits) {
+  uint32_t words[ZMAX];
+  const uint32_t lo = (uint32_t)col, hi = (uint32_t)(col >> 32);
+#pragma unroll
+  for (int b = 0; b < (ZMAX + 3) / 4; ++b) {
+    uint32_t c0 = lo, c1 = hi, c2 = (uint32_t)b, c3 = 0u;
+    if (4 * b < zeta) philox4x32_10(c0, c1, c2, c3, k0, k1);
+    if (4 * b + 0 < ZMAX) words[4 * b + 0] = c0;
+    if (4 * b + 1 < ZMAX) words[4 * b + 1] = c1;
+    if (4 * b + 2 < ZMAX) words[4 * b + 2] = c2;
+    if (4 * b + 3 < ZMAX) words[4 * b + 3] = c3;
+  }
+  {
+    uint32_t c0 = lo, c1 = hi, c2 = (uint32_t)((zeta + 3) / 4), c3 = 0u;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    signbits = c0;
+  }
+#pragma unroll
+  for (int l = 0; l < ZMAX; ++l) {
+    if (l < zeta) {
+      const uint32_t J = (uint32_t)(d - zeta + l);
+      const int r = (int)__umulhi(words[l], J + 1u);
+      bool taken = false;
+#pragma unroll
+      for (int q = 0; q < l; ++q) taken |= (rows[q] == r);
+      rows[l] = taken ? (int)J : r;
+    } else {
+      rows[l] = 0;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Small complex arithmetic (FP64) for the quadrature solves.
+// ----------------------------------------------------------------------------------------------
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmk(double r, double i) { return cplx{r, i}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+__device__ __forceinline__ double cabs1(cplx a) { return fabs(a.re) + fabs(a.im); }
+// a / b, scaled to avoid overflow (Smith's method)
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, den = b.re + b.im * r;
+    return cplx{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  } else {
+    const double r = b.re / b.im, den = b.re * r + b.im;
+    return cplx{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Device-resident solver state (one per solve; FP64).
+// ----------------------------------------------------------------------------------------------
+struct State {
+  double alpha, inv_alpha, beta, h;
+  double upd_coef[kMaxM + 1];   // window coefficients r_ij of the current step (index i - lo)
+  double inv_rho, raw2;
+  int meff, brk, nonfinite, step_lo;
+  // per-cycle outputs read by the host
+  double ynorm2[kMaxNt], xnorm2[kMaxNt], qdis2[kMaxNt];
+  double est, qdis_rel;
+  int converged, pad0;
+};
+
+// Host-visible per-cycle report (copied to pinned memory each cycle).
+struct Report {
+  double est, qdis_rel, alpha, beta;
+  int brk, meff, nonfinite, converged;
+};
+
+// Arguments of the cycle-end kernel.
+struct SmallArgs {
+  int d, m, nt, plain, fun, nq_main, nq_chk, ldscr;
+  const double* U;
+  double* Uq;       // d x (m+1) scratch for the Householder QR
+  const double* R;  // (m+1) x m
+  double* Tout;     // (m+1) x (m+1)
+  double* Xout;     // m x m
+  const cplx* rz;
+  const cplx* rw;
+  cplx* psi;
+  cplx* scr;        // per-system scratch, element e of system s at scr[e * ldscr + s]
+  double* gbuf;     // 2 x nt x m: main and check rule results
+  double* C;        // (m+1) x (nt+1) pass coefficients
+  State* st;
+};
+
+// Workspace carving, shared by the driver and workspace_size().
+struct Layout {
+  size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
+      scratch, report, total;
+  int nsys, nq_main, nq_chk, ldscr;
+};
+
+}  // namespace fab

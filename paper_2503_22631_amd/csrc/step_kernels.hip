@@ -1,0 +1,427 @@
+// Per-step kernels of the randomized Arnoldi cycle (Algorithm 1, window-truncated) and of the
+// classical Arnoldi comparator, for gfx950.
+//
+//   k_spmv_sketch : z = A w_j (CSR, one row per lane) fused with u = S z, the sparse-sign sketch
+//                   (Algorithm 1 lines 7-8).  S is regenerated on the fly from the counter-based
+//                   spec, scattered into per-block LDS bins and added into kSlots global copies.
+//   k_orth        : one workgroup; modified Gram-Schmidt of the sketch against the last k sketched
+//                   basis vectors (lines 9-12), the Hessenberg column, rho and the breakdown test.
+//   k_update      : w_{j+1} = (z - sum_i r_ij w_i) / rho over the window (lines 12-14).
+//   k_gram / k_cgs_update / k_plain_finish : classical Gram-Schmidt applied twice (CGS2) for the
+//                   plain restarted Arnoldi comparator.
+#include "fab_internal.h"
+
+namespace fab {
+
+// Row tile of a block: blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8.
+// Each XCD gets a contiguous slab of tiles, keeping the stencil neighbours of its rows in its L2.
+struct TileWalk {
+  int per_xcd, xcd, local, nloc;
+  __device__ TileWalk(int ntiles) {
+    per_xcd = (ntiles + kXcds - 1) / kXcds;
+    xcd = blockIdx.x % kXcds;
+    local = blockIdx.x / kXcds;
+    nloc = gridDim.x / kXcds;
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; every thread gets the result.  `buf` holds >= 2 * (kThreads/64) doubles and
+// `phase` alternates between calls so one barrier per call suffices.
+__device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* b = buf + phase * (kThreads / 64);
+  if ((threadIdx.x & 63) == 0) b[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < nw; ++q) s += b[q];
+  phase ^= 1;
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// MODE 0: y = A x and sketch of y;  MODE 1: sketch of x only;  MODE 2: y = A x only.
+// The sketch accumulates in the value type in LDS (FP64 or FP32) and in FP64 in the global slots.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int MODE, int ZMAX>
+__global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
+                                                          const int* __restrict__ colind,
+                                                          const T* __restrict__ vals,
+                                                          const T* __restrict__ x, T* __restrict__ y,
+                                                          int d, int zeta, T scale, uint32_t k0,
+                                                          uint32_t k1, double* __restrict__ slots,
+                                                          const State* __restrict__ st) {
+  extern __shared__ unsigned char smem_raw[];
+  T* bins = reinterpret_cast<T*>(smem_raw);
+  if (st != nullptr && st->brk) return;
+  if (MODE != 2) {
+    for (int i = threadIdx.x; i < d; i += kThreads) bins[i] = T(0);
+    __syncthreads();
+  }
+  const int ntiles = (n + kThreads - 1) / kThreads;
+  TileWalk tw(ntiles);
+  for (int tt = tw.local; tt < tw.per_xcd; tt += tw.nloc) {
+    const int tile = tw.xcd * tw.per_xcd + tt;
+    const int row = tile * kThreads + threadIdx.x;
+    if (tile >= ntiles || row >= n) continue;
+    T z;
+    if (MODE != 1) {
+      T acc = T(0);
+      const int p0 = rowptr[row], p1 = rowptr[row + 1];
+      for (int p = p0; p < p1; ++p) acc = fma(vals[p], x[colind[p]], acc);
+      y[row] = acc;
+      z = acc;
+    } else {
+      z = x[row];
+    }
+    if (MODE != 2) {
+      int rows[ZMAX];
+      uint32_t sb;
+      sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+      const T zs = z * scale;
+#pragma unroll
+      for (int l = 0; l < ZMAX; ++l) {
+        if (l < zeta) unsafeAtomicAdd(&bins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+      }
+    }
+  }
+  if (MODE != 2) {
+    __syncthreads();
+    double* slot = slots + (size_t)(blockIdx.x % kSlots) * d;
+    for (int i = threadIdx.x; i < d; i += kThreads) {
+      const double v = (double)bins[i];
+      if (v != 0.0) unsafeAtomicAdd(slot + i, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Sketch-space modified Gram-Schmidt of step j (one workgroup).
+// slots_cur: kSlots x d partial sketches of z; slots_next: the other set, zeroed here for step j+1.
+// U: d x (m+1) sketched basis (column j+1 written); R: (m+1) x m Hessenberg (column j written).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_orth(int j, int k, int m, int d,
+                                                   const double* __restrict__ slots_cur,
+                                                   double* __restrict__ slots_next, double* __restrict__ U,
+                                                   double* __restrict__ R, State* __restrict__ st) {
+  __shared__ double red[2 * (kThreads / 64)];
+  int phase = 0;
+  if (st->brk) return;
+  constexpr int PER = kMaxD / kThreads;
+  double u[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = threadIdx.x + q * kThreads;
+    double s = 0.0;
+    if (i < d) {
+#pragma unroll
+      for (int c = 0; c < kSlots; ++c) s += slots_cur[(size_t)c * d + i];
+    }
+    u[q] = s;
+  }
+  for (int i = threadIdx.x; i < kSlots * d; i += kThreads) slots_next[i] = 0.0;
+  double loc = 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
+  const double raw2 = block_sum(loc, red, phase);
+  const int lo = max(0, j - k + 1);
+  for (int i = lo; i <= j; ++i) {
+    const double* Ui = U + (size_t)i * d;
+    loc = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < d) loc += Ui[e] * u[q];
+    }
+    const double r = block_sum(loc, red, phase);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < d) u[q] -= r * Ui[e];
+    }
+    if (threadIdx.x == 0) {
+      R[(size_t)j * (m + 1) + i] = r;
+      st->upd_coef[i - lo] = r;
+    }
+  }
+  loc = 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
+  const double rho = sqrt(block_sum(loc, red, phase));
+  const bool finite = isfinite(rho) && isfinite(raw2);
+  const bool breakdown = !(rho > 64.0 * 2.220446049250313e-16 * sqrt(raw2));
+  if (!finite || breakdown) {
+    if (threadIdx.x == 0) {
+      st->brk = 1;
+      st->meff = j + 1;
+      if (!finite) st->nonfinite = 1;
+    }
+    return;
+  }
+  const double inv = 1.0 / rho;
+  double* Un = U + (size_t)(j + 1) * d;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    if (e < d) Un[e] = u[q] * inv;
+  }
+  if (threadIdx.x == 0) {
+    R[(size_t)j * (m + 1) + j + 1] = rho;
+    st->inv_rho = inv;
+    st->step_lo = lo;
+  }
+}
+
+// w_{j+1} = (z - sum_{i=lo..j} r_i w_i) / rho, in place on column j+1 of W (n x (m+1)).
+// KMAX bounds the window so the coefficients live in registers.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict__ W,
+                                                     const State* __restrict__ st) {
+  if (st->brk) return;
+  const int lo = st->step_lo, nw = j - lo + 1;
+  const T inv = (T)st->inv_rho;
+  T coef[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? (T)st->upd_coef[q] : T(0);
+  T* out = W + (size_t)(j + 1) * n;
+  const T* base = W + (size_t)lo * n;
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
+    T v = out[i];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < nw) v -= coef[q] * base[(size_t)q * n + i];
+    out[i] = v * inv;
+  }
+}
+
+// ------------------------------------------------------------------ plain Arnoldi (CGS2) kernels
+// Partial Gram products h_i = <V_i, z>, i < j1, plus ||z||^2 in slot entry j1 when want_norm.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gram(int n, int j1, const T* __restrict__ V,
+                                                   const T* __restrict__ z, double* __restrict__ slots,
+                                                   int want_norm, const State* __restrict__ st) {
+  __shared__ double part[kThreads / 64][kMaxM + 2];
+  if (st->brk) return;
+  const int ncol = j1 + (want_norm ? 1 : 0);
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c0 = 0; c0 < ncol; c0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
+      const double zi = (double)z[i];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = c0 + q;
+        if (c < j1) acc[q] += (double)V[(size_t)c * n + i] * zi;
+        else if (c == j1 && want_norm) acc[q] += zi * zi;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double s = wave_sum(acc[q]);
+      if (lane == 0 && c0 + q < ncol) part[w][c0 + q] = s;
+    }
+  }
+  __syncthreads();
+  double* slot = slots + (size_t)(blockIdx.x % kSlots) * (kMaxM + 2);
+  for (int c = threadIdx.x; c < ncol; c += kThreads) {
+    double s = 0.0;
+    for (int q = 0; q < (kThreads / 64); ++q) s += part[q][c];
+    unsafeAtomicAdd(slot + c, s);
+  }
+}
+
+// z -= V h with h = sum of the slot copies; accumulates ||z||^2 into norm slots when want_norm.
+// Block 0 adds h into the Hessenberg column j and zeroes `slots_zero` (the other pass's set).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cgs_update(int n, int j, int m, T* __restrict__ V,
+                                                         const double* __restrict__ slots,
+                                                         double* __restrict__ slots_zero,
+                                                         double* __restrict__ norm_slots, int want_norm,
+                                                         double* __restrict__ R, State* __restrict__ st) {
+  __shared__ double h[kMaxM + 1];
+  __shared__ double red[2 * (kThreads / 64)];
+  int phase = 0;
+  if (st->brk) return;
+  const int j1 = j + 1;
+  for (int c = threadIdx.x; c < j1; c += kThreads) {
+    double s = 0.0;
+    for (int q = 0; q < kSlots; ++q) s += slots[(size_t)q * (kMaxM + 2) + c];
+    h[c] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int c = threadIdx.x; c < j1; c += kThreads) R[(size_t)j * (m + 1) + c] += h[c];
+    if (!want_norm && threadIdx.x == 0) {  // pass 1 carries ||z||^2 before orthogonalization
+      double r2 = 0.0;
+      for (int q = 0; q < kSlots; ++q) r2 += slots[(size_t)q * (kMaxM + 2) + j1];
+      st->raw2 = r2;
+    }
+    for (int c = threadIdx.x; c < kSlots * (kMaxM + 2); c += kThreads) slots_zero[c] = 0.0;
+  }
+  T* z = V + (size_t)j1 * n;
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  double nrm = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
+    double v = (double)z[i];
+    for (int c = 0; c < j1; ++c) v -= h[c] * (double)V[(size_t)c * n + i];
+    const T vt = (T)v;
+    z[i] = vt;
+    nrm += (double)vt * (double)vt;
+  }
+  if (want_norm) {
+    const double s = block_sum(nrm, red, phase);
+    if (threadIdx.x == 0) unsafeAtomicAdd(norm_slots + (blockIdx.x % kSlots), s);
+  }
+}
+
+// rho = ||z|| after CGS2; Hessenberg entry, breakdown test against the raw norm kept by pass 1.
+__global__ void k_plain_finish(int j, int m, double* __restrict__ norm_slots, double* __restrict__ R,
+                               State* __restrict__ st) {
+  if (threadIdx.x != 0 || st->brk) return;
+  double s = 0.0;
+  for (int q = 0; q < kSlots; ++q) {
+    s += norm_slots[q];
+    norm_slots[q] = 0.0;
+  }
+  const double raw = st->raw2;
+  const double rho = sqrt(s);
+  const bool finite = isfinite(rho) && isfinite(raw);
+  if (!finite || !(rho > 64.0 * 2.220446049250313e-16 * sqrt(raw))) {
+    st->brk = 1;
+    st->meff = j + 1;
+    if (!finite) st->nonfinite = 1;
+    return;
+  }
+  R[(size_t)j * (m + 1) + j + 1] = rho;
+  st->inv_rho = 1.0 / rho;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v, const double* __restrict__ s_ptr,
+                                                        const State* __restrict__ st) {
+  if (st->brk) return;
+  const T s = (T)(*s_ptr);
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) v[i] *= s;
+}
+
+// ------------------------------------------------------------------------------------ launchers
+template <typename T>
+static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
+                                       const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
+                                       double* slots, const State* st) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const T scale = (T)(1.0 / sqrt((double)zeta));
+  const size_t lds = (mode == 2) ? 0 : (size_t)d * sizeof(T);
+#define FAB_L(M, Z)                                                                                    \
+  hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), dim3(grid), dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, \
+                     zeta, scale, k0, k1, slots, st)
+#define FAB_Z(M)          \
+  if (zeta <= 1) {        \
+    FAB_L(M, 1);          \
+  } else if (zeta <= 4) { \
+    FAB_L(M, 4);          \
+  } else if (zeta <= 8) { \
+    FAB_L(M, 8);          \
+  } else if (zeta <= 16) { \
+    FAB_L(M, 16);         \
+  } else {                \
+    FAB_L(M, 32);         \
+  }
+  if (mode == 0) {
+    FAB_Z(0)
+  } else if (mode == 1) {
+    FAB_Z(1)
+  } else {
+    FAB_L(2, 1);
+  }
+#undef FAB_Z
+#undef FAB_L
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
+                              const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
+                              double* slots, const State* st) {
+  if (dtype == 0)
+    return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, (const double*)va, (const double*)x,
+                                        (double*)y, d, zeta, seed, slots, st);
+  return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, (const float*)va, (const float*)x, (float*)y, d,
+                                     zeta, seed, slots, st);
+}
+
+hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* cur, double* next, double* U,
+                       double* R, State* st) {
+  hipLaunchKernelGGL(k_orth, dim3(1), dim3(kThreads), 0, s, j, k, m, d, cur, next, U, R, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st) {
+  if (k <= 4)
+    hipLaunchKernelGGL((k_update<T, 4>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+  else if (k <= 8)
+    hipLaunchKernelGGL((k_update<T, 8>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+  else if (k <= 16)
+    hipLaunchKernelGGL((k_update<T, 16>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+  else if (k <= 32)
+    hipLaunchKernelGGL((k_update<T, 32>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+  else
+    hipLaunchKernelGGL((k_update<T, 64>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+}
+
+hipError_t launch_update(hipStream_t s, int dtype, int grid, int n, int j, int k, void* W, const State* st) {
+  if (dtype == 0)
+    launch_update_t<double>(s, grid, n, j, k, (double*)W, st);
+  else
+    launch_update_t<float>(s, grid, n, j, k, (float*)W, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(hipStream_t s, int dtype, int grid, int n, int j1, const void* V, const void* z,
+                       double* slots, int want_norm, const State* st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_gram<double>, dim3(grid), dim3(kThreads), 0, s, n, j1, (const double*)V,
+                       (const double*)z, slots, want_norm, st);
+  else
+    hipLaunchKernelGGL(k_gram<float>, dim3(grid), dim3(kThreads), 0, s, n, j1, (const float*)V,
+                       (const float*)z, slots, want_norm, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_update(hipStream_t s, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
+                             double* slots_zero, double* norm_slots, int want_norm, double* R, State* st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_cgs_update<double>, dim3(grid), dim3(kThreads), 0, s, n, j, m, (double*)V, slots,
+                       slots_zero, norm_slots, want_norm, R, st);
+  else
+    hipLaunchKernelGGL(k_cgs_update<float>, dim3(grid), dim3(kThreads), 0, s, n, j, m, (float*)V, slots,
+                       slots_zero, norm_slots, want_norm, R, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_finish(hipStream_t s, int j, int m, double* norm_slots, double* R, State* st) {
+  hipLaunchKernelGGL(k_plain_finish, dim3(1), dim3(64), 0, s, j, m, norm_slots, R, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_col(hipStream_t s, int dtype, int grid, int n, void* v, const double* s_ptr,
+                            const State* st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_scale_col<double>, dim3(grid), dim3(kThreads), 0, s, n, (double*)v, s_ptr, st);
+  else
+    hipLaunchKernelGGL(k_scale_col<float>, dim3(grid), dim3(kThreads), 0, s, n, (float*)v, s_ptr, st);
+  return hipGetLastError();
+}
+
+}  // namespace fab

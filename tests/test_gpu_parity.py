@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: bit-exact for the sketch specification (integer work); FP64 kernels within stated relative
+2-norm tolerances; whole solves within the tolerance of the workload (1e-10 for the 4096-row
+Laplacian, 1e-8 for convection-diffusion) against the closed-form f(A)b.
+"""
+import numpy as np
+import pytest
+
+pytest.importorskip("torch")
+import torch  # noqa: E402
+
+import workloads as wl  # noqa: E402
+from oracle import exact, krylov, sketch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fab():
+    import paper_2503_22631_amd as fab_mod
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return fab_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(fab):
+    return fab.Context()
+
+
+def _op(fab, ctx, A, dtype=torch.float64):
+    return fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=dtype)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+# ------------------------------------------------------------------------------ sketch spec
+@pytest.mark.parametrize("col0,count,d,zeta,seed", [
+    (0, 5000, 80, 8, 1), (123456789, 3000, 200, 8, 7), (0, 2000, 5, 5, 3), (2 ** 32 - 10, 100, 96, 32, 2 ** 40 + 5),
+    (17, 4097, 64, 1, 0), (0, 1000, 2048, 16, 99)])
+def test_sketch_table_bit_exact(fab, ctx, col0, count, d, zeta, seed):
+    rows, signs = fab.sketch_table(ctx, col0, count, d, zeta, seed)
+    r0, s0 = sketch.rows_and_signs(col0, count, d, zeta, seed)
+    assert np.array_equal(rows.cpu().numpy(), r0)
+    assert np.array_equal(signs.cpu().numpy().astype(np.float64), s0)
+
+
+@pytest.mark.parametrize("n,d,zeta,dtype", [(4096, 80, 8, torch.float64), (100003, 200, 8, torch.float64),
+                                            (777, 120, 4, torch.float32), (1, 16, 1, torch.float64)])
+def test_sketch_apply(fab, ctx, n, d, zeta, dtype):
+    x = wl.gaussian_vector(n, 5)
+    S = sketch.sketch_matrix(n, d, zeta, seed=11)
+    xt = torch.as_tensor(x, dtype=dtype, device="cuda")
+    got = fab.sketch_apply(ctx, xt, d, zeta, 11).cpu().numpy()
+    ref = S @ xt.cpu().double().numpy()
+    tol = 1e-14 if dtype == torch.float64 else 2e-6
+    assert _rel(got, ref) <= tol
+
+
+# ------------------------------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("build,dtype", [(lambda: wl.laplacian_2d(64), torch.float64),
+                                         (lambda: wl.convdiff_3d(20, 50.0), torch.float64),
+                                         (lambda: wl.anisotropic_2d(37, 0.01), torch.float32)])
+def test_spmv(fab, ctx, build, dtype):
+    A = build()
+    op = _op(fab, ctx, A, dtype)
+    x = wl.gaussian_vector(A.n, 2)
+    xt = torch.as_tensor(x, dtype=dtype, device="cuda")
+    y = fab.spmv(op, xt).cpu().double().numpy()
+    ref = A.to_scipy().astype(np.float64) @ xt.cpu().double().numpy()
+    assert _rel(y, ref) <= (1e-15 if dtype == torch.float64 else 1e-6)
+
+
+# ------------------------------------------------------------------------ one cycle (twin)
+@pytest.mark.parametrize("N,m,k,d,zeta", [(64, 20, 2, 80, 8), (30, 12, 4, 50, 4), (17, 8, 8, 40, 1)])
+def test_cycle_matches_oracle_twin(fab, ctx, N, m, k, d, zeta):
+    """W, S W, R, T, X, h, beta of one cycle equal the oracle's step-by-step twin (same S)."""
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    v = wl.gaussian_vector(A.n, 3)
+    g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=m, k=k, d=d, zeta=zeta, seed=1)
+    S = sketch.sketch_matrix(A.n, d, zeta, seed=1)
+    c = krylov.sketched_cycle(A.to_scipy(), S, v, m, k)
+    assert g["m"] == c.m == m
+    assert abs(g["alpha"] - c.alpha) <= 1e-13 * c.alpha
+    for name, gv, ov in [("W", g["W"], c.W), ("U", g["U"], c.U), ("R", g["R"], c.R), ("T", g["T"], c.T),
+                         ("X", g["X"], c.X)]:
+        e = _rel(gv.cpu().numpy(), ov)
+        assert e <= 1e-10, (name, e)
+    assert abs(g["h"] - c.h) <= 1e-10 * abs(c.h)
+    assert abs(g["beta"] - c.beta) <= 1e-13 * c.beta
+
+
+def test_plain_cycle_matches_arnoldi(fab, ctx):
+    A = wl.convdiff_3d(12, 50.0)
+    op = _op(fab, ctx, A)
+    v = wl.gaussian_vector(A.n, 4)
+    g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=16, k=16, d=17, zeta=1, method="plain")
+    c = krylov.arnoldi_cycle(A.to_scipy(), v, 16)
+    assert _rel(g["W"].cpu().numpy(), c.W) <= 1e-11
+    assert _rel(g["X"].cpu().numpy(), c.X) <= 1e-11
+    assert abs(g["h"] - c.h) <= 1e-11 * c.h
+
+
+# ------------------------------------------------------------------------------ full solves
+def test_laplacian_2d_64_closed_form(fab, ctx):
+    """The 4096-row workload: exp(-1e-3 A) b, m=20, k=2, d=80, zeta=8, tol 1e-10."""
+    A = wl.laplacian_2d(64)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 0)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=1e-3, m=20, k=2, d=80, zeta=8, seed=1,
+                        tol=1e-10)
+    ref = exact.sine_fab("exp", b, 64, [1, 1], t=1e-3)
+    assert info["status"] == "FAB_OK"
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-10
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", 1e-3, m=20, k=2, S=S, tol=1e-10)
+    assert info["cycles"] == io.cycles
+    assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-12
+
+
+@pytest.mark.parametrize("method", ["sketched", "plain"])
+def test_convdiff_vs_kronecker(fab, ctx, method):
+    N = 24
+    A = wl.convdiff_3d(N, 50.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 0)
+    t = 20.0 / (12 * (N + 1) ** 2)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, m=50, k=4, d=200, zeta=8, seed=1,
+                        tol=1e-8, method=method)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=50.0)
+    ref = exact.kron_exp_fab(b, factors, t)
+    assert info["status"] == "FAB_OK", info
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
+
+
+def test_multiple_time_points(fab, ctx):
+    N = 40
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 1)
+    ts = [1e-5, 1e-4, 1e-3]
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=ts, m=20, k=2, d=80, zeta=8, seed=1,
+                        tol=1e-10, max_cycles=200)
+    assert info["status"] == "FAB_OK", info
+    for i, t in enumerate(ts):
+        ref = exact.sine_fab("exp", b, N, [1, 0.01], t=t)
+        assert _rel(x[:, i].cpu().numpy(), ref) <= 1e-9, t
+
+
+def test_invsqrt_shifted_laplacian(fab, ctx):
+    N = 16
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 0)
+    lo = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2 + 1
+    hi = 12 * (N + 1) ** 2 + 1
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "invsqrt", m=30, k=2, d=120, zeta=8, seed=1,
+                        tol=1e-10, spec=(lo, hi), max_cycles=200)
+    ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], 1.0)
+    assert info["status"] == "FAB_OK", info
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-9
+
+
+# ------------------------------------------------------------------------------- edge cases
+def test_ragged_sizes_and_tiny_n(fab, ctx):
+    for N in (3, 7, 31):                        # n = 9, 49, 961: partial tiles, m >= dim K for n = 9
+        A = wl.laplacian_2d(N)
+        op = _op(fab, ctx, A)
+        b = wl.gaussian_vector(A.n, N)
+        m = min(20, A.n)
+        x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=1e-2, m=m, k=2, d=max(2 * m, 16),
+                            zeta=4, seed=2, tol=1e-12)
+        ref = exact.sine_fab("exp", b, N, [1, 1], t=1e-2)
+        assert info["code"] >= 0
+        assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-10, (N, info)
+
+
+def test_breakdown_on_eigenvector(fab, ctx):
+    N = 16
+    Phi, lam = exact.sine_basis(N)
+    v = np.kron(Phi[:, 2], Phi[:, 4])
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    x, info = fab.solve(op, torch.as_tensor(v, device="cuda"), "exp", t=1e-3, m=10, k=2, d=40, zeta=8, seed=1,
+                        tol=1e-12)
+    assert info["status"] == "FAB_OK_BREAKDOWN" and info["cycles"] == 1
+    ref = np.exp(-1e-3 * (lam[2] + lam[4])) * v
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-12
+
+
+def test_zero_rhs_gives_zero(fab, ctx):
+    A = wl.laplacian_2d(20)
+    op = _op(fab, ctx, A)
+    x, info = fab.solve(op, torch.zeros(A.n, dtype=torch.float64, device="cuda"), "exp", t=1e-3)
+    assert info["status"] == "FAB_OK"
+    assert float(x.abs().max()) == 0.0
+
+
+def test_error_statuses(fab, ctx):
+    A = wl.laplacian_2d(20)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 0), device="cuda")
+    with pytest.raises(fab.FabError) as e:
+        fab.solve(op, b, "exp", t=1e-3, m=20, d=20)           # d < m + 1
+    assert e.value.status == -1
+    with pytest.raises(fab.FabError):
+        fab.solve(op, b, "exp", t=1e-3, m=20, k=21)           # k > m
+    with pytest.raises(fab.FabError):
+        fab.solve(op, b, "exp", t=-1.0)                       # t <= 0
+    bad = b.clone()
+    bad[7] = float("nan")
+    with pytest.raises(fab.FabError) as e:
+        fab.solve(op, bad, "exp", t=1e-3)
+    assert e.value.status == -4
+    x, info = fab.solve(op, b, "exp", t=1e-3, m=4, k=2, d=16, max_cycles=1, tol=1e-14)
+    assert info["status"] == "FAB_W_NOT_CONVERGED" and info["cycles"] == 1
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fab.FabError) as e:
+        fab.solve(op, b, "exp", t=1e-3, work=small)
+    assert e.value.status == -6
+
+
+def test_repeated_solves_are_consistent(fab, ctx):
+    """Graph replays with the same buffers give the same answer as the first call."""
+    A = wl.laplacian_2d(48)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 9), device="cuda")
+    x1, _ = fab.solve(op, b, "exp", t=1e-3)
+    x1 = x1.clone()
+    for _ in range(3):
+        x2, info = fab.solve(op, b, "exp", t=1e-3)
+        assert _rel(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-13
+
+
+# --------------------------------------------------------------- full-size workload (bench shape)
+def test_convdiff_128_full_size(fab, ctx):
+    """3-D convection-diffusion, 128^3 (n = 2.1M), Pe 50, exp(-1e-4 A) b, m=50, k=4, d=200, zeta=8:
+    the whole vector against the Kronecker-product oracle at 1e-8, in the launch configuration of
+    the benchmark."""
+    N = 128
+    A = wl.convdiff_3d(N, 50.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 0)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=1e-4, m=50, k=4, d=200, zeta=8, seed=1,
+                        tol=1e-8)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=50.0)
+    ref = exact.kron_exp_fab(b, factors, 1e-4)
+    assert info["status"] == "FAB_OK", info
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
