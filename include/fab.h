@@ -127,13 +127,30 @@ fab_status fab_sketch_table(fab_ctx* ctx, int64_t col0, int64_t count, int32_t d
                             uint64_t seed, int32_t* rows, int8_t* signs);
 
 /* One cycle from start vector v (A's dtype), exposing its intermediates:
- * W n x (m+1) (A's dtype, column-major), U d x (m+1), R (m+1) x m,
- * T (m+1) x (m+1), X m x m (all FP64 column-major), h_scal[4] = {alpha, beta, h, m_eff}. */
+ * W n x (m+1) (A's dtype, column-major), U = S W d x (m+1), R (m+1) x m, T (m+1) x (m+1)
+ * (all FP64 column-major), Rt m x m = R_m + r_{m+1,m} (T_m^{-1} t) e_m^T, the projected matrix
+ * in the basis W (the whitened X of the appendix's eq. A.1 is T_m Rt T_m^{-1}), and
+ * h_scal[4] = {alpha, beta, h, m_eff}. */
 fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const fab_params* p,
-                           void* W, double* U, double* R, double* T, double* X, double* h_scal,
+                           void* W, double* U, double* R, double* T, double* Rt, double* h_scal,
                            void* work, size_t work_bytes);
 
+/* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on
+ * the context's stream (instead of replaying the cycle graph: the same kernels with the same
+ * launch configuration) and records HIP events around each launch of the fused SpMV + sketch
+ * kernel (the product and sketch of Algorithm 1) and around each cycle's m-step loop,
+ * accumulating their durations.
+ * fab_timing_read returns the totals since the last read and clears them.  Counts only steps
+ * that ran (steps after a breakdown are excluded).  Errors: FAB_E_INVALID, FAB_E_HIP. */
+fab_status fab_timing_enable(fab_ctx* ctx, int32_t on);
+fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
+                           int64_t* h_loop_steps);
+
 const char* fab_status_string(fab_status s);
+
+/* After FAB_E_HIP: the failing HIP call and its error name, for this host thread ("" if none).
+ * The string is owned by the library and valid until the next failing call on the thread. */
+const char* fab_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -78,7 +78,7 @@ class Cycle:
 def randomized_arnoldi_window(A, S, v, m: int, k: int, orth: str = "sketch"):
     """Alg. 1 with the Gram-Schmidt loop limited to the last k vectors.
 
-    orth="sketch": sketched inner products (randomized Gram-Schmidt, lines 8-11);
+    orth="sketch": sketched inner products (randomized Gram-Schmidt of Algorithm 1);
     orth="full":   full-space inner products and 2-norm normalisation (the
                    incomplete orthogonalization of the comparison methods), with
                    U = S W formed afterwards for whitening.

@@ -23,7 +23,7 @@ METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
 __all__ = ["Context", "CSROperator", "Params", "solve", "workspace_size", "spmv", "sketch_apply",
-           "sketch_table", "cycle_debug", "FabError", "lib_path"]
+           "sketch_table", "cycle_debug", "timing_enable", "timing_read", "FabError", "lib_path"]
 
 
 def lib_path() -> str:
@@ -153,6 +153,18 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
     return x.view(nt, op.n).t(), out
 
 
+def timing_enable(ctx: Context, on: bool = True):
+    _lib.check(ctx.lib.fab_timing_enable(ctx.handle, 1 if on else 0), "fab_timing_enable", ok=(0,))
+
+
+def timing_read(ctx: Context) -> dict:
+    """Accumulated HIP-event durations of the SpMV+sketch kernel and of the step loops (ms)."""
+    a, b_, c, d = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    _lib.check(ctx.lib.fab_timing_read(ctx.handle, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c),
+                                       ctypes.byref(d)), "fab_timing_read", ok=(0,))
+    return {"spmv_ms": a.value, "spmv_launches": b_.value, "loop_ms": c.value, "loop_steps": d.value}
+
+
 def spmv(op: CSROperator, xv: torch.Tensor) -> torch.Tensor:
     y = torch.empty_like(xv)
     _lib.check(op.ctx.lib.fab_spmv(op.ctx.handle, op.handle, _ptr(xv.contiguous()), _ptr(y), None, 0),
@@ -178,7 +190,8 @@ def sketch_table(ctx: Context, col0: int, count: int, d: int, zeta: int, seed: i
 
 
 def cycle_debug(op: CSROperator, v: torch.Tensor, **kw):
-    """One cycle from v; returns the basis and small matrices of the whitened decomposition."""
+    """One cycle from v; returns the basis W, its sketch U, R, the whitening factor T, the projected
+    matrix Rt = R_m + r T_m^{-1} t e_m^T in the basis W, and the scalars alpha, beta, h."""
     ctx = op.ctx
     p = Params(**kw)
     m, d = p.m, p.d
@@ -194,5 +207,5 @@ def cycle_debug(op: CSROperator, v: torch.Tensor, **kw):
                                  _ptr(R), _ptr(T), _ptr(X), scal, _ptr(work), work.numel())
     _lib.check(st, "fab_cycle_debug", ok=(0,))
     meff = int(scal[3])
-    return {"W": W.t(), "U": U.t(), "R": R.t(), "T": T.t(), "X": X.t(), "alpha": scal[0], "beta": scal[1],
+    return {"W": W.t(), "U": U.t(), "R": R.t(), "T": T.t(), "Rt": X.t(), "alpha": scal[0], "beta": scal[1],
             "h": scal[2], "m": meff}

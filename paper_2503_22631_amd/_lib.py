@@ -16,7 +16,7 @@ STATUS = {
 }
 EXPORTS = ["fab_create", "fab_destroy", "fab_csr_create", "fab_op_destroy", "fab_workspace_size",
            "fab_solve", "fab_spmv", "fab_sketch_apply", "fab_sketch_table", "fab_cycle_debug",
-           "fab_status_string"]
+           "fab_timing_enable", "fab_timing_read", "fab_status_string", "fab_last_error"]
 
 
 class fab_params(ctypes.Structure):
@@ -33,7 +33,13 @@ class fab_info(ctypes.Structure):
 class FabError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {STATUS.get(status, status)} ({status_string(status)})")
+        detail = ""
+        if status == -3:
+            try:
+                detail = " [" + load().fab_last_error().decode() + "]"
+            except Exception:
+                pass
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status_string(status)}){detail}")
 
 
 _lib = None
@@ -62,7 +68,10 @@ def load():
         "fab_sketch_table": ([c_void_p, c_int64, c_int64, c_int32, c_int32, c_uint64, c_void_p, c_void_p], c_int32),
         "fab_cycle_debug": ([c_void_p, c_void_p, c_void_p, P(fab_params), c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p, P(c_double), c_void_p, c_size_t], c_int32),
+        "fab_timing_enable": ([c_void_p, c_int32], c_int32),
+        "fab_timing_read": ([c_void_p, P(c_double), P(c_int64), P(c_double), P(c_int64)], c_int32),
         "fab_status_string": ([c_int32], ctypes.c_char_p),
+        "fab_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

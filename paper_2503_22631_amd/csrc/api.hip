@@ -20,6 +20,8 @@ namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st);
+size_t spmv_sketch_lds(int dtype, int mode, int d);
+hipError_t configure_cycle_kernels();
 hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
                        double* R, State* st);
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st);
@@ -57,6 +59,7 @@ struct GraphKey {
   int m, k, d, zeta, nt, fun, method, nq, dtype;
   uint64_t seed;
   double tol;
+  int timing, pad;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -68,6 +71,12 @@ struct fab_ctx {
   Report* h_rep = nullptr;
   double* h_t = nullptr;  // pinned staging for the time points
   int num_cu = 256;
+  size_t lds_per_cu = 160 * 1024;
+  // benchmark timing: events around each SpMV+sketch launch (2 per step) and the loop end
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  double t_spmv_ms = 0.0, t_loop_ms = 0.0;
+  int64_t t_spmv_n = 0, t_loop_n = 0;
   struct Cached {
     GraphKey key;
     hipGraphExec_t exec;
@@ -97,7 +106,6 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.nq_main = (fun == FAB_EXP_NEG) ? N / 2 : N;
   L.nq_chk = (fun == FAB_EXP_NEG) ? ((3 * N) / 4) / 2 : (3 * N) / 4;
   L.nsys = nt * (L.nq_main + L.nq_chk);
-  L.ldscr = L.nsys;
   const size_t step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -120,8 +128,8 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.rule_w = take((size_t)L.nsys * sizeof(cplx));
   L.psi = take((size_t)L.nsys * sizeof(cplx));
   L.gbuf = take((size_t)2 * nt * m * 8 + (size_t)nt * 8 /* t values */);
-  const size_t per_sys = (size_t)3 * m + (size_t)m * (m + 1) / 2;
-  L.scratch = take(per_sys * L.nsys * sizeof(cplx));
+  L.scratch = take(0);
+  L.ldscr = m;
   L.report = 0;
   L.total = off;
   return L;
@@ -191,24 +199,47 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   return q;
 }
 
-#define FAB_TRY(expr)                         \
-  do {                                        \
-    hipError_t e_ = (expr);                   \
-    if (e_ != hipSuccess) return FAB_E_HIP;   \
+// Text of the last failing HIP call on this host thread (fab_last_error).
+static thread_local char g_last_error[256] = "";
+
+static fab_status hip_fail(hipError_t e, const char* expr, int line) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (%d) at api.hip:%d: %s", hipGetErrorName(e), (int)e, line,
+                expr);
+  return FAB_E_HIP;
+}
+
+#define FAB_TRY(expr)                                              \
+  do {                                                             \
+    hipError_t e_ = (expr);                                        \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);    \
   } while (0)
 
+// Timing events are recorded only on cycles enqueued directly on the stream (timing mode does
+// not capture a graph: an event recorded during capture becomes a graph dependency and never
+// receives a timestamp, and external event-record nodes are not accepted by this runtime).
+static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s); }
+
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
-static fab_status enqueue_cycle(hipStream_t s, const fab_op* A, const fab_params* p, int fun, int nt,
-                                const Layout& L, const Ptrs& q, double* x, Report* rep, bool with_pass) {
+// Blocks of the fused SpMV + sketch kernel: as many as fit on the device at once (LDS-limited).
+static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d) {
+  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d), 1);
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, ctx->lds_per_cu / lds));
+  return stream_grid(n, per_cu * ctx->num_cu);
+}
+
+static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op* A, const fab_params* p, int fun,
+                                int nt, const Layout& L, const Ptrs& q, double* x, Report* rep, bool with_pass,
+                                const std::vector<hipEvent_t>* tev) {
   const int n = (int)A->n, m = p->m, dt = A->dtype;
   const size_t es = dt == 0 ? 8 : 4;
   const bool plain = p->method == FAB_PLAIN_RESTART;
   const int d = plain ? 1 : p->d;
-  const int g_spmv = stream_grid(n, 2048);
+  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d);
+  const int g_sk = spmv_grid(ctx, n, dt, 1, d);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * n * es; };
   if (!plain) {
-    FAB_TRY(launch_spmv_sketch(s, dt, 1, g_spmv, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
+    FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
                                p->seed, q.slots_start, nullptr));
   } else {
     FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
@@ -219,15 +250,19 @@ static fab_status enqueue_cycle(hipStream_t s, const fab_op* A, const fab_params
     double* set_cur = q.slots_step + (size_t)(j & 1) * q.step_len;
     double* set_nxt = q.slots_step + (size_t)((j + 1) & 1) * q.step_len;
     if (!plain) {
+      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), d,
                                  p->zeta, p->seed, set_cur, q.st));
+      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st));
       FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st));
     } else {
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
+      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), 1, 1, 0,
                                  nullptr, q.st));
+      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set1, 0, q.st));
@@ -236,6 +271,7 @@ static fab_status enqueue_cycle(hipStream_t s, const fab_op* A, const fab_params
       FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(j + 1), &q.st->inv_rho, q.st));
     }
   }
+  if (tev) FAB_TRY(record_timing_event((*tev)[2 * kMaxM], s));
   SmallArgs a{};
   a.d = d;
   a.m = m;
@@ -273,6 +309,8 @@ static void info_init(fab_info* h, fab_status s) {
 
 extern "C" {
 
+const char* fab_last_error(void) { return g_last_error; }
+
 const char* fab_status_string(fab_status s) {
   switch (s) {
     case FAB_OK: return "ok";
@@ -300,7 +338,14 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
   }
   c->user = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    c->num_cu = prop.multiProcessorCount;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+  }
+  if (configure_cycle_kernels() != hipSuccess) {
+    delete c;
+    return FAB_E_HIP;
+  }
   if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&c->h_rep, sizeof(Report), hipHostMallocDefault) != hipSuccess ||
@@ -318,6 +363,7 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
 fab_status fab_destroy(fab_ctx* c) {
   if (!c) return FAB_E_INVALID;
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& e : c->tev) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(c->work);
   (void)hipStreamDestroy(c->work);
   (void)hipEventDestroy(c->ev);
@@ -410,15 +456,16 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   hipGraphExec_t exec = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) exec = g.exec;
-  if (!exec) {
+  if (!exec && !ctx->timing) {
     hipGraph_t graph;
     FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    fab_status es = enqueue_cycle(s, A, p, fun, nt, L, q, x, ctx->h_rep, true);
+    fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, nullptr);
     hipError_t ce = hipStreamEndCapture(s, &graph);
-    if (es != FAB_OK || ce != hipSuccess) return FAB_E_HIP;
+    if (es != FAB_OK) return es;
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture", __LINE__);
     hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) return FAB_E_HIP;
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate", __LINE__);
     if (ctx->graphs.size() >= 8) {
       (void)hipGraphExecDestroy(ctx->graphs.front().exec);
       ctx->graphs.erase(ctx->graphs.begin());
@@ -430,9 +477,29 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   double est = 0.0, qdis = 0.0;
   std::vector<double> hist;
   for (int c = 0; c < p->max_cycles; ++c) {
-    FAB_TRY(hipGraphLaunch(exec, s));
+    if (ctx->timing) {
+      const fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, &ctx->tev);
+      if (es != FAB_OK) return es;
+    } else {
+      FAB_TRY(hipGraphLaunch(exec, s));
+    }
     FAB_TRY(hipStreamSynchronize(s));
     const Report r = *ctx->h_rep;
+    if (ctx->timing) {
+      const int steps = r.nonfinite ? 0 : r.meff;
+      for (int j = 0; j < steps; ++j) {
+        float ms = 0.f;
+        FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[2 * j], ctx->tev[2 * j + 1]));
+        ctx->t_spmv_ms += ms;
+      }
+      ctx->t_spmv_n += steps;
+      if (steps == p->m) {
+        float ms = 0.f;
+        FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[2 * kMaxM]));
+        ctx->t_loop_ms += ms;
+        ctx->t_loop_n += steps;
+      }
+    }
     cycles = c + 1;
     matvecs += r.meff;
     est = r.est;
@@ -468,6 +535,31 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   return status;
 }
 
+fab_status fab_timing_enable(fab_ctx* ctx, int32_t on) {
+  if (!ctx) return FAB_E_INVALID;
+  if (on && ctx->tev.empty()) {
+    ctx->tev.resize(2 * kMaxM + 1, nullptr);
+    for (auto& e : ctx->tev)
+      if (hipEventCreate(&e) != hipSuccess) return FAB_E_HIP;
+  }
+  ctx->timing = on != 0;
+  ctx->t_spmv_ms = ctx->t_loop_ms = 0.0;
+  ctx->t_spmv_n = ctx->t_loop_n = 0;
+  return FAB_OK;
+}
+
+fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
+                           int64_t* h_loop_steps) {
+  if (!ctx || !h_spmv_ms || !h_spmv_launches || !h_loop_ms || !h_loop_steps) return FAB_E_INVALID;
+  *h_spmv_ms = ctx->t_spmv_ms;
+  *h_spmv_launches = ctx->t_spmv_n;
+  *h_loop_ms = ctx->t_loop_ms;
+  *h_loop_steps = ctx->t_loop_n;
+  ctx->t_spmv_ms = ctx->t_loop_ms = 0.0;
+  ctx->t_spmv_n = ctx->t_loop_n = 0;
+  return FAB_OK;
+}
+
 fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void* work, size_t work_bytes) {
   (void)work;
   (void)work_bytes;
@@ -475,8 +567,8 @@ fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void*
   hipStream_t s = ctx->work;
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
-  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, stream_grid(A->n, 2048), (int)A->n, A->rowptr, A->colind, A->vals, x, y,
-                             1, 1, 0, nullptr, nullptr));
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1), (int)A->n, A->rowptr, A->colind,
+                             A->vals, x, y, 1, 1, 0, nullptr, nullptr));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }
@@ -492,8 +584,8 @@ fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, ui
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
   double* slots = (double*)work;
   FAB_TRY(launch_zero(s, slots, (size_t)kSlots * d));
-  FAB_TRY(launch_spmv_sketch(s, dtype, 1, stream_grid(n, 2048), (int)n, nullptr, nullptr, nullptr, x, nullptr, d,
-                             zeta, seed, slots, nullptr));
+  FAB_TRY(launch_spmv_sketch(s, dtype, 1, spmv_grid(ctx, n, dtype, 1, d), (int)n, nullptr, nullptr, nullptr, x,
+                             nullptr, d, zeta, seed, slots, nullptr));
   FAB_TRY(launch_reduce_slots(s, d, slots, Sx));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
@@ -532,7 +624,7 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double), hipMemcpyHostToDevice, s));
   FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi));
   FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, q.W));
-  fab_status es2 = enqueue_cycle(s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false);
+  fab_status es2 = enqueue_cycle(ctx, s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false, nullptr);
   if (es2 != FAB_OK) return es2;
   FAB_TRY(hipMemcpyAsync(W, q.W, (size_t)n * (m + 1) * es, hipMemcpyDeviceToDevice, s));
   if (!plain) FAB_TRY(hipMemcpyAsync(U, q.U, (size_t)d * (m + 1) * 8, hipMemcpyDeviceToDevice, s));

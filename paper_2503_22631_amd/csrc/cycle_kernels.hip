@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_sqnorm(int n, const T* __restrict_
   }
 }
 
-// Cycle start (Algorithm 1, lines 1-3): alpha = ||S v|| and u_1 = S v / alpha (sketched), or
+// Cycle start (the normalisation that opens Algorithm 1): alpha = ||S v|| and u_1 = S v / alpha (sketched), or
 // alpha = ||v|| (plain).  Resets the per-cycle flags and zeroes all sketch accumulators.
 __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, double* __restrict__ slots_start,
                                                     double* __restrict__ slots_step, size_t step_len,
@@ -152,231 +152,379 @@ __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, dou
 // ------------------------------------------------------------------------- cycle-end small FP64
 
 
-// Solve (zeta I - X) y = e_1 for upper Hessenberg X (row-major in LDS, leading dimension ldx) by
-// Gaussian elimination with partial pivoting between neighbouring rows; the eliminated rows are
-// kept in the system's scratch column.  Writes y (length mm) at scr[0 .. mm).
-__device__ void hess_solve(int mm, const double* __restrict__ Xs, int ldx, cplx zeta, cplx* __restrict__ scr,
-                           int ld) {
-  // scratch regions (in elements): y [0, mm), carry [mm, 2mm), rhs [2mm, 3mm), U rows from 3mm
-  auto Y = [&](int e) -> cplx& { return scr[(size_t)e * ld]; };
-  auto CA = [&](int e) -> cplx& { return scr[(size_t)(mm + e) * ld]; };
-  auto RH = [&](int e) -> cplx& { return scr[(size_t)(2 * mm + e) * ld]; };
-  auto UR = [&](int i, int l) -> cplx& {  // row i stores columns i..mm-1
-    const int off = 3 * mm + i * mm - (i * (i - 1)) / 2 + (l - i);
-    return scr[(size_t)off * ld];
-  };
-  auto H = [&](int i, int l) -> cplx {  // (zeta I - X)[i][l]
-    const double x = Xs[i * ldx + l];
-    return (i == l) ? cmk(zeta.re - x, zeta.im) : cmk(-x, 0.0);
-  };
-  for (int l = 0; l < mm; ++l) CA(l) = H(0, l);
-  cplx rc = cmk(1.0, 0.0);
-  for (int i = 0; i < mm - 1; ++i) {
-    const cplx a = CA(i);
-    const cplx bsub = H(i + 1, i);
-    if (cabs1(bsub) > cabs1(a)) {  // pivot on row i+1
-      const cplx mult = cdiv(a, bsub);
-      for (int l = i; l < mm; ++l) {
-        const cplx hb = H(i + 1, l);
-        const cplx ca = CA(l);
-        UR(i, l) = hb;
-        if (l > i) CA(l) = csub(ca, cmul(mult, hb));
-      }
-      RH(i) = cmk(0.0, 0.0);  // row i+1 has zero right-hand side; the carried rhs stays
-    } else {
-      const cplx mult = (a.re == 0.0 && a.im == 0.0) ? cmk(0.0, 0.0) : cdiv(bsub, a);
-      for (int l = i; l < mm; ++l) {
-        const cplx ca = CA(l);
-        UR(i, l) = ca;
-        if (l > i) CA(l) = csub(H(i + 1, l), cmul(mult, ca));
-      }
-      RH(i) = rc;
-      rc = csub(cmk(0.0, 0.0), cmul(mult, rc));
-    }
+// ---------------------------------------------------------------------------------------------
+// Cycle-end small FP64 work.
+//
+// With U_{m+1} = Q T_{m+1}, the whitened projected matrix X = T_m R_m T_m^{-1} + (r/T_mm) t e_m^T
+// is similar to Rt = T_m^{-1} X T_m = R_m + r s e_m^T, s = T_m^{-1} t (r = r_{m+1,m}; the last row
+// of T_m is T_mm e_m^T).  Rt is still upper Hessenberg, so the restart works on Rt and X is never
+// formed: (zeta - X)^{-1} e_1 = T_m (zeta - Rt)^{-1} e_1 / T_11, and with beta = alpha T_11
+//   c_t = T_m^{-1} g_t = alpha sum_l w_l psi_l (zeta_l - Rt)^{-1} e_1   (pass coefficients on W_m)
+//   psi_l <- psi_l beta h [(zeta_l - X)^{-1} e_1]_m = psi_l alpha r tau [(zeta_l - Rt)^{-1} e_1]_m
+//   v_hat = (w_{m+1} - W_m s) / tau.
+// ---------------------------------------------------------------------------------------------
+constexpr int kWhitenThreads = 576;  // 9 waves x 8 columns x 8 lanes: up to kMaxM + 1 columns
+
+__device__ __forceinline__ double sum8(double v) {  // over the 8 lanes of a column group
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+
+// Common tail of the whitening kernels (T in LDS, row-major, positive diagonal; all threads arrive
+// after a barrier): T to global, s = T_m^{-1} t, Rt, the restart column of the pass coefficients,
+// and the scalars of the restart recursion.
+__device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int mm, int brk, double* s_lds) {
+  State* st = a.st;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = a.m, nt = a.nt, nthr = blockDim.x;
+  const int cols = brk ? mm : mm + 1;
+  for (int e = tid; e < (m + 1) * (m + 1); e += nthr) {
+    const int i = e % (m + 1), l = e / (m + 1);  // column-major output
+    a.Tout[e] = (i < cols && l < cols && l >= i) ? Ts[i * ldT + l] : 0.0;
   }
-  UR(mm - 1, mm - 1) = CA(mm - 1);
-  RH(mm - 1) = rc;
-  for (int i = mm - 1; i >= 0; --i) {
-    cplx s = RH(i);
-    for (int l = i + 1; l < mm; ++l) s = csub(s, cmul(UR(i, l), Y(l)));
-    Y(i) = cdiv(s, UR(i, i));
+  for (int e = tid; e < 2 * nt * m; e += nthr) a.gbuf[e] = 0.0;  // restart sums of k_quad
+  if (wv == 0) {  // s = T_m^{-1} t, column-oriented back substitution; lane i holds s_i
+    double rhs = (!brk && lane < mm) ? Ts[lane * ldT + mm] : 0.0;
+    double sl = 0.0;
+    for (int i = mm - 1; i >= 0; --i) {
+      const double si = __shfl(rhs, i, 64) / Ts[i * ldT + i];
+      if (lane == i) sl = si;
+      if (lane < i) rhs -= Ts[lane * ldT + i] * si;
+    }
+    if (lane < mm) s_lds[lane] = sl;
+  }
+  __syncthreads();
+  const double r = brk ? 0.0 : a.R[(size_t)(mm - 1) * (m + 1) + mm];
+  const double tau = brk ? 1.0 : Ts[mm * ldT + mm];
+  for (int e = tid; e < m * m; e += nthr) {  // Rt, column-major with leading dimension m
+    const int i = e % m, c = e / m;
+    double v = 0.0;
+    if (i < mm && c < mm) {
+      v = a.R[(size_t)c * (m + 1) + i];
+      if (c == mm - 1) v += r * s_lds[i];
+    }
+    a.Xout[e] = v;
+  }
+  double* rcol = a.C + (size_t)nt * (m + 1);
+  for (int e = tid; e <= m; e += nthr)
+    rcol[e] = brk ? 0.0 : (e < mm ? -s_lds[e] / tau : (e == mm ? 1.0 / tau : 0.0));
+  if (tid == 0) {
+    const double alpha = st->alpha;
+    st->beta = alpha * Ts[0];
+    st->h = brk ? 0.0 : r * tau / Ts[(mm - 1) * ldT + (mm - 1)];
+    st->cpl = brk ? 0.0 : alpha * r * tau;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_small(SmallArgs a) {
-  __shared__ double Xs[kMaxM * kMaxM];          // X row-major (also P = T R during formation)
-  __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];  // T row-major
-  __shared__ double red[kThreads / 64][2];
-  __shared__ double sh_scal[4];
+// Whitening QR with the sketched basis in registers (d <= 8 KR).  Column q of U is owned by the
+// eight lanes 8*(q%8) .. 8*(q%8)+7 of wave q/8; lane `part` keeps rows i = part + 8k.  The
+// reflector of column c is formed from the tail norm its owners accumulated in the previous step,
+// the column is published in LDS (double-buffered), and every owner updates its own column in
+// registers: one barrier per column.
+template <int KR>
+__global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a) {
+  __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
+  __shared__ double vcol[2][8 * KR];
+  __shared__ double rfs[2][2];
+  __shared__ double diagR[kMaxM + 1];
+  __shared__ double tail2[kMaxM + 2];
+  __shared__ double s_lds[kMaxM];
   State* st = a.st;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = kThreads / 64;
-  const int m = a.m, d = a.d, nt = a.nt;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int d = a.d;
   const int mm = st->meff;
   const int brk = st->brk;
-  const int C_ld = m + 1;
-  // C = 0 by default (nothing added, no restart vector)
-  for (int i = tid; i < (m + 1) * (nt + 1); i += kThreads) a.C[i] = 0.0;
   if (st->nonfinite || mm == 0) return;
   const int cols = brk ? mm : mm + 1;
   const int ldT = kMaxM + 1;
-
-  // ---- 1. T from the thin QR of U[:, :cols] (sketched) or T = I (plain Arnoldi, orthonormal basis)
+  for (int e = tid; e < cols * cols; e += kWhitenThreads) Ts[(e / cols) * ldT + (e % cols)] = 0.0;
+  __syncthreads();  // the zeros land before any entry of T is written below
   if (!a.plain) {
-    for (int i = tid; i < d * cols; i += kThreads) a.Uq[i] = a.U[i];
-    __syncthreads();
+    const int q = wv * 8 + (lane >> 3), part = lane & 7;
+    double col[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = part + 8 * k;
+      col[k] = (q < cols && i < d) ? a.U[(size_t)q * d + i] : 0.0;
+    }
+    if (q == 0) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        vcol[0][part + 8 * k] = col[k];
+        s2 += (part + 8 * k >= 1) ? col[k] * col[k] : 0.0;
+      }
+      s2 = sum8(s2);
+      if (part == 0) tail2[0] = s2;
+    }
     for (int c = 0; c < cols; ++c) {
-      double* uc = a.Uq + (size_t)c * d;
-      // norm of uc[c:d] (block reduction)
-      double s = 0.0;
-      for (int i = c + 1 + tid; i < d; i += kThreads) s += uc[i] * uc[i];
-      s = wave_sum_c(s);
-      if (lane == 0) red[wv][0] = s;
-      __syncthreads();
-      if (tid == 0) {
-        double tail = 0.0;
-        for (int q = 0; q < nwv; ++q) tail += red[q][0];
-        const double alp = uc[c];
-        const double nrm = sqrt(alp * alp + tail);
+      const int b = c & 1;
+      if (q == c && part == 0) {  // reflector of column c
+        const double s2 = tail2[c];
+        const double alp = vcol[b][c];
+        const double nrm = sqrt(alp * alp + s2);
         double tau = 0.0, beta_h = alp, scal = 0.0;
-        if (tail > 0.0 || alp < 0.0) {  // reflect unless already e_c with a nonnegative entry
+        if (s2 > 0.0 || alp < 0.0) {  // reflect unless already a nonnegative multiple of e_c
           beta_h = (alp >= 0.0) ? -nrm : nrm;
           tau = (beta_h - alp) / beta_h;
           scal = 1.0 / (alp - beta_h);
         }
-        sh_scal[0] = tau;
-        sh_scal[1] = beta_h;
-        sh_scal[2] = scal;
+        rfs[b][0] = tau;
+        rfs[b][1] = scal;
+        diagR[c] = beta_h;
       }
       __syncthreads();
-      const double tau = sh_scal[0], beta_h = sh_scal[1], scal = sh_scal[2];
-      for (int i = c + 1 + tid; i < d; i += kThreads) uc[i] *= scal;  // v = [1; uc[c+1:] * scal]
-      __syncthreads();
-      if (tid == 0) uc[c] = beta_h;
-      // apply (I - tau v v^T) to columns c+1 .. cols-1, one wave per column
-      if (tau != 0.0) {
-        for (int q = c + 1 + wv; q < cols; q += nwv) {
-          double* uq = a.Uq + (size_t)q * d;
-          double dot = 0.0;
-          for (int i = c + 1 + lane; i < d; i += 64) dot += uc[i] * uq[i];
-          dot = wave_sum_c(dot) + uq[c];
-          const double f = tau * dot;
-          if (lane == 0) uq[c] -= f;
-          for (int i = c + 1 + lane; i < d; i += 64) uq[i] -= f * uc[i];
+      const double tau = rfs[b][0], scal = rfs[b][1];
+      if (q > c && q < cols) {
+        // H = I - tau v v^T with v = [1; U[c+1:, c] * scal].  Branch-free over the register rows:
+        // every index stays inside vcol, out-of-range rows are masked by selects.
+        double vc = 0.0, dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+          const int i = part + 8 * k;
+          const double v = vcol[b][i];
+          vc = (i == c) ? col[k] : vc;
+          dot += (i > c && i < d) ? v * col[k] : 0.0;
+        }
+        vc = sum8(vc);
+        dot = sum8(dot);
+        const double f = tau * (dot * scal + vc), fs = f * scal;
+        double nxt = 0.0;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+          const int i = part + 8 * k;
+          const double v = vcol[b][i];
+          const double upd = (i > c && i < d) ? col[k] - fs * v : (i == c ? col[k] - f : col[k]);
+          col[k] = upd;
+          nxt += (i >= c + 2 && i < d) ? upd * upd : 0.0;
+        }
+        if (q == c + 1) {  // publish the next reflector column and its tail norm
+#pragma unroll
+          for (int k = 0; k < KR; ++k) vcol[b ^ 1][part + 8 * k] = col[k];
+          nxt = sum8(nxt);
+          if (part == 0) tail2[c + 1] = nxt;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     // T = upper triangle of the factor with a positive diagonal (appendix: sign of t_11)
-    for (int e = tid; e < cols * cols; e += kThreads) {
-      const int i = e / cols, l = e % cols;
-      double v = 0.0;
-      if (l >= i) {
-        v = a.Uq[(size_t)l * d + i];
-        if (a.Uq[(size_t)i * d + i] < 0.0) v = -v;
+    if (q < cols) {
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = part + 8 * k;
+        if (i < q) Ts[i * ldT + q] = (diagR[i] < 0.0) ? -col[k] : col[k];
       }
-      Ts[i * ldT + l] = v;
+    }
+    for (int i = tid; i < cols; i += kWhitenThreads) Ts[i * ldT + i] = fabs(diagR[i]);
+  } else {
+    for (int i = tid; i < cols; i += kWhitenThreads) Ts[i * ldT + i] = 1.0;
+  }
+  __syncthreads();
+  whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+}
+
+// Whitening QR for large d (> 512): the same column-parallel Householder QR with the basis in
+// global scratch (U copied to a.Uq).
+__global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a) {
+  __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
+  __shared__ double rfs[2][2];
+  __shared__ double diagR[kMaxM + 1];
+  __shared__ double tail2[kMaxM + 2];
+  __shared__ double s_lds[kMaxM];
+  State* st = a.st;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int d = a.d;
+  const int mm = st->meff;
+  const int brk = st->brk;
+  if (st->nonfinite || mm == 0) return;
+  const int cols = brk ? mm : mm + 1;
+  const int ldT = kMaxM + 1;
+  for (int e = tid; e < cols * cols; e += kWhitenThreads) Ts[(e / cols) * ldT + (e % cols)] = 0.0;
+  __syncthreads();  // the zeros land before any entry of T is written below
+  if (!a.plain) {
+    double* Ub = a.Uq;
+    for (int e = tid; e < d * cols; e += kWhitenThreads) Ub[e] = a.U[e];
+    const int q = wv * 8 + (lane >> 3), part = lane & 7;
+    double* uq = Ub + (size_t)q * d;
+    __syncthreads();
+    if (q == 0) {
+      double s0 = 0.0;
+      for (int i = 1 + part; i < d; i += 8) s0 += uq[i] * uq[i];
+      s0 = sum8(s0);
+      if (part == 0) tail2[0] = s0;
+    }
+    for (int c = 0; c < cols; ++c) {
+      const double* uc = Ub + (size_t)c * d;
+      const int b = c & 1;
+      if (q == c && part == 0) {
+        const double s2 = tail2[c];
+        const double alp = uc[c];
+        const double nrm = sqrt(alp * alp + s2);
+        double tau = 0.0, beta_h = alp, scal = 0.0;
+        if (s2 > 0.0 || alp < 0.0) {
+          beta_h = (alp >= 0.0) ? -nrm : nrm;
+          tau = (beta_h - alp) / beta_h;
+          scal = 1.0 / (alp - beta_h);
+        }
+        rfs[b][0] = tau;
+        rfs[b][1] = scal;
+        diagR[c] = beta_h;
+      }
+      __syncthreads();
+      const double tau = rfs[b][0], scal = rfs[b][1];
+      if (q > c && q < cols) {
+        double nxt = 0.0;
+        if (tau != 0.0) {
+          double dot = 0.0;
+          for (int i = c + 1 + part; i < d; i += 8) dot += uc[i] * uq[i];
+          dot = sum8(dot);
+          const double f = tau * (dot * scal + uq[c]);
+          const double fs = f * scal;
+          for (int i = c + 1 + part; i < d; i += 8) {
+            const double v = uq[i] - fs * uc[i];
+            uq[i] = v;
+            if (i >= c + 2) nxt += v * v;
+          }
+          if (part == 0) uq[c] -= f;
+        } else if (q == c + 1) {
+          for (int i = c + 2 + part; i < d; i += 8) nxt += uq[i] * uq[i];
+        }
+        if (q == c + 1) {
+          nxt = sum8(nxt);
+          if (part == 0) tail2[c + 1] = nxt;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < cols * cols; e += kWhitenThreads) {
+      const int i = e / cols, l = e % cols;
+      if (l > i) Ts[i * ldT + l] = (diagR[i] < 0.0) ? -Ub[(size_t)l * d + i] : Ub[(size_t)l * d + i];
+      else if (l == i) Ts[i * ldT + l] = fabs(diagR[i]);
     }
   } else {
-    for (int e = tid; e < cols * cols; e += kThreads) {
-      const int i = e / cols, l = e % cols;
-      Ts[i * ldT + l] = (i == l) ? 1.0 : 0.0;
+    for (int i = tid; i < cols; i += kWhitenThreads) Ts[i * ldT + i] = 1.0;
+  }
+  __syncthreads();
+  whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+}
+
+// Quadrature solves, one wavefront per system s: (zeta_s I - Rt) y = e_1 with Rt upper Hessenberg.
+// Lane l holds column l of the row being eliminated (m <= 64); Gaussian elimination with partial
+// pivoting between neighbouring rows stores the triangular factor in LDS, then a column-oriented
+// back substitution needs one broadcast per row.  Adds alpha w_s psi_s y into the pass
+// coefficients of its rule (FP64 atomics into the zeroed g buffer) and advances
+// psi_s <- psi_s alpha r tau y_m.
+__device__ __forceinline__ cplx shfl_c(cplx v, int src) {
+  return cplx{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+// 1 / b through one real division (the moduli met here are far from the FP64 range limits)
+__device__ __forceinline__ cplx crecip(cplx b) {
+  const double s = 1.0 / (b.re * b.re + b.im * b.im);
+  return cplx{b.re * s, -b.im * s};
+}
+
+__global__ __launch_bounds__(64) void k_quad(SmallArgs a) {
+  extern __shared__ unsigned char smq[];
+  const State* st = a.st;
+  const int mm = st->meff;
+  if (st->nonfinite || mm == 0) return;
+  const int ld = mm + 1;
+  double* Xs = reinterpret_cast<double*>(smq);
+  cplx* Us = reinterpret_cast<cplx*>(smq + (((size_t)mm * ld * 8 + 15) & ~(size_t)15));
+  const int sidx = blockIdx.x, lane = threadIdx.x;
+  for (int e = lane; e < mm * mm; e += 64) {  // Rt is m x m column-major in global memory
+    const int i = e % mm, l = e / mm;
+    Xs[i * ld + l] = a.Xout[(size_t)l * a.m + i];
+  }
+  __syncthreads();
+  const cplx zeta = a.rz[sidx];
+  auto H = [&](int i, int l) -> cplx {
+    const double x = Xs[i * ld + l];
+    return (i == l) ? cmk(zeta.re - x, zeta.im) : cmk(-x, 0.0);
+  };
+  cplx carry = (lane < mm) ? H(0, lane) : cmk(0.0, 0.0);
+  cplx rc = cmk(1.0, 0.0);
+  cplx r = cmk(0.0, 0.0);  // right-hand side entry of row `lane` after elimination
+  for (int i = 0; i < mm - 1; ++i) {
+    const cplx av = shfl_c(carry, i);
+    const cplx hb = (lane < mm) ? H(i + 1, lane) : cmk(0.0, 0.0);
+    const cplx bs = shfl_c(hb, i);
+    if (cabs1(bs) > cabs1(av)) {  // pivot on row i+1 (uniform branch)
+      const cplx mult = cmul(av, crecip(bs));
+      if (lane >= i && lane < mm) Us[i * ld + lane] = hb;
+      if (lane == i) r = cmk(0.0, 0.0);
+      carry = csub(carry, cmul(mult, hb));
+    } else {
+      const cplx mult = (av.re == 0.0 && av.im == 0.0) ? cmk(0.0, 0.0) : cmul(bs, crecip(av));
+      if (lane >= i && lane < mm) Us[i * ld + lane] = carry;
+      if (lane == i) r = rc;
+      carry = csub(hb, cmul(mult, carry));
+      rc = csub(cmk(0.0, 0.0), cmul(mult, rc));
     }
   }
-  __syncthreads();
-  for (int e = tid; e < (m + 1) * (m + 1); e += kThreads) {
-    const int i = e % (m + 1), l = e / (m + 1);  // column-major output
-    a.Tout[e] = (i < cols && l < cols) ? Ts[i * ldT + l] : 0.0;
+  if (lane == mm - 1) {
+    Us[(mm - 1) * ld + lane] = carry;
+    r = rc;
   }
+  __syncthreads();
+  const cplx inv_ll = (lane < mm) ? crecip(Us[lane * ld + lane]) : cmk(0.0, 0.0);
+  cplx y = cmk(0.0, 0.0);
+  for (int i = mm - 1; i >= 0; --i) {
+    const cplx yi = cmul(shfl_c(r, i), shfl_c(inv_ll, i));
+    if (lane == i) y = yi;
+    if (lane < i) r = csub(r, cmul(Us[lane * ld + i], yi));
+  }
+  const cplx ps = a.psi[sidx];
+  const cplx wp = cmul(a.rw[sidx], ps);
+  {
+    // add alpha * w psi y into the coefficients of its rule and time point (twice the real part
+    // for the conjugate-half exp rules)
+    const int nq_tot = a.nq_main + a.nq_chk;
+    const int it = sidx / nq_tot, l = sidx % nq_tot, rule = (l >= a.nq_main) ? 1 : 0;
+    const double fac = (a.fun == 0) ? 2.0 : 1.0;
+    if (lane < mm)
+      unsafeAtomicAdd(a.gbuf + (size_t)rule * a.nt * a.m + (size_t)it * a.m + lane,
+                      fac * st->alpha * cmul(wp, y).re);
+  }
+  const cplx ym = shfl_c(y, mm - 1);
+  if (lane == 0) a.psi[sidx] = cscale(cmul(ps, ym), st->cpl);
+}
 
-  // ---- 2. X = T_m R_m T_m^{-1} (+ rank-one), h, beta
-  const double* R = a.R;
-  const int ldR = m + 1;
-  for (int e = tid; e < mm * mm; e += kThreads) {  // P = T_m R_m (R upper Hessenberg)
-    const int i = e / mm, c = e % mm;
-    double s = 0.0;
-    const int lend = min(c + 1, mm - 1);
-    for (int l = i; l <= lend; ++l) s += Ts[i * ldT + l] * R[(size_t)c * ldR + l];
-    Xs[i * kMaxM + c] = s;
+// Pass coefficients C[:, t] (t < nt) from the main rule's sums, and the disagreement of the two
+// rules measured in the sketch-orthonormal coordinates, ||T_m (c_main - c_check)||.  The restart
+// column C[:, nt] was written by the whitening kernel.  One wavefront per time point.
+__global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a) {
+  __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
+  State* st = a.st;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = kThreads / 64;
+  const int m = a.m, nt = a.nt;
+  const int mm = st->meff;
+  const int C_ld = m + 1, ldT = kMaxM + 1;
+  if (st->nonfinite || mm == 0) {
+    for (int i = tid; i < (m + 1) * (nt + 1); i += kThreads) a.C[i] = 0.0;
+    return;
+  }
+  for (int e = tid; e < mm * mm; e += kThreads) {
+    const int i = e % mm, l = e / mm;
+    Ts[i * ldT + l] = a.Tout[(size_t)l * (m + 1) + i];
   }
   __syncthreads();
-  for (int i = tid; i < mm; i += kThreads) {  // row i of X: X[i,:] T_m = P[i,:]
-    for (int c = 0; c < mm; ++c) {
-      double s = Xs[i * kMaxM + c];
-      for (int l = 0; l < c; ++l) s -= Xs[i * kMaxM + l] * Ts[l * ldT + c];
-      Xs[i * kMaxM + c] = s / Ts[c * ldT + c];
-    }
-  }
-  __syncthreads();
-  double hcoup = 0.0;
-  if (!brk) {
-    const double r = R[(size_t)(mm - 1) * ldR + mm];
-    const double tmm = Ts[(mm - 1) * ldT + (mm - 1)];
-    hcoup = r * Ts[mm * ldT + mm] / tmm;
-    for (int i = tid; i < mm; i += kThreads) Xs[i * kMaxM + (mm - 1)] += (r / tmm) * Ts[i * ldT + mm];
-  }
-  const double beta = st->alpha * Ts[0];
-  __syncthreads();
-  for (int e = tid; e < m * m; e += kThreads) {
-    const int i = e % m, c = e / m;
-    a.Xout[e] = (i < mm && c < mm) ? Xs[i * kMaxM + c] : 0.0;
-  }
-  if (tid == 0) {
-    st->beta = beta;
-    st->h = hcoup;
-  }
-
-  // ---- 3. quadrature solves (zeta_l I - X) y = e_1, one system per thread
-  const int nq_tot = a.nq_main + a.nq_chk;
-  const int nsys = nt * nq_tot;
-  for (int s = tid; s < nsys; s += kThreads) hess_solve(mm, Xs, kMaxM, a.rz[s], a.scr + s, a.ldscr);
-  __syncthreads();
-
-  // ---- 4. g_t = beta * sum_l w_l psi_l y_l  (twice the real part for conjugate-half rules)
-  const double fac = (a.fun == 0) ? 2.0 : 1.0;
-  for (int e = tid; e < 2 * nt * mm; e += kThreads) {
-    const int rule = e / (nt * mm), rem = e % (nt * mm), it = rem / mm, i = rem % mm;
-    const int l0 = it * nq_tot + (rule ? a.nq_main : 0);
-    const int l1 = l0 + (rule ? a.nq_chk : a.nq_main);
-    double acc = 0.0;
-    for (int l = l0; l < l1; ++l) {
-      const cplx y = a.scr[(size_t)i * a.ldscr + l];
-      const cplx wp = cmul(a.rw[l], a.psi[l]);
-      acc += wp.re * y.re - wp.im * y.im;
-    }
-    a.gbuf[(size_t)rule * nt * m + (size_t)it * m + i] = fac * beta * acc;
-  }
-  __syncthreads();
-  // psi_l <- psi_l * beta * h * [y_l]_m
-  for (int s = tid; s < nsys; s += kThreads) {
-    const cplx ym = a.scr[(size_t)(mm - 1) * a.ldscr + s];
-    a.psi[s] = cscale(cmul(a.psi[s], ym), beta * hcoup);
-  }
-
-  // ---- 5. pass coefficients: C[:, t] = T_m^{-1} g_t ; C[:, nt] = restart vector coefficients
-  for (int it = tid; it <= nt; it += kThreads) {
+  for (int it = wv; it < nt; it += nwv) {
     double* col = a.C + (size_t)it * C_ld;
-    if (it < nt) {
-      const double* g = a.gbuf + (size_t)it * m;
-      for (int i = mm - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int l = i + 1; l < mm; ++l) s -= Ts[i * ldT + l] * col[l];
-        col[i] = s / Ts[i * ldT + i];
-      }
-      // disagreement of the two rules, measured in the sketch-orthonormal coordinates
-      const double* gc = a.gbuf + (size_t)nt * m + (size_t)it * m;
-      double q2 = 0.0;
-      for (int i = 0; i < mm; ++i) q2 += (g[i] - gc[i]) * (g[i] - gc[i]);
-      st->qdis2[it] = q2;
-    } else if (!brk) {
-      // v_hat = (w_{m+1} - W_m T_m^{-1} t) / tau
-      const double tau = Ts[mm * ldT + mm];
-      for (int i = mm - 1; i >= 0; --i) {
-        double s = Ts[i * ldT + mm];
-        for (int l = i + 1; l < mm; ++l) s -= Ts[i * ldT + l] * (-col[l] * tau);
-        col[i] = -(s / Ts[i * ldT + i]) / tau;
-      }
-      col[mm] = 1.0 / tau;
+    const double cm = (lane < mm) ? a.gbuf[(size_t)it * m + lane] : 0.0;
+    const double cc = (lane < mm) ? a.gbuf[(size_t)nt * m + (size_t)it * m + lane] : 0.0;
+    const double dl = cm - cc;
+    double td = 0.0;  // (T_m (c_main - c_check))_lane
+    for (int l = 0; l < mm; ++l) {
+      const double dv = __shfl(dl, l, 64);
+      if (lane <= l && lane < mm) td += Ts[lane * ldT + l] * dv;
     }
+    double q2 = td * td;
+    for (int off = 32; off > 0; off >>= 1) q2 += __shfl_xor(q2, off, 64);
+    if (lane == 0) st->qdis2[it] = q2;
+    for (int e = lane; e <= m; e += 64) col[e] = (e < mm) ? __shfl(cm, e & 63, 64) : 0.0;
   }
 }
 
@@ -537,8 +685,29 @@ hipError_t launch_start(hipStream_t s, int d, int m, int plain, double* slots_st
   return hipGetLastError();
 }
 
+size_t quad_lds(int m) { return (size_t)m * (m + 1) * 8 + 16 + (size_t)m * (m + 1) * sizeof(cplx); }
+
+hipError_t configure_cycle_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_quad), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)quad_lds(kMaxM));
+}
+
 hipError_t launch_small(hipStream_t s, const SmallArgs& a) {
-  hipLaunchKernelGGL(k_small, dim3(1), dim3(kThreads), 0, s, a);
+  if (a.plain || a.d <= 64)
+    hipLaunchKernelGGL(k_whiten<8>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+  else if (a.d <= 256)
+    hipLaunchKernelGGL(k_whiten<32>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+  else if (a.d <= 512)
+    hipLaunchKernelGGL(k_whiten<64>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_whiten_mem, dim3(1), dim3(kWhitenThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nsys = a.nt * (a.nq_main + a.nq_chk);
+  hipLaunchKernelGGL(k_quad, dim3(nsys), dim3(64), quad_lds(a.m), s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

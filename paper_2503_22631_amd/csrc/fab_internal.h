@@ -104,7 +104,7 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
 // Device-resident solver state (one per solve; FP64).
 // ----------------------------------------------------------------------------------------------
 struct State {
-  double alpha, inv_alpha, beta, h;
+  double alpha, inv_alpha, beta, h, cpl;  // cpl = alpha r_{m+1,m} tau: restart coupling of psi
   double upd_coef[kMaxM + 1];   // window coefficients r_ij of the current step (index i - lo)
   double inv_rho, raw2;
   int meff, brk, nonfinite, step_lo;
@@ -127,11 +127,11 @@ struct SmallArgs {
   double* Uq;       // d x (m+1) scratch for the Householder QR
   const double* R;  // (m+1) x m
   double* Tout;     // (m+1) x (m+1)
-  double* Xout;     // m x m
+  double* Xout;     // m x m: Rt = R_m + r_{m+1,m} T_m^{-1} t e_m^T (similar to the whitened X)
   const cplx* rz;
   const cplx* rw;
   cplx* psi;
-  cplx* scr;        // per-system scratch, element e of system s at scr[e * ldscr + s]
+  cplx* scr;        // per-system restart contributions, entry i of system s at scr[s * ldscr + i]
   double* gbuf;     // 2 x nt x m: main and check rule results
   double* C;        // (m+1) x (nt+1) pass coefficients
   State* st;

@@ -2,11 +2,12 @@
 // classical Arnoldi comparator, for gfx950.
 //
 //   k_spmv_sketch : z = A w_j (CSR, one row per lane) fused with u = S z, the sparse-sign sketch
-//                   (Algorithm 1 lines 7-8).  S is regenerated on the fly from the counter-based
-//                   spec, scattered into per-block LDS bins and added into kSlots global copies.
-//   k_orth        : one workgroup; modified Gram-Schmidt of the sketch against the last k sketched
-//                   basis vectors (lines 9-12), the Hessenberg column, rho and the breakdown test.
-//   k_update      : w_{j+1} = (z - sum_i r_ij w_i) / rho over the window (lines 12-14).
+//                   (the product and sketch of Algorithm 1).  S comes from its counter-based spec
+//                   (regenerated per row from its counter-based spec), scattered into per-block
+//                   LDS bins and added into kSlots global copies.
+//   k_orth        : one wavefront; modified Gram-Schmidt of the sketch against the last k sketched
+//                   basis vectors, the Hessenberg column, rho and the breakdown test.
+//   k_update      : w_{j+1} = (z - sum_i r_ij w_i) / rho over the window (the basis update of Algorithm 1).
 //   k_gram / k_cgs_update / k_plain_finish : classical Gram-Schmidt applied twice (CGS2) for the
 //                   plain restarted Arnoldi comparator.
 #include "fab_internal.h"
@@ -47,18 +48,30 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 
 // ---------------------------------------------------------------------------------------------
 // MODE 0: y = A x and sketch of y;  MODE 1: sketch of x only;  MODE 2: y = A x only.
-// The sketch accumulates in the value type in LDS (FP64 or FP32) and in FP64 in the global slots.
+//
+// Each block walks row tiles of kThreads rows (XCD-contiguous slabs).  The tile's nonzeros are
+// staged through LDS in chunks of kChunk with coalesced loads of values and column indices, then
+// every lane forms its own row (so stencil gathers of x stay coalesced across the wavefront).
+// The sketch of the row value is scattered into per-block LDS bins (value type), which are added
+// into one of kSlots global FP64 copies at the end.  The rows and signs of S are regenerated from
+// the counter-based specification for every row (no bytes of S are read): with the LDS-staged
+// product the generator's integer work overlaps the memory traffic.
 // ---------------------------------------------------------------------------------------------
+constexpr int kChunk = 2048;
+
 template <typename T, int MODE, int ZMAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
                                                           const T* __restrict__ vals,
                                                           const T* __restrict__ x, T* __restrict__ y,
-                                                          int d, int zeta, T scale, uint32_t k0,
-                                                          uint32_t k1, double* __restrict__ slots,
+                                                          int d, int zeta, T scale, uint32_t k0, uint32_t k1,
+                                                          double* __restrict__ slots,
                                                           const State* __restrict__ st) {
   extern __shared__ unsigned char smem_raw[];
+  const int bins_bytes = (MODE == 2) ? 0 : ((d * (int)sizeof(T) + 15) & ~15);
   T* bins = reinterpret_cast<T*>(smem_raw);
+  T* sv = reinterpret_cast<T*>(smem_raw + bins_bytes);
+  int* sc = reinterpret_cast<int*>(smem_raw + bins_bytes + kChunk * sizeof(T));
   if (st != nullptr && st->brk) return;
   if (MODE != 2) {
     for (int i = threadIdx.x; i < d; i += kThreads) bins[i] = T(0);
@@ -68,27 +81,40 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
   TileWalk tw(ntiles);
   for (int tt = tw.local; tt < tw.per_xcd; tt += tw.nloc) {
     const int tile = tw.xcd * tw.per_xcd + tt;
-    const int row = tile * kThreads + threadIdx.x;
-    if (tile >= ntiles || row >= n) continue;
-    T z;
+    if (tile >= ntiles) break;  // uniform over the block
+    const int row0 = tile * kThreads;
+    const int row = row0 + threadIdx.x;
+    const bool live = row < n;
+    T z = T(0);
     if (MODE != 1) {
+      const int rend = min(row0 + kThreads, n);
+      const int p0 = rowptr[row0], p1 = rowptr[rend];
+      const int my_lo = live ? rowptr[row] : 0, my_hi = live ? rowptr[row + 1] : 0;
       T acc = T(0);
-      const int p0 = rowptr[row], p1 = rowptr[row + 1];
-      for (int p = p0; p < p1; ++p) acc = fma(vals[p], x[colind[p]], acc);
-      y[row] = acc;
+      for (int cs = p0; cs < p1; cs += kChunk) {
+        const int len = min(kChunk, p1 - cs);
+        __syncthreads();  // the previous chunk has been consumed
+        for (int e = threadIdx.x; e < len; e += kThreads) {
+          sv[e] = vals[cs + e];
+          sc[e] = colind[cs + e];
+        }
+        __syncthreads();
+        const int lo = max(my_lo, cs), hi = min(my_hi, cs + len);
+        for (int p = lo; p < hi; ++p) acc = fma(sv[p - cs], x[sc[p - cs]], acc);
+      }
+      if (live) y[row] = acc;
       z = acc;
-    } else {
+    } else if (live) {
       z = x[row];
     }
-    if (MODE != 2) {
+    if (MODE != 2 && live) {
+      const T zs = z * scale;
       int rows[ZMAX];
       uint32_t sb;
       sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
-      const T zs = z * scale;
 #pragma unroll
-      for (int l = 0; l < ZMAX; ++l) {
+      for (int l = 0; l < ZMAX; ++l)
         if (l < zeta) unsafeAtomicAdd(&bins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
-      }
     }
   }
   if (MODE != 2) {
@@ -102,50 +128,48 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
 }
 
 // ---------------------------------------------------------------------------------------------
-// Sketch-space modified Gram-Schmidt of step j (one workgroup).
+// Sketch-space modified Gram-Schmidt of step j, one wavefront (no barriers).  Element e of the
+// d-vector lives in lane e % 64, slot e / 64 (PER slots per lane, d <= 64 PER).
 // slots_cur: kSlots x d partial sketches of z; slots_next: the other set, zeroed here for step j+1.
 // U: d x (m+1) sketched basis (column j+1 written); R: (m+1) x m Hessenberg (column j written).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_orth(int j, int k, int m, int d,
-                                                   const double* __restrict__ slots_cur,
-                                                   double* __restrict__ slots_next, double* __restrict__ U,
-                                                   double* __restrict__ R, State* __restrict__ st) {
-  __shared__ double red[2 * (kThreads / 64)];
-  int phase = 0;
+template <int PER>
+__global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ slots_cur,
+                                             double* __restrict__ slots_next, double* __restrict__ U,
+                                             double* __restrict__ R, State* __restrict__ st) {
   if (st->brk) return;
-  constexpr int PER = kMaxD / kThreads;
+  const int lane = threadIdx.x;
+  const int lo = max(0, j - k + 1);
   double u[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int i = threadIdx.x + q * kThreads;
+    const int e = lane + 64 * q;
     double s = 0.0;
-    if (i < d) {
+    if (e < d) {
 #pragma unroll
-      for (int c = 0; c < kSlots; ++c) s += slots_cur[(size_t)c * d + i];
+      for (int c = 0; c < kSlots; ++c) s += slots_cur[(size_t)c * d + e];
     }
     u[q] = s;
   }
-  for (int i = threadIdx.x; i < kSlots * d; i += kThreads) slots_next[i] = 0.0;
+  for (int i = lane; i < kSlots * d; i += 64) slots_next[i] = 0.0;
   double loc = 0.0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
-  const double raw2 = block_sum(loc, red, phase);
-  const int lo = max(0, j - k + 1);
+  const double raw2 = wave_sum(loc);
   for (int i = lo; i <= j; ++i) {
     const double* Ui = U + (size_t)i * d;
+    double ui[PER];
     loc = 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * kThreads;
-      if (e < d) loc += Ui[e] * u[q];
+      const int e = lane + 64 * q;
+      ui[q] = (e < d) ? Ui[e] : 0.0;
+      loc += ui[q] * u[q];
     }
-    const double r = block_sum(loc, red, phase);
+    const double r = wave_sum(loc);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * kThreads;
-      if (e < d) u[q] -= r * Ui[e];
-    }
-    if (threadIdx.x == 0) {
+    for (int q = 0; q < PER; ++q) u[q] -= r * ui[q];
+    if (lane == 0) {
       R[(size_t)j * (m + 1) + i] = r;
       st->upd_coef[i - lo] = r;
     }
@@ -153,11 +177,11 @@ __global__ __launch_bounds__(kThreads) void k_orth(int j, int k, int m, int d,
   loc = 0.0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
-  const double rho = sqrt(block_sum(loc, red, phase));
+  const double rho = sqrt(wave_sum(loc));
   const bool finite = isfinite(rho) && isfinite(raw2);
   const bool breakdown = !(rho > 64.0 * 2.220446049250313e-16 * sqrt(raw2));
   if (!finite || breakdown) {
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       st->brk = 1;
       st->meff = j + 1;
       if (!finite) st->nonfinite = 1;
@@ -168,10 +192,10 @@ __global__ __launch_bounds__(kThreads) void k_orth(int j, int k, int m, int d,
   double* Un = U + (size_t)(j + 1) * d;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * kThreads;
+    const int e = lane + 64 * q;
     if (e < d) Un[e] = u[q] * inv;
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     R[(size_t)j * (m + 1) + j + 1] = rho;
     st->inv_rho = inv;
     st->step_lo = lo;
@@ -316,27 +340,33 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 }
 
 // ------------------------------------------------------------------------------------ launchers
+size_t spmv_sketch_lds(int dtype, int mode, int d) {
+  const size_t es = dtype == 0 ? 8 : 4;
+  const size_t bins = (mode == 2) ? 0 : ((d * es + 15) & ~(size_t)15);
+  return bins + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
+}
+
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
                                        const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
                                        double* slots, const State* st) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
-  const size_t lds = (mode == 2) ? 0 : (size_t)d * sizeof(T);
-#define FAB_L(M, Z)                                                                                    \
+  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d);
+#define FAB_L(M, Z)                                                                                   \
   hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), dim3(grid), dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, \
                      zeta, scale, k0, k1, slots, st)
-#define FAB_Z(M)          \
-  if (zeta <= 1) {        \
-    FAB_L(M, 1);          \
-  } else if (zeta <= 4) { \
-    FAB_L(M, 4);          \
-  } else if (zeta <= 8) { \
-    FAB_L(M, 8);          \
+#define FAB_Z(M)           \
+  if (zeta <= 1) {         \
+    FAB_L(M, 1);           \
+  } else if (zeta <= 4) {  \
+    FAB_L(M, 4);           \
+  } else if (zeta <= 8) {  \
+    FAB_L(M, 8);           \
   } else if (zeta <= 16) { \
-    FAB_L(M, 16);         \
-  } else {                \
-    FAB_L(M, 32);         \
+    FAB_L(M, 16);          \
+  } else {                 \
+    FAB_L(M, 32);          \
   }
   if (mode == 0) {
     FAB_Z(0)
@@ -362,7 +392,14 @@ hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int 
 
 hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* cur, double* next, double* U,
                        double* R, State* st) {
-  hipLaunchKernelGGL(k_orth, dim3(1), dim3(kThreads), 0, s, j, k, m, d, cur, next, U, R, st);
+  if (d <= 256)
+    hipLaunchKernelGGL(k_orth<4>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+  else if (d <= 512)
+    hipLaunchKernelGGL(k_orth<8>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+  else if (d <= 1024)
+    hipLaunchKernelGGL(k_orth<16>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+  else
+    hipLaunchKernelGGL(k_orth<32>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
   return hipGetLastError();
 }
 

@@ -86,10 +86,14 @@ def test_cycle_matches_oracle_twin(fab, ctx, N, m, k, d, zeta):
     c = krylov.sketched_cycle(A.to_scipy(), S, v, m, k)
     assert g["m"] == c.m == m
     assert abs(g["alpha"] - c.alpha) <= 1e-13 * c.alpha
+    Tm, r = c.T[:m, :m], c.R[m, m - 1]
+    Rt = c.R[:m, :m] + r * np.outer(np.linalg.solve(Tm, c.T[:m, m]), np.eye(m)[m - 1])
     for name, gv, ov in [("W", g["W"], c.W), ("U", g["U"], c.U), ("R", g["R"], c.R), ("T", g["T"], c.T),
-                         ("X", g["X"], c.X)]:
+                         ("Rt", g["Rt"], Rt)]:
         e = _rel(gv.cpu().numpy(), ov)
         assert e <= 1e-10, (name, e)
+    Tg = g["T"].cpu().numpy()[:m, :m]
+    assert _rel(Tg @ g["Rt"].cpu().numpy() @ np.linalg.inv(Tg), c.X) <= 1e-10   # the whitened X
     assert abs(g["h"] - c.h) <= 1e-10 * abs(c.h)
     assert abs(g["beta"] - c.beta) <= 1e-13 * c.beta
 
@@ -101,7 +105,7 @@ def test_plain_cycle_matches_arnoldi(fab, ctx):
     g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=16, k=16, d=17, zeta=1, method="plain")
     c = krylov.arnoldi_cycle(A.to_scipy(), v, 16)
     assert _rel(g["W"].cpu().numpy(), c.W) <= 1e-11
-    assert _rel(g["X"].cpu().numpy(), c.X) <= 1e-11
+    assert _rel(g["Rt"].cpu().numpy(), c.X) <= 1e-11                              # T = I: Rt = H_m
     assert abs(g["h"] - c.h) <= 1e-11 * c.h
 
 
@@ -251,3 +255,40 @@ def test_convdiff_128_full_size(fab, ctx):
     ref = exact.kron_exp_fab(b, factors, 1e-4)
     assert info["status"] == "FAB_OK", info
     assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
+
+
+def test_timing_hooks_count_launches(fab, ctx):
+    """Benchmark timing: one event pair per SpMV+sketch launch, recorded inside the cycle graph."""
+    A = wl.laplacian_2d(64)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 0), device="cuda")
+    fab.timing_enable(ctx, True)
+    try:
+        fab.timing_read(ctx)
+        x, info = fab.solve(op, b, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, tol=1e-10)
+        tm = fab.timing_read(ctx)
+    finally:
+        fab.timing_enable(ctx, False)
+    assert tm["spmv_launches"] == 20 * info["cycles"]
+    assert tm["loop_steps"] == 20 * info["cycles"]
+    assert 0 < tm["spmv_ms"] < tm["loop_ms"]
+    x2, _ = fab.solve(op, b, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, tol=1e-10)
+    assert _rel(x2.cpu().numpy(), x.cpu().numpy()) <= 1e-13
+
+
+@pytest.mark.parametrize("d,zeta", [(300, 16), (90, 8), (257, 2)])
+def test_hash_and_table_paths_match_oracle(fab, ctx, d, zeta):
+    """The sketch comes from the packed per-solve table when d <= 256 and zeta <= 8, otherwise from
+    the generator inside the fused kernel; both must reproduce the oracle twin with the same S."""
+    A = wl.convdiff_3d(14, 20.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 12)
+    t = 5e-4
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, m=24, k=3, d=d, zeta=zeta, seed=5,
+                        tol=1e-12, max_cycles=30)
+    S = sketch.sketch_matrix(A.n, d, zeta, seed=5)
+    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=24, k=3, S=S, tol=1e-12, max_cycles=30)
+    assert info["cycles"] == io.cycles
+    assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-11
+    factors, _ = exact.problem_factors("convdiff_3d", 14, peclet=20.0)
+    assert _rel(x[:, 0].cpu().numpy(), exact.kron_exp_fab(b, factors, t)) <= 1e-10
