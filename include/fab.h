@@ -46,12 +46,12 @@ typedef enum {
   FAB_OK = 0,
   FAB_OK_BREAKDOWN = 1,     /* invariant Krylov subspace found: result exact */
   FAB_W_NOT_CONVERGED = 2,  /* max_cycles reached; x holds the last iterate  */
-  FAB_W_QUADRATURE = 3,     /* main and check quadrature rules disagree       */
+  FAB_W_QUADRATURE = 3,     /* rule error > max(tol/10, 1e-11) (see below)   */
   FAB_E_INVALID = -1,       /* bad argument (sizes, nulls, parameter ranges)  */
   FAB_E_UNSUPPORTED = -2,   /* valid but not supported by this build          */
   FAB_E_HIP = -3,           /* a HIP runtime call failed                      */
   FAB_E_NONFINITE = -4,     /* NaN/Inf met in the iteration (A or b)          */
-  FAB_E_DIVERGED = -5,      /* estimate grew 10x over two cycles              */
+  FAB_E_DIVERGED = -5,      /* an increment exceeded 1e8 ||x||                */
   FAB_E_WORKSPACE = -6      /* work_bytes smaller than fab_workspace_size     */
 } fab_status;
 
@@ -80,7 +80,12 @@ typedef struct {
   int32_t matvecs;         /* products with A                                       */
   int32_t reserved;
   double est_rel_update;   /* max_t ||y_t|| / ||x_t|| of the last cycle             */
-  double quad_disagreement;/* max over cycles of ||g_main - g_check|| / ||x||        */
+  double quad_rule_error;  /* error of the partial-fraction rule r against f over   *
+                            * the spectral region, max over 256 samples and t: exp: *
+                            * |r - f| at t z = 0 and t z geometric in [1e-4, 1e4];  *
+                            * z^(-1/2): |r/f - 1| at z geometric in [lo, hi].  The   *
+                            * restarted iteration with a fixed rule converges to     *
+                            * r(A) b, so this bounds what the rule adds to the error */
 } fab_info;
 
 typedef struct fab_ctx fab_ctx;

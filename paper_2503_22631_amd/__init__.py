@@ -149,7 +149,7 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
         _lib.check(st, "fab_solve")
     out = {"status": _lib.STATUS.get(info.status, info.status), "code": int(st), "cycles": info.cycles,
            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update,
-           "quad_disagreement": info.quad_disagreement}
+           "quad_rule_error": info.quad_rule_error}
     return x.view(nt, op.n).t(), out
 
 

@@ -34,7 +34,7 @@ hipError_t launch_scale_col(hipStream_t, int dtype, int grid, int n, void* v, co
                             const State* st);
 hipError_t launch_zero(hipStream_t, double* p, size_t count);
 hipError_t launch_rule(hipStream_t, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
-                       cplx* rz, cplx* rw, cplx* psi);
+                       cplx* rz, cplx* rw, cplx* psi, State* st);
 hipError_t launch_copy_in(hipStream_t, int dtype, int grid, int n, const void* b, void* w0);
 hipError_t launch_sqnorm(hipStream_t, int dtype, int grid, int n, const void* v, double* slots);
 hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_start, double* slots_step,
@@ -93,6 +93,8 @@ struct fab_op {
   int dtype;
 };
 
+constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which the solve is abandoned
+
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static int rule_nodes(int fun, const fab_params* p) { return (p->n_quad > 0) ? p->n_quad : kRuleMain; }
@@ -103,9 +105,8 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   const int m = p->m;
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   const int N = rule_nodes(fun, p);
-  L.nq_main = (fun == FAB_EXP_NEG) ? N / 2 : N;
-  L.nq_chk = (fun == FAB_EXP_NEG) ? ((3 * N) / 4) / 2 : (3 * N) / 4;
-  L.nsys = nt * (L.nq_main + L.nq_chk);
+  L.nq = (fun == FAB_EXP_NEG) ? N / 2 : N;
+  L.nsys = nt * L.nq;
   const size_t step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -127,7 +128,7 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.rule_z = take((size_t)L.nsys * sizeof(cplx));
   L.rule_w = take((size_t)L.nsys * sizeof(cplx));
   L.psi = take((size_t)L.nsys * sizeof(cplx));
-  L.gbuf = take((size_t)2 * nt * m * 8 + (size_t)nt * 8 /* t values */);
+  L.gbuf = take((size_t)nt * m * 8 + (size_t)nt * 8 /* t values */);
   L.scratch = take(0);
   L.ldscr = m;
   L.report = 0;
@@ -192,7 +193,7 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   q.rw = (cplx*)(q.base + L.rule_w);
   q.psi = (cplx*)(q.base + L.psi);
   q.gbuf = (double*)(q.base + L.gbuf);
-  q.tvals = q.gbuf + (size_t)2 * nt * p->m;
+  q.tvals = q.gbuf + (size_t)nt * p->m;
   q.scr = (cplx*)(q.base + L.scratch);
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   q.step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
@@ -278,8 +279,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.nt = nt;
   a.plain = plain ? 1 : 0;
   a.fun = fun;
-  a.nq_main = L.nq_main;
-  a.nq_chk = L.nq_chk;
+  a.nq = L.nq;
   a.ldscr = L.ldscr;
   a.U = q.U;
   a.Uq = q.Ut;
@@ -316,12 +316,12 @@ const char* fab_status_string(fab_status s) {
     case FAB_OK: return "ok";
     case FAB_OK_BREAKDOWN: return "ok: breakdown (invariant subspace, exact result)";
     case FAB_W_NOT_CONVERGED: return "warning: max_cycles reached before the tolerance";
-    case FAB_W_QUADRATURE: return "warning: main and check quadrature rules disagree";
+    case FAB_W_QUADRATURE: return "warning: the quadrature rule misses f by more than tol/10 on the spectral region";
     case FAB_E_INVALID: return "error: invalid argument";
     case FAB_E_UNSUPPORTED: return "error: unsupported size or option";
     case FAB_E_HIP: return "error: HIP runtime failure";
     case FAB_E_NONFINITE: return "error: non-finite value in the iteration";
-    case FAB_E_DIVERGED: return "error: the restart iteration diverged";
+    case FAB_E_DIVERGED: return "error: the restart iteration diverged (increment > 1e8 ||x||)";
     case FAB_E_WORKSPACE: return "error: workspace too small";
   }
   return "unknown status";
@@ -433,7 +433,7 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
   for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double) * nt, hipMemcpyHostToDevice, s));
-  FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi));
+  FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi, q.st));
   FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, b, q.W));
 
   GraphKey key;
@@ -474,8 +474,7 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   }
   fab_status status = FAB_W_NOT_CONVERGED;
   int cycles = 0, matvecs = 0;
-  double est = 0.0, qdis = 0.0;
-  std::vector<double> hist;
+  double est = 0.0, rule_err = 0.0;
   for (int c = 0; c < p->max_cycles; ++c) {
     if (ctx->timing) {
       const fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, &ctx->tev);
@@ -503,8 +502,7 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
     cycles = c + 1;
     matvecs += r.meff;
     est = r.est;
-    qdis = std::max(qdis, r.qdis_rel);
-    hist.push_back(est);
+    rule_err = std::max(rule_err, r.rule_err);
     if (r.nonfinite) {
       status = FAB_E_NONFINITE;
       break;
@@ -518,19 +516,23 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
       status = FAB_OK;
       break;
     }
-    if (c >= 2 && est >= 1.0 && est >= 10.0 * hist[c - 2]) {
+    // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
+    // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
+    if (est > kDivergedEst) {
       status = FAB_E_DIVERGED;
       break;
     }
   }
-  if ((status == FAB_OK || status == FAB_OK_BREAKDOWN) && qdis > std::max(0.1 * p->tol, 1e-11))
+  // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
+  // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
+  if ((status == FAB_OK || status == FAB_OK_BREAKDOWN) && rule_err > std::max(0.1 * p->tol, 1e-11))
     status = FAB_W_QUADRATURE;
   if (h_info) {
     h_info->status = status;
     h_info->cycles = cycles;
     h_info->matvecs = matvecs;
     h_info->est_rel_update = est;
-    h_info->quad_disagreement = qdis;
+    h_info->quad_rule_error = rule_err;
   }
   return status;
 }
@@ -622,7 +624,7 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
   FAB_TRY(hipStreamSynchronize(s));
   ctx->h_t[0] = 1.0;
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double), hipMemcpyHostToDevice, s));
-  FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi));
+  FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi, q.st));
   FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, q.W));
   fab_status es2 = enqueue_cycle(ctx, s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false, nullptr);
   if (es2 != FAB_OK) return es2;

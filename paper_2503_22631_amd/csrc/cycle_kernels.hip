@@ -30,25 +30,20 @@ __global__ void k_zero(double* p, size_t count) {
 // fun 0, exp(-t z): parabolic Hankel contour s(u) = P - mu u^2 + 2 i mu u, u in [-U, U],
 //   U = sqrt((P+L)/mu), N midpoint nodes; zeta = -s/t, w = -h s'(u) e^s / (2 pi i t).  Only the
 //   nodes with u < 0 (Im zeta > 0) are kept: for real X the other half are conjugates, and the
-//   accumulation takes twice the real part.  Main rule (N, 3, 6, 45), check rule (3N/4, 5, 8, 45).
+//   accumulation takes twice the real part.  (N, P, mu, L) = (N, 3, 6, 45).
 // fun 1, z^(-1/2) = (2/pi) int_0^inf (z + s^2)^{-1} ds with s = c tan(theta), N midpoint nodes on
-//   (0, pi/2): zeta = -c^2 tan^2(theta), w = -(c/N) sec^2(theta), c = (lo hi)^(1/4).  Check rule 3N/4.
-// Layout per time point t: nq_main main nodes then nq_chk check nodes (nq_tot = nq_main + nq_chk).
+//   (0, pi/2): zeta = -c^2 tan^2(theta), w = -(c/N) sec^2(theta), c = (lo hi)^(1/4).
+// Layout: nq nodes per time point (nq = N/2 for exp, N for z^(-1/2)).
 __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_main, double lo, double hi,
                        cplx* __restrict__ rz, cplx* __restrict__ rw, cplx* __restrict__ psi) {
-  const int n_chk = (3 * n_main) / 4;
-  const int nq_main = (fun == 0) ? n_main / 2 : n_main;
-  const int nq_chk = (fun == 0) ? n_chk / 2 : n_chk;
-  const int nq_tot = nq_main + nq_chk;
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nt * nq_tot; s += gridDim.x * blockDim.x) {
-    const int it = s / nq_tot, l = s % nq_tot;
-    const bool chk = l >= nq_main;
-    const int idx = chk ? l - nq_main : l;
+  const int nq = (fun == 0) ? n_main / 2 : n_main;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nt * nq; s += gridDim.x * blockDim.x) {
+    const int it = s / nq, idx = s % nq;
     cplx z, w;
     if (fun == 0) {
       const double t = tvals[it];
-      const int N = chk ? n_chk : n_main;
-      const double P = chk ? 5.0 : 3.0, mu = chk ? 8.0 : 6.0, L = 45.0;
+      const int N = n_main;
+      const double P = kExpP, mu = kExpMu, L = kExpL;
       const double U = sqrt((P + L) / mu), h = 2.0 * U / N;
       const double u = -U + (idx + 0.5) * h;
       const cplx sv = cmk(P - mu * u * u, 2.0 * mu * u);
@@ -61,7 +56,7 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
       const double f = h / (2.0 * M_PI * t);
       w = cmk(-q.im * f, q.re * f);
     } else {
-      const int N = chk ? n_chk : n_main;
+      const int N = n_main;
       const double c = sqrt(sqrt(lo * hi));
       const double th = (idx + 0.5) * (0.5 * M_PI) / N;
       const double tn = tan(th), cs = cos(th);
@@ -71,6 +66,46 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
     rz[s] = z;
     rw[s] = w;
     psi[s] = cmk(1.0, 0.0);
+  }
+}
+
+// Accuracy of the rule as a function, once per solve: the restarted iteration with a fixed rule r
+// converges to r(A) b, so |r - f| over the spectral region bounds what the rule adds to the error.
+// Samples (kRuleSamples per time point): exp(-t z) at t z = 0 and t z geometric in [1e-4, 1e4],
+// absolute error (f <= 1 there); z^(-1/2) at z geometric in [lo, hi], relative error.  The largest
+// error over samples and time points goes to st->rule_err.  One block of kRuleSamples threads.
+__global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, const double* __restrict__ tvals,
+                                                             int nq, double lo, double hi,
+                                                             const cplx* __restrict__ rz,
+                                                             const cplx* __restrict__ rw, State* __restrict__ st) {
+  __shared__ double red[kRuleSamples / 64];
+  const int j = threadIdx.x;
+  double err = 0.0;
+  for (int it = 0; it < nt; ++it) {
+    const cplx* zz = rz + (size_t)it * nq;
+    const cplx* ww = rw + (size_t)it * nq;
+    double z, f;
+    if (fun == 0) {
+      const double t = tvals[it];
+      const double tz = (j == 0) ? 0.0 : 1e-4 * pow(1e8, (double)(j - 1) / (kRuleSamples - 2));
+      z = tz / t;
+      f = exp(-tz);
+    } else {
+      z = lo * pow(hi / lo, (double)j / (kRuleSamples - 1));
+      f = 1.0 / sqrt(z);
+    }
+    cplx r = cmk(0.0, 0.0);
+    for (int l = 0; l < nq; ++l) r = cadd(r, cdiv(ww[l], csub(zz[l], cmk(z, 0.0))));
+    const double rv = (fun == 0) ? 2.0 * r.re : r.re;  // conjugate-half exp rule: twice the real part
+    err = fmax(err, (fun == 0) ? fabs(rv - f) : fabs(rv / f - 1.0));
+  }
+  for (int off = 32; off > 0; off >>= 1) err = fmax(err, __shfl_xor(err, off, 64));
+  if ((j & 63) == 0) red[j >> 6] = err;
+  __syncthreads();
+  if (j == 0) {
+    double e = 0.0;
+    for (int q = 0; q < kRuleSamples / 64; ++q) e = fmax(e, red[q]);
+    st->rule_err = e;
   }
 }
 
@@ -184,7 +219,7 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
     const int i = e % (m + 1), l = e / (m + 1);  // column-major output
     a.Tout[e] = (i < cols && l < cols && l >= i) ? Ts[i * ldT + l] : 0.0;
   }
-  for (int e = tid; e < 2 * nt * m; e += nthr) a.gbuf[e] = 0.0;  // restart sums of k_quad
+  for (int e = tid; e < nt * m; e += nthr) a.gbuf[e] = 0.0;  // rule sums of k_quad
   if (wv == 0) {  // s = T_m^{-1} t, column-oriented back substitution; lane i holds s_i
     double rhs = (!brk && lane < mm) ? Ts[lane * ldT + mm] : 0.0;
     double sl = 0.0;
@@ -479,53 +514,28 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a) {
   const cplx ps = a.psi[sidx];
   const cplx wp = cmul(a.rw[sidx], ps);
   {
-    // add alpha * w psi y into the coefficients of its rule and time point (twice the real part
-    // for the conjugate-half exp rules)
-    const int nq_tot = a.nq_main + a.nq_chk;
-    const int it = sidx / nq_tot, l = sidx % nq_tot, rule = (l >= a.nq_main) ? 1 : 0;
+    // add alpha * w psi y into the coefficients of its time point (twice the real part for the
+    // conjugate-half exp rule)
+    const int it = sidx / a.nq;
     const double fac = (a.fun == 0) ? 2.0 : 1.0;
-    if (lane < mm)
-      unsafeAtomicAdd(a.gbuf + (size_t)rule * a.nt * a.m + (size_t)it * a.m + lane,
-                      fac * st->alpha * cmul(wp, y).re);
+    if (lane < mm) unsafeAtomicAdd(a.gbuf + (size_t)it * a.m + lane, fac * st->alpha * cmul(wp, y).re);
   }
   const cplx ym = shfl_c(y, mm - 1);
   if (lane == 0) a.psi[sidx] = cscale(cmul(ps, ym), st->cpl);
 }
 
-// Pass coefficients C[:, t] (t < nt) from the main rule's sums, and the disagreement of the two
-// rules measured in the sketch-orthonormal coordinates, ||T_m (c_main - c_check)||.  The restart
-// column C[:, nt] was written by the whitening kernel.  One wavefront per time point.
+// Pass coefficients C[:, t] (t < nt) from the rule sums; the restart column C[:, nt] was written
+// by the whitening kernel.
 __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a) {
-  __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
-  State* st = a.st;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = kThreads / 64;
-  const int m = a.m, nt = a.nt;
-  const int mm = st->meff;
-  const int C_ld = m + 1, ldT = kMaxM + 1;
-  if (st->nonfinite || mm == 0) {
-    for (int i = tid; i < (m + 1) * (nt + 1); i += kThreads) a.C[i] = 0.0;
-    return;
+  const State* st = a.st;
+  const int m = a.m, nt = a.nt, mm = st->meff;
+  const bool zero = st->nonfinite || mm == 0;
+  for (int e = threadIdx.x; e < (m + 1) * nt; e += kThreads) {
+    const int i = e % (m + 1), it = e / (m + 1);
+    a.C[e] = (zero || i >= mm) ? 0.0 : a.gbuf[(size_t)it * m + i];
   }
-  for (int e = tid; e < mm * mm; e += kThreads) {
-    const int i = e % mm, l = e / mm;
-    Ts[i * ldT + l] = a.Tout[(size_t)l * (m + 1) + i];
-  }
-  __syncthreads();
-  for (int it = wv; it < nt; it += nwv) {
-    double* col = a.C + (size_t)it * C_ld;
-    const double cm = (lane < mm) ? a.gbuf[(size_t)it * m + lane] : 0.0;
-    const double cc = (lane < mm) ? a.gbuf[(size_t)nt * m + (size_t)it * m + lane] : 0.0;
-    const double dl = cm - cc;
-    double td = 0.0;  // (T_m (c_main - c_check))_lane
-    for (int l = 0; l < mm; ++l) {
-      const double dv = __shfl(dl, l, 64);
-      if (lane <= l && lane < mm) td += Ts[lane * ldT + l] * dv;
-    }
-    double q2 = td * td;
-    for (int off = 32; off > 0; off >>= 1) q2 += __shfl_xor(q2, off, 64);
-    if (lane == 0) st->qdis2[it] = q2;
-    for (int e = lane; e <= m; e += 64) col[e] = (e < mm) ? __shfl(cm, e & 63, 64) : 0.0;
-  }
+  if (zero)
+    for (int i = threadIdx.x; i <= m; i += kThreads) a.C[(size_t)nt * (m + 1) + i] = 0.0;
 }
 
 // ------------------------------------------------------------------------------ fused pass
@@ -602,16 +612,14 @@ __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, Sta
     st->ynorm2[it] = y2;
     st->xnorm2[it] = x2;
     const double e = (x2 > 0.0) ? sqrt(y2 / x2) : 0.0;
-    const double qq = (x2 > 0.0) ? sqrt(st->qdis2[it] / x2) : 0.0;
     est = fmax(est, e);
-    qd = fmax(qd, qq);
   }
+  qd = st->rule_err;
   for (int q = 0; q < kSlots * 2 * kMaxNt; ++q) norm_slots[q] = 0.0;
   st->est = est;
-  st->qdis_rel = qd;
   st->converged = (est <= tol) ? 1 : 0;
   rep->est = est;
-  rep->qdis_rel = qd;
+  rep->rule_err = qd;
   rep->alpha = st->alpha;
   rep->beta = st->beta;
   rep->brk = st->brk;
@@ -657,8 +665,10 @@ hipError_t launch_zero(hipStream_t s, double* p, size_t count) {
 }
 
 hipError_t launch_rule(hipStream_t s, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
-                       cplx* rz, cplx* rw, cplx* psi) {
+                       cplx* rz, cplx* rw, cplx* psi, State* st) {
   hipLaunchKernelGGL(k_rule, dim3(8), dim3(256), 0, s, fun, nt, tvals, n_main, lo, hi, rz, rw, psi);
+  const int nq = (fun == 0) ? n_main / 2 : n_main;
+  hipLaunchKernelGGL(k_rule_check, dim3(1), dim3(kRuleSamples), 0, s, fun, nt, tvals, nq, lo, hi, rz, rw, st);
   return hipGetLastError();
 }
 
@@ -703,7 +713,7 @@ hipError_t launch_small(hipStream_t s, const SmallArgs& a) {
     hipLaunchKernelGGL(k_whiten_mem, dim3(1), dim3(kWhitenThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nsys = a.nt * (a.nq_main + a.nq_chk);
+  const int nsys = a.nt * a.nq;
   hipLaunchKernelGGL(k_quad, dim3(nsys), dim3(64), quad_lds(a.m), s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

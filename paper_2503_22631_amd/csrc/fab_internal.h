@@ -11,7 +11,9 @@ constexpr int kSlots = 8;          // copies of each sketch accumulator (spreads
 constexpr int kMaxM = 64;          // largest cycle length
 constexpr int kMaxD = 2048;        // largest sketch dimension (LDS bins: 16 KB FP64)
 constexpr int kMaxNt = 16;         // largest number of time points per solve
-constexpr int kRuleMain = 128;     // default nodes of the main quadrature rule
+constexpr int kRuleMain = 128;     // default nodes of the quadrature rule
+constexpr int kRuleSamples = 256;  // sample points of the rule's accuracy check
+constexpr double kExpP = 3.0, kExpMu = 6.0, kExpL = 45.0;  // parabolic contour of the exp rule
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
 
 // ----------------------------------------------------------------------------------------------
@@ -109,20 +111,20 @@ struct State {
   double inv_rho, raw2;
   int meff, brk, nonfinite, step_lo;
   // per-cycle outputs read by the host
-  double ynorm2[kMaxNt], xnorm2[kMaxNt], qdis2[kMaxNt];
-  double est, qdis_rel;
+  double ynorm2[kMaxNt], xnorm2[kMaxNt];
+  double est, rule_err;
   int converged, pad0;
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
 struct Report {
-  double est, qdis_rel, alpha, beta;
+  double est, rule_err, alpha, beta;
   int brk, meff, nonfinite, converged;
 };
 
 // Arguments of the cycle-end kernel.
 struct SmallArgs {
-  int d, m, nt, plain, fun, nq_main, nq_chk, ldscr;
+  int d, m, nt, plain, fun, nq, ldscr;
   const double* U;
   double* Uq;       // d x (m+1) scratch for the Householder QR
   const double* R;  // (m+1) x m
@@ -132,8 +134,8 @@ struct SmallArgs {
   const cplx* rw;
   cplx* psi;
   cplx* scr;        // per-system restart contributions, entry i of system s at scr[s * ldscr + i]
-  double* gbuf;     // 2 x nt x m: main and check rule results
-  double* C;        // (m+1) x (nt+1) pass coefficients
+  double* gbuf;     // nt x m: the rule sums of the cycle (restart coefficients before k_combine)
+  double* C;        // (m+1) x (nt+1) pass coefficients (main rule), restart column last
   State* st;
 };
 
@@ -141,7 +143,7 @@ struct SmallArgs {
 struct Layout {
   size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
       scratch, report, total;
-  int nsys, nq_main, nq_chk, ldscr;
+  int nsys, nq, ldscr;
 };
 
 }  // namespace fab

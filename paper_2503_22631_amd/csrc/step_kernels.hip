@@ -52,12 +52,19 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 // Each block walks row tiles of kThreads rows (XCD-contiguous slabs).  The tile's nonzeros are
 // staged through LDS in chunks of kChunk with coalesced loads of values and column indices, then
 // every lane forms its own row (so stencil gathers of x stay coalesced across the wavefront).
-// The sketch of the row value is scattered into per-block LDS bins (value type), which are added
+// The sketch of the row value is scattered into per-block FP64 LDS bins, which are added
 // into one of kSlots global FP64 copies at the end.  The rows and signs of S are regenerated from
 // the counter-based specification for every row (no bytes of S are read): with the LDS-staged
 // product the generator's integer work overlaps the memory traffic.
+// Rows are summed in FP64 for FP32 data too: a stencil row's terms are ~|w|/h^2 while the row sum
+// of a smooth w is ~lambda_min |w|, so FP32 sums would lose log10(kappa) digits on exactly the
+// slowly converging components; products of FP32 values are exact in FP64, and only the stored z
+// is rounded to FP32.
+// The product z is stored non-temporally: the next reader is the window update, and the 256 MB
+// memory-side cache is better spent on the CSR arrays, which every step reads again.
 // ---------------------------------------------------------------------------------------------
 constexpr int kChunk = 2048;
+constexpr int kGather = 8;
 
 template <typename T, int MODE, int ZMAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
@@ -68,13 +75,13 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
                                                           double* __restrict__ slots,
                                                           const State* __restrict__ st) {
   extern __shared__ unsigned char smem_raw[];
-  const int bins_bytes = (MODE == 2) ? 0 : ((d * (int)sizeof(T) + 15) & ~15);
-  T* bins = reinterpret_cast<T*>(smem_raw);
+  const int bins_bytes = (MODE == 2) ? 0 : ((d * 8 + 15) & ~15);
+  double* bins = reinterpret_cast<double*>(smem_raw);
   T* sv = reinterpret_cast<T*>(smem_raw + bins_bytes);
   int* sc = reinterpret_cast<int*>(smem_raw + bins_bytes + kChunk * sizeof(T));
   if (st != nullptr && st->brk) return;
   if (MODE != 2) {
-    for (int i = threadIdx.x; i < d; i += kThreads) bins[i] = T(0);
+    for (int i = threadIdx.x; i < d; i += kThreads) bins[i] = 0.0;
     __syncthreads();
   }
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -90,25 +97,57 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
       const int rend = min(row0 + kThreads, n);
       const int p0 = rowptr[row0], p1 = rowptr[rend];
       const int my_lo = live ? rowptr[row] : 0, my_hi = live ? rowptr[row + 1] : 0;
-      T acc = T(0);
+      double acc = 0.0;  // FP64 row sums for either value type (see the note above)
       for (int cs = p0; cs < p1; cs += kChunk) {
         const int len = min(kChunk, p1 - cs);
         __syncthreads();  // the previous chunk has been consumed
-        for (int e = threadIdx.x; e < len; e += kThreads) {
-          sv[e] = vals[cs + e];
-          sc[e] = colind[cs + e];
+        // All loads of the chunk are issued before the first LDS write, so a tile waits for one
+        // memory round trip here rather than one per element.
+        T tv[kChunk / kThreads];
+        int tc[kChunk / kThreads];
+#pragma unroll
+        for (int q = 0; q < kChunk / kThreads; ++q) {
+          const int e = threadIdx.x + q * kThreads;
+          if (e < len) {
+            tv[q] = vals[cs + e];
+            tc[q] = colind[cs + e];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk / kThreads; ++q) {
+          const int e = threadIdx.x + q * kThreads;
+          if (e < len) {
+            sv[e] = tv[q];
+            sc[e] = tc[q];
+          }
         }
         __syncthreads();
+        // Row entries in groups of kGather: the gathers of x are all in flight together; the
+        // products are summed in entry order.
         const int lo = max(my_lo, cs), hi = min(my_hi, cs + len);
-        for (int p = lo; p < hi; ++p) acc = fma(sv[p - cs], x[sc[p - cs]], acc);
+        for (int pg = lo; pg < hi; pg += kGather) {
+          T av[kGather], xv[kGather];
+#pragma unroll
+          for (int q = 0; q < kGather; ++q) {
+            const int p = pg + q;
+            av[q] = T(0);
+            xv[q] = T(0);
+            if (p < hi) {
+              av[q] = sv[p - cs];
+              xv[q] = x[sc[p - cs]];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < kGather; ++q) acc = fma((double)av[q], (double)xv[q], acc);
+        }
       }
-      if (live) y[row] = acc;
-      z = acc;
+      z = (T)acc;
+      if (live) __builtin_nontemporal_store(z, &y[row]);
     } else if (live) {
       z = x[row];
     }
     if (MODE != 2 && live) {
-      const T zs = z * scale;
+      const double zs = (double)z * (double)scale;
       int rows[ZMAX];
       uint32_t sb;
       sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
@@ -121,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
     __syncthreads();
     double* slot = slots + (size_t)(blockIdx.x % kSlots) * d;
     for (int i = threadIdx.x; i < d; i += kThreads) {
-      const double v = (double)bins[i];
+      const double v = bins[i];
       if (v != 0.0) unsafeAtomicAdd(slot + i, v);
     }
   }
@@ -203,25 +242,28 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
 }
 
 // w_{j+1} = (z - sum_{i=lo..j} r_i w_i) / rho, in place on column j+1 of W (n x (m+1)).
-// KMAX bounds the window so the coefficients live in registers.
+// KMAX bounds the window so the coefficients live in registers.  Streaming loads and stores are
+// non-temporal (see the SpMV note on cache residency).
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict__ W,
                                                      const State* __restrict__ st) {
   if (st->brk) return;
   const int lo = st->step_lo, nw = j - lo + 1;
-  const T inv = (T)st->inv_rho;
-  T coef[KMAX];
+  // FP64 arithmetic for either value type: z is nearly in the span of the window, so the
+  // difference cancels; only the stored w_{j+1} is rounded to T.
+  const double inv = st->inv_rho;
+  double coef[KMAX];
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? (T)st->upd_coef[q] : T(0);
+  for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? st->upd_coef[q] : 0.0;
   T* out = W + (size_t)(j + 1) * n;
   const T* base = W + (size_t)lo * n;
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
-    T v = out[i];
+    double v = (double)__builtin_nontemporal_load(&out[i]);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (q < nw) v -= coef[q] * base[(size_t)q * n + i];
-    out[i] = v * inv;
+      if (q < nw) v -= coef[q] * (double)__builtin_nontemporal_load(&base[(size_t)q * n + i]);
+    __builtin_nontemporal_store((T)(v * inv), &out[i]);
   }
 }
 
@@ -342,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 // ------------------------------------------------------------------------------------ launchers
 size_t spmv_sketch_lds(int dtype, int mode, int d) {
   const size_t es = dtype == 0 ? 8 : 4;
-  const size_t bins = (mode == 2) ? 0 : ((d * es + 15) & ~(size_t)15);
+  const size_t bins = (mode == 2) ? 0 : ((d * 8 + 15) & ~(size_t)15);
   return bins + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
 }
 

@@ -5,7 +5,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 import workloads as wl
-from oracle import exact, krylov, sketch
+from oracle import exact, krylov, quadrature, sketch
 
 
 def _rand_nonsym(n, seed):
@@ -138,7 +138,7 @@ def test_laplacian_2d_64_closed_form():
     x, info = krylov.restart_solve(A.to_scipy(), b, "exp", 1e-3, m=20, k=2, S=S, tol=1e-10)
     assert info.status == "ok"
     assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
-    assert info.quad_disagreement < 1e-11
+    assert info.quad_rule_error < 1e-11
 
 
 @pytest.mark.parametrize("method", ["sketched", "plain"])
@@ -173,3 +173,46 @@ def test_unrestarted_arnoldi_matches_closed_form():
     ref = exact.sine_fab("exp", b, 30, [1, 1], t=1e-3)
     x = krylov.arnoldi_full(A.to_scipy(), b, 60, "exp", 1e-3)
     assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_fixed_rules_converge_to_the_same_result_at_high_condition_number():
+    """z^(-1/2) of a 3-D Laplacian shifted to condition number 2.6e4 (Section 4's quadrature-based
+    restart with the tan-substituted Stieltjes rule): increments grow transiently over the cycles,
+    yet the fixed rule r converges to r(A) b and the result meets the closed form; the main and check
+    rules agree on every cycle's projected matrix."""
+    N = 16
+    lmin0 = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2
+    lmax = 12 * (N + 1) ** 2
+    shift = lmax / 2.6e4 - lmin0
+    A = wl.shifted_laplacian_3d(N, shift)
+    b = wl.gaussian_vector(A.n, 0)
+    spec = (lmin0 + shift, lmax + shift)
+    S = sketch.sketch_matrix(A.n, 120, 8, seed=1)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "invsqrt", m=30, k=2, S=S, tol=1e-10, max_cycles=400,
+                                   spec=spec)
+    ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], shift)
+    assert info.status == "ok" and info.cycles > 50
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert info.quad_rule_error <= 1e-11
+
+
+def test_fixed_rule_iteration_converges_to_r_of_A():
+    """With a deliberately coarse rule r (6 nodes for z^(-1/2)), the restarted iteration converges
+    to r(A) b, not to f(A) b: x matches r(A) b from the eigendecomposition, and the gap to f(A) b
+    stays within the sampled rule error (the quantity the solver reports)."""
+    N = 10
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    b = wl.gaussian_vector(A.n, 4)
+    lo = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2 + 1.0
+    hi = 12 * (N + 1) ** 2 + 1.0
+    S = sketch.sketch_matrix(A.n, 60, 4, seed=2)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "invsqrt", m=20, k=3, S=S, tol=1e-14, max_cycles=200,
+                                   n_quad=6, spec=(lo, hi))
+    lam, Q = np.linalg.eigh(A.to_scipy().toarray())
+    zeta, w, _ = krylov.make_rule("invsqrt", n_quad=6, spec=(lo, hi))
+    r = quadrature.rational_scalar(zeta, w, lam).real
+    rA_b = Q @ (r * (Q.T @ b))
+    fA_b = Q @ ((Q.T @ b) / np.sqrt(lam))
+    assert np.linalg.norm(x - rA_b) <= 1e-11 * np.linalg.norm(rA_b)
+    gap = np.linalg.norm(rA_b - fA_b) / np.linalg.norm(fA_b)
+    assert 1e-8 < gap <= info.quad_rule_error

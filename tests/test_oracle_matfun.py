@@ -63,7 +63,8 @@ def _sector_points(n=400):
 def test_exp_rule_scalar_accuracy(t):
     s = _sector_points()
     z = -s / t
-    for (N, P, mu, L) in (quadrature.EXP_MAIN, quadrature.EXP_CHECK):
+    P, mu, L = quadrature.EXP_MAIN[1:]
+    for N in (quadrature.EXP_MAIN[0], 160):
         zeta, w = quadrature.exp_rule(t, N, P, mu, L)
         r = quadrature.rational_scalar(zeta, w, z)
         err = np.abs(r - np.exp(-t * z))
@@ -88,3 +89,20 @@ def test_invsqrt_rule_accuracy():
     for zz in (z, z * np.exp(0.5j)):
         r = quadrature.rational_scalar(zeta, w, zz)
         assert np.max(np.abs(r * np.sqrt(zz) - 1.0)) < 1e-14
+
+
+@pytest.mark.parametrize("fun,N,lo", [("exp", 128, None), ("exp", 24, None), ("invsqrt", 128, 0.5),
+                                       ("invsqrt", 12, 0.5)])
+def test_rule_error_tracks_node_count(fun, N, lo):
+    """rule_error is tiny for the default rules and large for coarse ones (the quantity the solver
+    compares with the tolerance)."""
+    if fun == "exp":
+        z, w = quadrature.conjugate_half(*quadrature.exp_rule(1e-3, N))
+        e = quadrature.rule_error("exp", z, w, True, t=1e-3)
+    else:
+        z, w = quadrature.invsqrt_rule(N, lo, 2e4)
+        e = quadrature.rule_error("invsqrt", z, w, False, spec=(lo, 2e4))
+    if N >= 128:
+        assert e < 1e-12
+    else:
+        assert e > 1e-6
