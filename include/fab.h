@@ -28,7 +28,8 @@
  *     h_info is filled (it synchronises the stream once per cycle).
  *   - Ownership: the caller owns and keeps alive A's arrays, b, x and the
  *     workspace (typically torch tensors).  The library owns fab_ctx and fab_op
- *     objects (and nothing else on the device).
+ *     objects, the arrays of operators made by fab_op_transpose, and an 8 KB
+ *     reduction buffer per context (fab_dot).
  *   - Thread safety: one context per host thread; calls on one context are
  *     serialised by the caller.
  */
@@ -105,6 +106,19 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
                           const int32_t* colind, const void* vals, int32_t dtype, fab_op** op);
 fab_status fab_op_destroy(fab_op* op);
 
+/* A^T as a new CSR operator whose arrays the library allocates and owns (freed
+ * by fab_op_destroy).  Rows of A^T are sorted by column index, so the result
+ * is canonical.  The adjoint of the method needs it: <c, f(A) b> = <f(A^T) c,
+ * b>, so d<c, f(tA) b>/db = f(tA^T) c, computed by fab_solve on A^T.  A's
+ * structure is checked on the device first (row pointers non-decreasing from 0
+ * to nnz, column indices in [0, n)).  Errors: FAB_E_INVALID (null arguments or
+ * a malformed CSR), FAB_E_HIP (allocation or launch failure). */
+fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT);
+
+/* Copy an operator's arrays (rowptr[n+1], colind[nnz], vals[nnz] in its dtype)
+ * into caller-provided device buffers (test hook for fab_op_transpose). */
+fab_status fab_op_copy_arrays(fab_ctx* ctx, const fab_op* A, int32_t* rowptr, int32_t* colind, void* vals);
+
 /* Bytes of device workspace fab_solve needs for nt time points. */
 fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, size_t* h_bytes);
 
@@ -150,6 +164,11 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on);
 fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
                            int64_t* h_loop_steps);
+
+/* out[0] = <x, y> for FP64 device vectors of length n, summed in a fixed order
+ * (reproducible bits).  Used for the time derivative of <c, exp(-tA) b>, which
+ * is -<c, A x> with x = exp(-tA) b.  out is device memory. */
+fab_status fab_dot(fab_ctx* ctx, int64_t n, const double* x, const double* y, double* out);
 
 const char* fab_status_string(fab_status s);
 

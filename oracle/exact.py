@@ -75,6 +75,28 @@ def kron_exp_fab(b: np.ndarray, factors, t: float, shift: float = 0.0, transpose
     return np.exp(-t * shift) * _mode_apply(E, np.asarray(b, dtype=np.float64), N)
 
 
+def kron_sum_apply(factors, x: np.ndarray, shift: float = 0.0) -> np.ndarray:
+    """A x for A = factors[0] (+) factors[1] (+) ... + shift I (each factor along its own axis)."""
+    N = factors[0].shape[0]
+    D = len(factors)
+    eye = np.eye(N)
+    y = shift * np.asarray(x, dtype=np.float64)
+    for d, F in enumerate(factors):
+        y = y + _mode_apply([F if e == d else eye for e in range(D)], x, N)
+    return y
+
+
+def exp_action_grads(factors, b: np.ndarray, c: np.ndarray, t: float, shift: float = 0.0):
+    """L = <c, exp(-t A) b> and its derivatives, from the adjoint identity <c, f(A) b> =
+    <f(A^T) c, b> (so dL/db = exp(-t A^T) c) and d/dt exp(-t A) = -A exp(-t A) (so
+    dL/dt = -<c, A exp(-t A) b>).  Returns (L, dL/db, dL/dt)."""
+    x = kron_exp_fab(b, factors, t, shift)
+    L = float(np.dot(c, x))
+    gb = kron_exp_fab(c, factors, t, shift, transpose=True)
+    gt = -float(np.dot(c, kron_sum_apply(factors, x, shift)))
+    return L, gb, gt
+
+
 def assemble_dense(factors, shift: float = 0.0) -> np.ndarray:
     """The dense Kronecker sum (tiny sizes only)."""
     N = factors[0].shape[0]

@@ -23,7 +23,8 @@ METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
 __all__ = ["Context", "CSROperator", "Params", "solve", "workspace_size", "spmv", "sketch_apply",
-           "sketch_table", "cycle_debug", "timing_enable", "timing_read", "FabError", "lib_path"]
+           "sketch_table", "cycle_debug", "dot", "ExpAction", "exp_action", "timing_enable", "timing_read",
+           "FabError", "lib_path"]
 
 
 def lib_path() -> str:
@@ -85,6 +86,26 @@ class CSROperator:
                                           _ptr(self.vals), DTYPE[self.dtype], ctypes.byref(h)),
                    "fab_csr_create", ok=(0,))
         self.handle = h
+
+    def transpose(self) -> "CSROperator":
+        """A^T on the device (fab_op_transpose); the library owns its arrays."""
+        h = ctypes.c_void_p()
+        _lib.check(self.ctx.lib.fab_op_transpose(self.ctx.handle, self.handle, ctypes.byref(h)),
+                   "fab_op_transpose", ok=(0,))
+        op = CSROperator.__new__(CSROperator)
+        op.ctx, op.rowptr, op.colind, op.vals = self.ctx, None, None, None
+        op.n, op.nnz, op.dtype, op.handle = self.n, self.nnz, self.dtype, h
+        return op
+
+    def arrays(self):
+        """Copies of the operator's (rowptr, colind, vals) as device tensors."""
+        dev = self.ctx.device
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        va = torch.empty(max(self.nnz, 1), dtype=self.dtype, device=dev)
+        _lib.check(self.ctx.lib.fab_op_copy_arrays(self.ctx.handle, self.handle, _ptr(rp), _ptr(ci), _ptr(va)),
+                   "fab_op_copy_arrays", ok=(0,))
+        return rp, ci[:self.nnz], va[:self.nnz]
 
     @classmethod
     def from_arrays(cls, ctx: Context, rowptr, colind, vals, dtype=None):
@@ -209,3 +230,58 @@ def cycle_debug(op: CSROperator, v: torch.Tensor, **kw):
     meff = int(scal[3])
     return {"W": W.t(), "U": U.t(), "R": R.t(), "T": T.t(), "Rt": X.t(), "alpha": scal[0], "beta": scal[1],
             "h": scal[2], "m": meff}
+
+
+def dot(ctx: Context, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """<x, y> of two FP64 device vectors (fab_dot), as a 0-d device tensor."""
+    assert x.dtype == torch.float64 and y.dtype == torch.float64 and x.numel() == y.numel()
+    out = torch.empty((), dtype=torch.float64, device=ctx.device)
+    _lib.check(ctx.lib.fab_dot(ctx.handle, x.numel(), _ptr(x.contiguous()), _ptr(y.contiguous()), _ptr(out)),
+               "fab_dot", ok=(0,))
+    return out
+
+
+class ExpAction(torch.autograd.Function):
+    """x = exp(-t A) b with gradients for b and t (FP64 operators).
+
+    Backward, for an upstream gradient c = dL/dx:
+      dL/db = exp(-t A^T) c   (adjoint identity <c, f(A) b> = <f(A^T) c, b>): the same restarted
+                              sketched Krylov solve, run on A^T, which recomputes its own basis;
+      dL/dt = -<c, A x>       (d/dt exp(-t A) b = -A exp(-t A) b): one product with A and a dot.
+    Nothing of the forward basis is stored; only x is kept.
+    """
+
+    @staticmethod
+    def forward(fctx, b, t, op, op_t, params):
+        tv = float(t)
+        x, info = solve(op, b, "exp", t=tv, params=params)
+        x = x[:, 0].contiguous()
+        fctx.save_for_backward(x)
+        fctx.op, fctx.op_t, fctx.params, fctx.tv = op, op_t, params, tv
+        fctx.t_shape = t.shape if isinstance(t, torch.Tensor) else None
+        fctx.t_device = t.device if isinstance(t, torch.Tensor) else None
+        return x
+
+    @staticmethod
+    def backward(fctx, gx):
+        (x,) = fctx.saved_tensors
+        gb = gt = None
+        gx = gx.contiguous()
+        if fctx.needs_input_grad[0]:
+            y, _ = solve(fctx.op_t, gx, "exp", t=fctx.tv, params=fctx.params)
+            gb = y[:, 0]
+        if fctx.needs_input_grad[1]:
+            ax = spmv(fctx.op, x)
+            g = -dot(fctx.op.ctx, gx, ax)
+            gt = g.to(fctx.t_device).reshape(fctx.t_shape)
+        return gb, gt, None, None, None
+
+
+def exp_action(op: CSROperator, b: torch.Tensor, t, op_t: CSROperator | None = None, **kw) -> torch.Tensor:
+    """Differentiable exp(-t A) b (see ExpAction); op_t defaults to op.transpose()."""
+    assert op.dtype == torch.float64, "the differentiable action is provided for FP64 operators"
+    if op_t is None:
+        op_t = op.transpose()
+    if not isinstance(t, torch.Tensor):
+        t = torch.tensor(float(t), dtype=torch.float64)
+    return ExpAction.apply(b, t, op, op_t, Params(**kw))

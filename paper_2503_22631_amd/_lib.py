@@ -14,9 +14,10 @@ STATUS = {
     -1: "FAB_E_INVALID", -2: "FAB_E_UNSUPPORTED", -3: "FAB_E_HIP", -4: "FAB_E_NONFINITE",
     -5: "FAB_E_DIVERGED", -6: "FAB_E_WORKSPACE",
 }
-EXPORTS = ["fab_create", "fab_destroy", "fab_csr_create", "fab_op_destroy", "fab_workspace_size",
-           "fab_solve", "fab_spmv", "fab_sketch_apply", "fab_sketch_table", "fab_cycle_debug",
-           "fab_timing_enable", "fab_timing_read", "fab_status_string", "fab_last_error"]
+EXPORTS = ["fab_create", "fab_destroy", "fab_csr_create", "fab_op_destroy", "fab_op_transpose",
+           "fab_op_copy_arrays", "fab_workspace_size", "fab_solve", "fab_spmv", "fab_sketch_apply",
+           "fab_sketch_table", "fab_cycle_debug", "fab_dot", "fab_timing_enable", "fab_timing_read",
+           "fab_status_string", "fab_last_error"]
 
 
 class fab_params(ctypes.Structure):
@@ -59,6 +60,9 @@ def load():
         "fab_destroy": ([c_void_p], c_int32),
         "fab_csr_create": ([c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_int32, P(c_void_p)], c_int32),
         "fab_op_destroy": ([c_void_p], c_int32),
+        "fab_op_transpose": ([c_void_p, c_void_p, P(c_void_p)], c_int32),
+        "fab_op_copy_arrays": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
+        "fab_dot": ([c_void_p, c_int64, c_void_p, c_void_p, c_void_p], c_int32),
         "fab_workspace_size": ([c_void_p, P(fab_params), c_int32, P(c_size_t)], c_int32),
         "fab_solve": ([c_void_p, c_void_p, c_int32, P(c_double), c_int32, c_void_p, c_void_p, P(fab_params),
                        c_void_p, c_size_t, P(fab_info)], c_int32),

@@ -47,7 +47,15 @@ hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, Sta
 hipError_t launch_reduce_slots(hipStream_t, int len, const double* slots, double* out);
 hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
                                int8_t* signs);
+hipError_t launch_dot(hipStream_t, int64_t n, const double* x, const double* y, double* part, int max_blocks,
+                      double* out);
+hipError_t launch_csr_validate(hipStream_t, int n, int nnz, const int* rowptr, const int* colind, int* flag);
+size_t transpose_scan_blocks(int64_t len);
+hipError_t launch_transpose(hipStream_t, int dtype, int n, int nnz, const int* rowptr, const int* colind,
+                            const void* vals, int* rowptrT, int* colT, void* valT, int* cursor, int* sums);
 }  // namespace fab
+
+constexpr int kDotBlocks = 1024;  // partial sums of fab_dot (fixed grid: reproducible bits)
 
 using namespace fab;
 
@@ -69,6 +77,7 @@ struct fab_ctx {
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   Report* h_rep = nullptr;
+  double* d_part = nullptr;  // kDotBlocks partial sums of fab_dot (device)
   double* h_t = nullptr;  // pinned staging for the time points
   int num_cu = 256;
   size_t lds_per_cu = 160 * 1024;
@@ -91,6 +100,7 @@ struct fab_op {
   const int32_t* colind;
   const void* vals;
   int dtype;
+  void* owned;  // device storage the library allocated for this operator (transposes), else null
 };
 
 constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which the solve is abandoned
@@ -349,8 +359,10 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
   if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&c->h_rep, sizeof(Report), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_t, sizeof(double) * kMaxNt, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->h_t, sizeof(double) * kMaxNt, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&c->d_part, sizeof(double) * kDotBlocks) != hipSuccess) {
     if (c->h_rep) (void)hipHostFree(c->h_rep);
+    if (c->h_t) (void)hipHostFree(c->h_t);
     if (c->work) (void)hipStreamDestroy(c->work);
     if (c->ev) (void)hipEventDestroy(c->ev);
     delete c;
@@ -369,6 +381,7 @@ fab_status fab_destroy(fab_ctx* c) {
   (void)hipEventDestroy(c->ev);
   (void)hipHostFree(c->h_rep);
   (void)hipHostFree(c->h_t);
+  (void)hipFree(c->d_part);
   delete c;
   return FAB_OK;
 }
@@ -379,7 +392,7 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
     return FAB_E_INVALID;
   if (dtype != FAB_F64 && dtype != FAB_F32) return FAB_E_INVALID;
   if (n >= ((int64_t)1 << 31)) return FAB_E_UNSUPPORTED;
-  fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype};
+  fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype, nullptr};
   if (!o) return FAB_E_HIP;
   *op = o;
   return FAB_OK;
@@ -387,7 +400,92 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
 
 fab_status fab_op_destroy(fab_op* op) {
   if (!op) return FAB_E_INVALID;
+  if (op->owned) (void)hipFree(op->owned);  // hipFree waits for the device
   delete op;
+  return FAB_OK;
+}
+
+fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT) {
+  if (!ctx || !A || !AT) return FAB_E_INVALID;
+  *AT = nullptr;
+  const int n = (int)A->n, nnz = (int)A->nnz;
+  const size_t es = A->dtype == 0 ? 8 : 4;
+  const size_t o_col = align_up(sizeof(int) * ((size_t)n + 1));
+  const size_t o_val = o_col + align_up(sizeof(int) * (size_t)std::max(nnz, 1));
+  const size_t total = o_val + align_up(es * (size_t)std::max(nnz, 1));
+  const size_t nb = transpose_scan_blocks((int64_t)n + 1);
+  const size_t t_cur = align_up(sizeof(int) * 64);  // flag at 0, cursor after it, then the scan sums
+  const size_t t_sums = t_cur + align_up(sizeof(int) * (size_t)n);
+  const size_t ttotal = t_sums + align_up(sizeof(int) * nb);
+  char* base = nullptr;
+  char* tmp = nullptr;
+  hipStream_t s = ctx->work;
+  int flag = 0;
+  auto fail = [&](hipError_t e, const char* what, int line) {
+    if (tmp) (void)hipFree(tmp);
+    if (base) (void)hipFree(base);
+    return hip_fail(e, what, line);
+  };
+#define FAB_TRYT(expr)                                               \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess) return fail(e_, #expr, __LINE__);          \
+  } while (0)
+  FAB_TRYT(hipMalloc((void**)&base, total));
+  FAB_TRYT(hipMalloc((void**)&tmp, ttotal));
+  int* rowptrT = (int*)base;
+  int* colT = (int*)(base + o_col);
+  void* valT = base + o_val;
+  int* dflag = (int*)tmp;
+  int* cursor = (int*)(tmp + t_cur);
+  int* sums = (int*)(tmp + t_sums);
+  FAB_TRYT(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRYT(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRYT(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  FAB_TRYT(launch_csr_validate(s, n, nnz, A->rowptr, A->colind, dflag));
+  FAB_TRYT(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FAB_TRYT(hipStreamSynchronize(s));
+  if (flag != 0) {  // every later step indexes with rowptr and colind
+    (void)hipFree(tmp);
+    (void)hipFree(base);
+    return FAB_E_INVALID;
+  }
+  FAB_TRYT(hipMemsetAsync(rowptrT, 0, sizeof(int) * ((size_t)n + 1), s));
+  FAB_TRYT(launch_transpose(s, A->dtype, n, nnz, A->rowptr, A->colind, A->vals, rowptrT, colT, valT, cursor, sums));
+  FAB_TRYT(hipStreamSynchronize(s));
+#undef FAB_TRYT
+  (void)hipFree(tmp);
+  fab_op* o = new (std::nothrow) fab_op{ctx, A->n, A->nnz, rowptrT, colT, valT, A->dtype, base};
+  if (!o) {
+    (void)hipFree(base);
+    return FAB_E_HIP;
+  }
+  *AT = o;
+  return FAB_OK;
+}
+
+fab_status fab_op_copy_arrays(fab_ctx* ctx, const fab_op* A, int32_t* rowptr, int32_t* colind, void* vals) {
+  if (!ctx || !A || !rowptr || (A->nnz > 0 && (!colind || !vals))) return FAB_E_INVALID;
+  const size_t es = A->dtype == 0 ? 8 : 4;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(hipMemcpyAsync(rowptr, A->rowptr, sizeof(int) * ((size_t)A->n + 1), hipMemcpyDeviceToDevice, s));
+  if (A->nnz > 0) {
+    FAB_TRY(hipMemcpyAsync(colind, A->colind, sizeof(int) * (size_t)A->nnz, hipMemcpyDeviceToDevice, s));
+    FAB_TRY(hipMemcpyAsync(vals, A->vals, es * (size_t)A->nnz, hipMemcpyDeviceToDevice, s));
+  }
+  FAB_TRY(hipStreamSynchronize(s));
+  return FAB_OK;
+}
+
+fab_status fab_dot(fab_ctx* ctx, int64_t n, const double* x, const double* y, double* out) {
+  if (!ctx || !x || !y || !out || n < 0) return FAB_E_INVALID;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(launch_dot(s, n, x, y, ctx->d_part, kDotBlocks, out));
+  FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }
 

@@ -655,6 +655,32 @@ __global__ void k_sketch_table(int64_t col0, int64_t count, int d, int zeta, uin
   }
 }
 
+// FP64 dot product <x, y> with a fixed summation order (per-block partials, then one block):
+// the same grid gives the same bits on every call.
+__global__ __launch_bounds__(kThreads) void k_dot_partial(int64_t n, const double* __restrict__ x,
+                                                          const double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double buf[kThreads / 64];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) acc = fma(x[i], y[i], acc);
+  acc = wave_sum_c(acc);
+  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) s += buf[q];
+    part[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_dot_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    *out = s;
+  }
+}
+
 // ------------------------------------------------------------------------------------ launchers
 hipError_t launch_zero(hipStream_t s, double* p, size_t count) {
   if (count == 0) return hipSuccess;
@@ -774,4 +800,13 @@ hipError_t launch_sketch_table(hipStream_t s, int64_t col0, int64_t count, int d
   return hipGetLastError();
 }
 
+hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* part, int max_blocks,
+                      double* out) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g > max_blocks) g = max_blocks;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_dot_partial, dim3((int)g), dim3(kThreads), 0, s, n, x, y, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (int)g, part, out);
+  return hipGetLastError();
+}
 }  // namespace fab

@@ -405,3 +405,131 @@ def test_fp32_invsqrt_256_full_size(fab, ctx):
     print(f"fp32 invsqrt 256^3: {info} rel err {err:.3e}", flush=True)
     assert info["status"] == "FAB_OK", info
     assert err <= FP32_FULL_TOL
+
+
+# ---------------------------------------------------- adjoint and differentiation (A^T, autograd)
+def _scipy_transpose(A):
+    T = A.to_scipy().T.tocsr()
+    T.sort_indices()
+    return T
+
+
+@pytest.mark.parametrize("build,dtype", [(lambda: wl.convdiff_3d(13, 20.0), torch.float64),
+                                         (lambda: wl.anisotropic_2d(41, 0.01), torch.float32)])
+def test_transpose_bit_exact(fab, ctx, build, dtype):
+    """A^T on the device equals scipy's transpose with sorted rows, index for index and bit for bit."""
+    A = build()
+    op = _op(fab, ctx, A, dtype)
+    rp, ci, va = op.transpose().arrays()
+    T = _scipy_transpose(A)
+    assert np.array_equal(rp.cpu().numpy(), T.indptr.astype(np.int32))
+    assert np.array_equal(ci.cpu().numpy(), T.indices.astype(np.int32))
+    ref = T.data.astype(np.float32 if dtype == torch.float32 else np.float64)
+    assert np.array_equal(va.cpu().numpy(), ref)
+
+
+def test_transpose_ragged_rows_and_bad_input(fab, ctx):
+    """Empty rows and columns, long rows, unsorted input columns; a malformed CSR is refused."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(11)
+    n = 3001
+    M = sp.random(n, n, density=0.002, random_state=rng, format="lil")
+    M[5, :] = 0
+    M[:, 7] = 0
+    M[9, :400] = rng.standard_normal(400)          # one long row
+    M = M.tocsr()
+    perm_rows = [np.random.default_rng(r).permutation(M.indptr[r + 1] - M.indptr[r]) for r in range(n)]
+    colind = np.concatenate([M.indices[M.indptr[r]:M.indptr[r + 1]][perm_rows[r]] for r in range(n)])
+    vals = np.concatenate([M.data[M.indptr[r]:M.indptr[r + 1]][perm_rows[r]] for r in range(n)])
+    op = fab.CSROperator.from_arrays(ctx, M.indptr, colind, vals)
+    rp, ci, va = op.transpose().arrays()
+    T = M.T.tocsr()
+    T.sort_indices()
+    assert np.array_equal(rp.cpu().numpy(), T.indptr)
+    assert np.array_equal(ci.cpu().numpy(), T.indices)
+    assert np.array_equal(va.cpu().numpy(), T.data)
+    bad = colind.copy()
+    bad[17] = n                                    # column out of range: caught by the device check
+    op_bad = fab.CSROperator.from_arrays(ctx, M.indptr, bad, vals)
+    with pytest.raises(fab.FabError):
+        op_bad.transpose()
+
+
+def test_adjoint_solve_vs_kronecker(fab, ctx):
+    """exp(-t A^T) c through the transposed operator against the transposed Kronecker form."""
+    N, t = 24, 1e-4
+    A = wl.convdiff_3d(N, 20.0)
+    op = _op(fab, ctx, A)
+    c = wl.gaussian_vector(A.n, 7)
+    y, info = fab.solve(op.transpose(), torch.as_tensor(c, device="cuda"), "exp", t=t, m=40, k=4, d=160, zeta=8,
+                        seed=1, tol=1e-10)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=20.0)
+    assert info["status"] == "FAB_OK", info
+    assert _rel(y[:, 0].cpu().numpy(), exact.kron_exp_fab(c, factors, t, transpose=True)) <= 1e-10
+
+
+def test_dot_is_reproducible(fab, ctx):
+    x = torch.as_tensor(wl.gaussian_vector(1_000_003, 1), device="cuda")
+    y = torch.as_tensor(wl.gaussian_vector(1_000_003, 2), device="cuda")
+    d1, d2 = fab.dot(ctx, x, y).item(), fab.dot(ctx, x, y).item()
+    ref = float(np.dot(x.cpu().numpy(), y.cpu().numpy()))
+    assert d1 == d2 and abs(d1 - ref) <= 1e-12 * np.linalg.norm(x.cpu().numpy()) * np.linalg.norm(y.cpu().numpy())
+
+
+def _grad_case(fab, ctx, N, kw, t=1e-4, peclet=20.0):
+    A = wl.convdiff_3d(N, peclet)
+    op = _op(fab, ctx, A)
+    op_t = op.transpose()
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 0), device="cuda").requires_grad_(True)
+    c = torch.as_tensor(wl.gaussian_vector(A.n, 7), device="cuda")
+    tt = torch.tensor(t, dtype=torch.float64, requires_grad=True)
+    x = fab.exp_action(op, b, tt, op_t=op_t, **kw)
+    L = torch.dot(c, x)
+    L.backward()
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=peclet)
+    Lo, gbo, gto = exact.exp_action_grads(factors, b.detach().cpu().numpy(), c.cpu().numpy(), t)
+    return op, op_t, b, c, tt, L, Lo, gbo, gto
+
+
+def _fd_checks(fab, op, b, c, t, gb, gt, kw):
+    """Central differences with h = 1e-6 along a unit direction (b) and h_t = 1e-6 t (t)."""
+    u = torch.as_tensor(wl.unit_direction(b.numel(), 3), device="cuda")
+    Lf = lambda bb, tv: float(torch.dot(c, fab.solve(op, bb, "exp", t=tv, **kw)[0][:, 0]))
+    bd = b.detach()
+    h = 1e-6
+    fd_b = (Lf(bd + h * u, t) - Lf(bd - h * u, t)) / (2 * h)
+    ht = 1e-6 * t
+    fd_t = (Lf(bd, t + ht) - Lf(bd, t - ht)) / (2 * ht)
+    gbu = float(torch.dot(gb, u))
+    return fd_b, gbu, fd_t, gt
+
+
+def test_exp_action_gradients_small(fab, ctx):
+    """Autograd of L = <c, exp(-t A) b> (96^3 settings on a 24^3 grid): gradients against the
+    oracle's adjoint-identity gradient and against central finite differences."""
+    kw = dict(m=40, k=4, d=160, zeta=8, seed=1, tol=1e-12)
+    op, op_t, b, c, tt, L, Lo, gbo, gto = _grad_case(fab, ctx, 24, kw)
+    assert abs(float(L) - Lo) <= 1e-11 * abs(Lo)
+    assert _rel(b.grad.cpu().numpy(), gbo) <= 1e-10
+    assert abs(float(tt.grad) - gto) <= 1e-10 * abs(gto)
+    fd_b, gbu, fd_t, gt = _fd_checks(fab, op, b, c, 1e-4, b.grad, float(tt.grad), kw)
+    assert abs(fd_b - gbu) <= 1e-5 * abs(gbu)
+    assert abs(fd_t - gt) <= 1e-6 * abs(gt)
+
+
+def test_exp_action_gradients_96_full_size(fab, ctx):
+    """The differentiation workload at full size: 96^3 convection-diffusion (Pe 20, n = 884,736),
+    t = 1e-4, forward m=40, k=4, d=160, tol 1e-10, adjoint on A^T; the whole gradient against the
+    oracle, and finite differences (h = 1e-6) for both derivatives."""
+    kw = dict(m=40, k=4, d=160, zeta=8, seed=1, tol=1e-10)
+    op, op_t, b, c, tt, L, Lo, gbo, gto = _grad_case(fab, ctx, 96, kw)
+    err_b = _rel(b.grad.cpu().numpy(), gbo)
+    err_t = abs(float(tt.grad) - gto) / abs(gto)
+    fd_b, gbu, fd_t, gt = _fd_checks(fab, op, b, c, 1e-4, b.grad, float(tt.grad), kw)
+    print(f"96^3 gradients: |db err| {err_b:.2e}  |dt err| {err_t:.2e}  FD b {abs(fd_b - gbu) / abs(gbu):.2e}  "
+          f"FD t {abs(fd_t - gt) / abs(gt):.2e}", flush=True)
+    assert abs(float(L) - Lo) <= 1e-10 * abs(Lo)
+    assert err_b <= 1e-9
+    assert err_t <= 1e-9
+    assert abs(fd_b - gbu) <= 1e-4 * abs(gbu)
+    assert abs(fd_t - gt) <= 1e-5 * abs(gt)

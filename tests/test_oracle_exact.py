@@ -68,3 +68,30 @@ def test_published_sizes():
     assert (wl.laplacian_2d(64).n, wl.laplacian_2d(64).nnz) == (4096, 20224)
     A = wl.convdiff_3d(96, 20.0)
     assert (A.n, A.nnz) == (884736, 6137856)
+
+
+def test_kron_sum_apply_matches_csr():
+    A = wl.convdiff_3d(7, 20.0)
+    factors, _ = exact.problem_factors("convdiff_3d", 7, peclet=20.0)
+    x = wl.gaussian_vector(A.n, 3)
+    assert np.allclose(exact.kron_sum_apply(factors, x), A.to_scipy() @ x, rtol=1e-13, atol=1e-9)
+
+
+def test_exp_action_grads_against_finite_differences():
+    """Gradient of L = <c, exp(-t A) b> (nonsymmetric convection-diffusion) against central
+    differences: exact in b (L is linear in b), O(h^2) in t."""
+    N, t = 8, 1e-3
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=20.0)
+    n = N ** 3
+    b, c = wl.gaussian_vector(n, 1), wl.gaussian_vector(n, 2)
+    L, gb, gt = exact.exp_action_grads(factors, b, c, t)
+    for seed in (5, 6):
+        u = wl.unit_direction(n, seed)
+        h = 1e-3
+        fd = (exact.exp_action_grads(factors, b + h * u, c, t)[0] - exact.exp_action_grads(factors, b - h * u, c, t)[0]) / (2 * h)
+        assert abs(fd - gb @ u) <= 1e-10 * max(abs(fd), 1.0)
+    ht = 1e-4 * t
+    fdt = (exact.exp_action_grads(factors, b, c, t + ht)[0] - exact.exp_action_grads(factors, b, c, t - ht)[0]) / (2 * ht)
+    assert abs(fdt - gt) <= 1e-7 * abs(gt)
+    # the adjoint differs from the forward operator for this nonsymmetric A
+    assert np.linalg.norm(gb - exact.kron_exp_fab(c, factors, t)) > 1e-3 * np.linalg.norm(gb)
