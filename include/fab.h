@@ -130,6 +130,22 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
                      const void* b, double* x, const fab_params* p, void* work, size_t work_bytes,
                      fab_info* h_info);
 
+/* Batched solves: nb right-hand sides sharing A (columns of b, b[r * ldb + i], A's dtype).
+ * x[(r * nt + i) * ldx + row] = f_i(A) b_r (FP64, overwritten).  Every member runs the
+ * method of fab_solve with the same parameters and its own basis, sketch (the same S), restart
+ * weights and stopping test; members that have finished are skipped by every kernel while the
+ * others continue.  The fused product + sketch kernel reads each CSR chunk once for a group of
+ * G members (G chosen once per operator and batch shape by timing 1, 2, 4, 8, 16 on the device).
+ * The whole cycle of all members is one captured graph.  h_info has nb entries; the return value
+ * is the most severe member status (errors before warnings before FAB_OK_BREAKDOWN before FAB_OK).
+ * 1 <= nb <= 1024; ldb, ldx >= n; FAB_PLAIN_RESTART is not batched (FAB_E_UNSUPPORTED).
+ * work: fab_workspace_size_batched bytes (nb copies of the single-solve workspace). */
+fab_status fab_workspace_size_batched(const fab_op* A, const fab_params* p, int32_t nt, int32_t nb,
+                                      size_t* h_bytes);
+fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt,
+                             int32_t nb, const void* b, int64_t ldb, double* x, int64_t ldx,
+                             const fab_params* p, void* work, size_t work_bytes, fab_info* h_info);
+
 /* ---- test hooks: the same kernels as fab_solve, exposed for parity tests ---- */
 
 /* y = A x (A's dtype for x and y). */

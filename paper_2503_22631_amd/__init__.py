@@ -22,7 +22,7 @@ FUN = {"exp": 0, "invsqrt": 1}
 METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
-__all__ = ["Context", "CSROperator", "Params", "solve", "workspace_size", "spmv", "sketch_apply",
+__all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "workspace_size", "spmv", "sketch_apply",
            "sketch_table", "cycle_debug", "dot", "ExpAction", "exp_action", "timing_enable", "timing_read",
            "FabError", "lib_path"]
 
@@ -172,6 +172,40 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update,
            "quad_rule_error": info.quad_rule_error}
     return x.view(nt, op.n).t(), out
+
+
+def _info_dict(info, code):
+    return {"status": _lib.STATUS.get(info.status, info.status), "code": int(code), "cycles": info.cycles,
+            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update, "quad_rule_error": info.quad_rule_error}
+
+
+def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None,
+                  check: bool = True, **kw):
+    """X[:, r, i] = f_i(A) B[:, r] for the nb columns of B (n x nb) in one batched solve.
+
+    Returns (X, infos): X of shape (n, nb, nt) (FP64, a view of the column-major result), and one
+    info dict per column.  Negative statuses raise FabError when ``check`` is true.
+    """
+    ctx = op.ctx
+    p = kw.pop("params", None) or Params(**kw)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    nt = len(ts)
+    assert B.is_cuda and B.dtype == op.dtype and B.dim() == 2 and B.shape[0] == op.n
+    nb = B.shape[1]
+    Bc = B.t().contiguous()                      # member r at Bc[r], leading dimension n
+    x = torch.empty((nb * nt, op.n), dtype=torch.float64, device=ctx.device)
+    nbytes = ctypes.c_size_t()
+    _lib.check(ctx.lib.fab_workspace_size_batched(op.handle, ctypes.byref(p), nt, nb, ctypes.byref(nbytes)),
+               "fab_workspace_size_batched", ok=(0,))
+    if work is None:
+        work = ctx.workspace(nbytes.value)
+    infos = (fab_info * nb)()
+    tarr = (ctypes.c_double * nt)(*ts.tolist())
+    st = ctx.lib.fab_solve_batched(ctx.handle, op.handle, FUN[fun], tarr, nt, nb, _ptr(Bc), op.n, _ptr(x), op.n,
+                                   ctypes.byref(p), _ptr(work), work.numel(), infos)
+    if check:
+        _lib.check(st, "fab_solve_batched")
+    return x.view(nb, nt, op.n).permute(2, 0, 1), [_info_dict(infos[r], st) for r in range(nb)]
 
 
 def timing_enable(ctx: Context, on: bool = True):

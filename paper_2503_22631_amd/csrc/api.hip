@@ -19,31 +19,35 @@
 namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* slots, const State* st);
-size_t spmv_sketch_lds(int dtype, int mode, int d);
+                              double* slots, const State* st, int nb, int G, size_t bs);
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G);
 hipError_t configure_cycle_kernels();
 hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
-                       double* R, State* st);
-hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st);
+                       double* R, State* st, int nb, size_t bs);
+hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
+                         size_t bs);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
                              double* slots_zero, double* norm_slots, int want_norm, double* R, State* st);
 hipError_t launch_plain_finish(hipStream_t, int j, int m, double* norm_slots, double* R, State* st);
 hipError_t launch_scale_col(hipStream_t, int dtype, int grid, int n, void* v, const double* s_ptr,
-                            const State* st);
+                            const State* st, int nb, size_t bs);
 hipError_t launch_zero(hipStream_t, double* p, size_t count);
+hipError_t launch_zero_strided(hipStream_t, double* p, size_t count, int reps, size_t step_bytes);
 hipError_t launch_rule(hipStream_t, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
-                       cplx* rz, cplx* rw, cplx* psi, State* st);
-hipError_t launch_copy_in(hipStream_t, int dtype, int grid, int n, const void* b, void* w0);
+                       cplx* rz, cplx* rw, cplx* psi, State* st, int nb, size_t bs);
+hipError_t launch_copy_in(hipStream_t, int dtype, int grid, int n, const void* b, int64_t ldb, void* w0, int nb,
+                          size_t bs);
 hipError_t launch_sqnorm(hipStream_t, int dtype, int grid, int n, const void* v, double* slots);
 hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_start, double* slots_step,
-                        size_t step_len, double* U, double* R, State* st);
+                        size_t step_len, double* U, double* R, State* st, int nb, size_t bs);
 
-hipError_t launch_small(hipStream_t, const SmallArgs& a);
+hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb);
 hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, const double* C, void* W, double* x,
-                       double* norm_slots, const State* st);
-hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep);
+                       int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs);
+hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
+                        size_t bs);
 hipError_t launch_reduce_slots(hipStream_t, int len, const double* slots, double* out);
 hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
                                int8_t* signs);
@@ -67,7 +71,9 @@ struct GraphKey {
   int m, k, d, zeta, nt, fun, method, nq, dtype;
   uint64_t seed;
   double tol;
-  int timing, pad;
+  int timing, nb, G, pad;
+  int64_t ldx;
+  size_t bs;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -90,6 +96,12 @@ struct fab_ctx {
     GraphKey key;
     hipGraphExec_t exec;
   };
+  struct Tuned {  // autotuned members per block of the fused kernel, per operator and batch shape
+    const void* op;
+    int64_t n;
+    int nb, d, zeta, dtype, G;
+  };
+  std::vector<Tuned> tuned;
   std::vector<Cached> graphs;
 };
 
@@ -102,8 +114,6 @@ struct fab_op {
   int dtype;
   void* owned;  // device storage the library allocated for this operator (transposes), else null
 };
-
-constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which the solve is abandoned
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -232,54 +242,64 @@ static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipE
 
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
 // Blocks of the fused SpMV + sketch kernel: as many as fit on the device at once (LDS-limited).
-static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d) {
-  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d), 1);
+static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1) {
+  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d, G), 1);
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, ctx->lds_per_cu / lds));
   return stream_grid(n, per_cu * ctx->num_cu);
 }
 
+// Batch geometry: nb members, each with a single-solve workspace bs bytes apart; the fused kernel
+// serves G members per block; member r's time points are columns r nt .. r nt + nt - 1 of x.
+struct Batch {
+  int nb = 1, G = 1;
+  size_t bs = 0;
+  int64_t ldx = 0;
+};
+
 static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op* A, const fab_params* p, int fun,
                                 int nt, const Layout& L, const Ptrs& q, double* x, Report* rep, bool with_pass,
-                                const std::vector<hipEvent_t>* tev) {
+                                const std::vector<hipEvent_t>* tev, const Batch& B) {
   const int n = (int)A->n, m = p->m, dt = A->dtype;
   const size_t es = dt == 0 ? 8 : 4;
   const bool plain = p->method == FAB_PLAIN_RESTART;
   const int d = plain ? 1 : p->d;
-  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d);
-  const int g_sk = spmv_grid(ctx, n, dt, 1, d);
+  const int nb = B.nb;
+  const size_t bs = B.bs;
+  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G);
+  const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * n * es; };
   if (!plain) {
     FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
-                               p->seed, q.slots_start, nullptr));
+                               p->seed, q.slots_start, q.st, nb, B.G, bs));
   } else {
     FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
   }
-  FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st));
-  FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st));
+  FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st, nb, bs));
+  FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st, nb, bs));
   for (int j = 0; j < m; ++j) {
     double* set_cur = q.slots_step + (size_t)(j & 1) * q.step_len;
     double* set_nxt = q.slots_step + (size_t)((j + 1) & 1) * q.step_len;
     if (!plain) {
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), d,
-                                 p->zeta, p->seed, set_cur, q.st));
+                                 p->zeta, p->seed, set_cur, q.st, nb, B.G, bs));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
-      FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st));
-      FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st));
+      FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
+      FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
     } else {
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), 1, 1, 0,
-                                 nullptr, q.st));
+                                 nullptr, q.st, 1, 1, 0));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set1, 0, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set1, set0, q.slots_start, 1, q.R, q.st));
       FAB_TRY(launch_plain_finish(s, j, m, q.slots_start, q.R, q.st));
-      FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(j + 1), &q.st->inv_rho, q.st));
+      FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(j + 1), &q.st->inv_rho, q.st, 1, 0));
     }
   }
   if (tev) FAB_TRY(record_timing_event((*tev)[2 * kMaxM], s));
@@ -303,10 +323,11 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.gbuf = q.gbuf;
   a.C = q.C;
   a.st = q.st;
-  FAB_TRY(launch_small(s, a));
+  a.bs = bs;
+  FAB_TRY(launch_small(s, a, nb));
   if (with_pass) {
-    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, q.slots_norm, q.st));
-    FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep));
+    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, B.ldx, q.slots_norm, q.st, nb, bs));
+    FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep, nb, bs));
   }
   return FAB_OK;
 }
@@ -358,7 +379,7 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
   }
   if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_rep, sizeof(Report), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_rep, sizeof(Report) * kMaxBatch, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_t, sizeof(double) * kMaxNt, hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&c->d_part, sizeof(double) * kDotBlocks) != hipSuccess) {
     if (c->h_rep) (void)hipHostFree(c->h_rep);
@@ -499,14 +520,80 @@ fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, 
   return FAB_OK;
 }
 
-fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, const void* b,
-                     double* x, const fab_params* p, void* work, size_t work_bytes, fab_info* h_info) {
-  info_init(h_info, FAB_E_INVALID);
+fab_status fab_workspace_size_batched(const fab_op* A, const fab_params* p, int32_t nt, int32_t nb, size_t* h_bytes) {
+  if (nb < 1 || nb > kMaxBatch) return FAB_E_INVALID;
+  size_t one = 0;
+  const fab_status st = fab_workspace_size(A, p, nt, &one);
+  if (st != FAB_OK) return st;
+  *h_bytes = (nb == 1) ? one : (size_t)nb * align_up(one);
+  return FAB_OK;
+}
+
+// Members per block of the fused SpMV + sketch kernel for a batch: each candidate is timed on the
+// batch's own operator and workspace (HIP events, 3 launches after 1 warm-up) and the fastest is
+// kept for this operator and batch shape.  Runs before the solve's set-up, which clears what the
+// timing launches wrote.
+static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p, int nb, const Ptrs& q, size_t bs,
+                             int* G_out) {
+  *G_out = 1;
+  if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
+  for (const auto& t : ctx->tuned)
+    if (t.op == A && t.n == A->n && t.nb == nb && t.d == p->d && t.zeta == p->zeta && t.dtype == A->dtype) {
+      *G_out = t.G;
+      return FAB_OK;
+    }
+  const int n = (int)A->n, dt = A->dtype, d = p->d;
+  const size_t es = dt == 0 ? 8 : 4;
+  hipStream_t s = ctx->work;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  FAB_TRY(hipEventCreate(&e0));
+  FAB_TRY(hipEventCreate(&e1));
+  int best = 1;
+  float best_ms = 1e30f;
+  hipError_t err = hipSuccess;
+  for (int G = 1; G <= 16 && G <= nb && err == hipSuccess; G *= 2) {
+    if (spmv_sketch_lds(dt, 0, d, G) > 64 * 1024) break;
+    const int grid = spmv_grid(ctx, n, dt, 0, d, G);
+    void* x0 = q.W;
+    void* y0 = (char*)q.W + (size_t)n * es;
+    for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+      if (rep == 1) err = hipEventRecord(e0, s);
+      if (err == hipSuccess)
+        err = launch_spmv_sketch(s, dt, 0, grid, n, A->rowptr, A->colind, A->vals, x0, y0, d, p->zeta, p->seed,
+                                 q.slots_step, nullptr, nb, G, bs);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = G;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(err, "tune_group", __LINE__);
+  ctx->tuned.push_back({A, A->n, nb, d, p->zeta, A->dtype, best});
+  *G_out = best;
+  return FAB_OK;
+}
+
+static int status_rank(fab_status s) { return s < 0 ? 100 - (int)s : (int)s; }  // errors above warnings
+
+// The restarted loop of Algorithm 2 for nb right-hand sides (columns of b, leading dimension ldb)
+// sharing A; member r's result for time point i is column r nt + i of x (leading dimension ldx).
+static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, int nb,
+                              const void* b, int64_t ldb, double* x, int64_t ldx, const fab_params* p, void* work,
+                              size_t work_bytes, fab_info* h_info) {
+  for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_INVALID);
   if (!ctx || !A || !b || !x || !p || !work) return FAB_E_INVALID;
+  if (nb < 1 || nb > kMaxBatch || ldb < A->n || ldx < A->n) return FAB_E_INVALID;
+  if (nb > 1 && p->method == FAB_PLAIN_RESTART) return FAB_E_UNSUPPORTED;
   if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
   fab_status ps = check_params(A, p, fun, nt);
   if (ps != FAB_OK) {
-    info_init(h_info, ps);
+    for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, ps);
     return ps;
   }
   if (fun == FAB_EXP_NEG)
@@ -514,25 +601,34 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
       if (!std::isfinite(h_t[i]) || !(h_t[i] > 0.0)) return FAB_E_INVALID;
   if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
   const Layout L = make_layout(A->n, A->dtype, p, fun, nt);
-  if (work_bytes < L.total) {
-    info_init(h_info, FAB_E_WORKSPACE);
+  const size_t bs = (nb == 1) ? 0 : align_up(L.total);
+  const size_t need = (nb == 1) ? L.total : (size_t)nb * bs;
+  if (work_bytes < need) {
+    for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_WORKSPACE);
     return FAB_E_WORKSPACE;
   }
-  info_init(h_info, FAB_E_HIP);
+  for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_HIP);
   const Ptrs q = carve(work, L, p, nt);
   hipStream_t s = ctx->work;
   const int n = (int)A->n;
   // order after the caller's stream
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  Batch B;
+  B.nb = nb;
+  B.bs = bs;
+  B.ldx = ldx;
+  const fab_status ts = tune_group(ctx, A, p, nb, q, bs, &B.G);
+  if (ts != FAB_OK) return ts;
   // solve set-up: zero accumulators, state and x; quadrature nodes; w_1 <- b
-  FAB_TRY(launch_zero(s, (double*)((char*)work + L.slots_step), (L.T - L.slots_step) / 8));
-  FAB_TRY(launch_zero(s, x, (size_t)n * nt));
+  FAB_TRY(launch_zero_strided(s, (double*)((char*)work + L.slots_step), (L.T - L.slots_step) / 8, nb, bs));
+  FAB_TRY(launch_zero_strided(s, x, (size_t)n, nb * nt, (size_t)ldx * 8));
   FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
   for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double) * nt, hipMemcpyHostToDevice, s));
-  FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi, q.st));
-  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, b, q.W));
+  FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi, q.st, nb,
+                      bs));
+  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, b, ldb, q.W, nb, bs));
 
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
@@ -551,13 +647,17 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
   key.dtype = A->dtype;
   key.seed = p->seed;
   key.tol = p->tol;
+  key.nb = nb;
+  key.G = B.G;
+  key.ldx = ldx;
+  key.bs = bs;
   hipGraphExec_t exec = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) exec = g.exec;
   if (!exec && !ctx->timing) {
     hipGraph_t graph;
     FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, nullptr);
+    fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, nullptr, B);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (es != FAB_OK) return es;
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture", __LINE__);
@@ -570,20 +670,45 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
     }
     ctx->graphs.push_back({key, exec});
   }
-  fab_status status = FAB_W_NOT_CONVERGED;
-  int cycles = 0, matvecs = 0;
-  double est = 0.0, rule_err = 0.0;
-  for (int c = 0; c < p->max_cycles; ++c) {
+  std::vector<fab_status> status(nb, FAB_W_NOT_CONVERGED);
+  std::vector<int> cycles(nb, 0), matvecs(nb, 0);
+  std::vector<char> finished(nb, 0);
+  std::vector<double> est(nb, 0.0), rule_err(nb, 0.0);
+  int remaining = nb;
+  for (int c = 0; c < p->max_cycles && remaining > 0; ++c) {
     if (ctx->timing) {
-      const fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, &ctx->tev);
+      const fab_status es = enqueue_cycle(ctx, s, A, p, fun, nt, L, q, x, ctx->h_rep, true, &ctx->tev, B);
       if (es != FAB_OK) return es;
     } else {
       FAB_TRY(hipGraphLaunch(exec, s));
     }
     FAB_TRY(hipStreamSynchronize(s));
-    const Report r = *ctx->h_rep;
+    int steps = 0;  // steps run this cycle: the longest among members still iterating
+    for (int r = 0; r < nb; ++r) {
+      if (finished[r]) continue;
+      const Report rr = ctx->h_rep[r];
+      if (!rr.nonfinite) steps = std::max(steps, rr.meff);
+      cycles[r] = c + 1;
+      matvecs[r] += rr.meff;
+      est[r] = rr.est;
+      rule_err[r] = std::max(rule_err[r], rr.rule_err);
+      if (rr.nonfinite) {
+        status[r] = FAB_E_NONFINITE;
+      } else if (rr.brk) {
+        status[r] = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
+      } else if (rr.converged) {
+        status[r] = FAB_OK;
+      } else if (!(rr.est <= kDivergedEst)) {
+        // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
+        // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
+        status[r] = FAB_E_DIVERGED;
+      } else {
+        continue;
+      }
+      finished[r] = 1;
+      --remaining;
+    }
     if (ctx->timing) {
-      const int steps = r.nonfinite ? 0 : r.meff;
       for (int j = 0; j < steps; ++j) {
         float ms = 0.f;
         FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[2 * j], ctx->tev[2 * j + 1]));
@@ -597,42 +722,38 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
         ctx->t_loop_n += steps;
       }
     }
-    cycles = c + 1;
-    matvecs += r.meff;
-    est = r.est;
-    rule_err = std::max(rule_err, r.rule_err);
-    if (r.nonfinite) {
-      status = FAB_E_NONFINITE;
-      break;
-    }
-    if (r.brk) {
-      status = FAB_OK_BREAKDOWN;
-      if (r.meff == 0 && c == 0) status = FAB_OK;  // b = 0: x = 0 exactly
-      break;
-    }
-    if (r.converged) {
-      status = FAB_OK;
-      break;
-    }
-    // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
-    // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
-    if (est > kDivergedEst) {
-      status = FAB_E_DIVERGED;
-      break;
+  }
+  fab_status worst = FAB_OK;
+  for (int r = 0; r < nb; ++r) {
+    // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
+    // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
+    if ((status[r] == FAB_OK || status[r] == FAB_OK_BREAKDOWN) && rule_err[r] > std::max(0.1 * p->tol, 1e-11))
+      status[r] = FAB_W_QUADRATURE;
+    if (status_rank(status[r]) > status_rank(worst)) worst = status[r];
+    if (h_info) {
+      h_info[r].status = status[r];
+      h_info[r].cycles = cycles[r];
+      h_info[r].matvecs = matvecs[r];
+      h_info[r].est_rel_update = est[r];
+      h_info[r].quad_rule_error = rule_err[r];
     }
   }
-  // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
-  // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
-  if ((status == FAB_OK || status == FAB_OK_BREAKDOWN) && rule_err > std::max(0.1 * p->tol, 1e-11))
-    status = FAB_W_QUADRATURE;
-  if (h_info) {
-    h_info->status = status;
-    h_info->cycles = cycles;
-    h_info->matvecs = matvecs;
-    h_info->est_rel_update = est;
-    h_info->quad_rule_error = rule_err;
+  return worst;
+}
+
+fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, const void* b,
+                     double* x, const fab_params* p, void* work, size_t work_bytes, fab_info* h_info) {
+  if (!A) {
+    info_init(h_info, FAB_E_INVALID);
+    return FAB_E_INVALID;
   }
-  return status;
+  return solve_batch(ctx, A, fun, h_t, nt, 1, b, A->n, x, A->n, p, work, work_bytes, h_info);
+}
+
+fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, int32_t nb,
+                             const void* b, int64_t ldb, double* x, int64_t ldx, const fab_params* p, void* work,
+                             size_t work_bytes, fab_info* h_info) {
+  return solve_batch(ctx, A, fun, h_t, nt, nb, b, ldb, x, ldx, p, work, work_bytes, h_info);
 }
 
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on) {
@@ -667,8 +788,8 @@ fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void*
   hipStream_t s = ctx->work;
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
-  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1), (int)A->n, A->rowptr, A->colind,
-                             A->vals, x, y, 1, 1, 0, nullptr, nullptr));
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1, 1), (int)A->n, A->rowptr, A->colind,
+                             A->vals, x, y, 1, 1, 0, nullptr, nullptr, 1, 1, 0));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }
@@ -685,7 +806,7 @@ fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, ui
   double* slots = (double*)work;
   FAB_TRY(launch_zero(s, slots, (size_t)kSlots * d));
   FAB_TRY(launch_spmv_sketch(s, dtype, 1, spmv_grid(ctx, n, dtype, 1, d), (int)n, nullptr, nullptr, nullptr, x,
-                             nullptr, d, zeta, seed, slots, nullptr));
+                             nullptr, d, zeta, seed, slots, nullptr, 1, 1, 0));
   FAB_TRY(launch_reduce_slots(s, d, slots, Sx));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
@@ -722,9 +843,10 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
   FAB_TRY(hipStreamSynchronize(s));
   ctx->h_t[0] = 1.0;
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double), hipMemcpyHostToDevice, s));
-  FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi, q.st));
-  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, q.W));
-  fab_status es2 = enqueue_cycle(ctx, s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false, nullptr);
+  FAB_TRY(launch_rule(s, FAB_EXP_NEG, 1, q.tvals, rule_nodes(FAB_EXP_NEG, p), 0.0, 0.0, q.rz, q.rw, q.psi, q.st, 1,
+                      0));
+  FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, n, q.W, 1, 0));
+  fab_status es2 = enqueue_cycle(ctx, s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false, nullptr, Batch{});
   if (es2 != FAB_OK) return es2;
   FAB_TRY(hipMemcpyAsync(W, q.W, (size_t)n * (m + 1) * es, hipMemcpyDeviceToDevice, s));
   if (!plain) FAB_TRY(hipMemcpyAsync(U, q.U, (size_t)d * (m + 1) * 8, hipMemcpyDeviceToDevice, s));

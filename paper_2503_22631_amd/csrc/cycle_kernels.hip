@@ -26,6 +26,13 @@ __global__ void k_zero(double* p, size_t count) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.0;
 }
 
+// count doubles at p + blockIdx.y * step_bytes, for every y (batch members, or columns of x).
+__global__ void k_zero_strided(double* p, size_t count, size_t step_bytes) {
+  p = bat(p, step_bytes);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.0;
+}
+
 // ------------------------------------------------------------------------------- quadrature rules
 // fun 0, exp(-t z): parabolic Hankel contour s(u) = P - mu u^2 + 2 i mu u, u in [-U, U],
 //   U = sqrt((P+L)/mu), N midpoint nodes; zeta = -s/t, w = -h s'(u) e^s / (2 pi i t).  Only the
@@ -35,7 +42,10 @@ __global__ void k_zero(double* p, size_t count) {
 //   (0, pi/2): zeta = -c^2 tan^2(theta), w = -(c/N) sec^2(theta), c = (lo hi)^(1/4).
 // Layout: nq nodes per time point (nq = N/2 for exp, N for z^(-1/2)).
 __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_main, double lo, double hi,
-                       cplx* __restrict__ rz, cplx* __restrict__ rw, cplx* __restrict__ psi) {
+                       cplx* __restrict__ rz, cplx* __restrict__ rw, cplx* __restrict__ psi, size_t bs) {
+  rz = bat(rz, bs);  // every batch member holds its own copy (psi is per member)
+  rw = bat(rw, bs);
+  psi = bat(psi, bs);
   const int nq = (fun == 0) ? n_main / 2 : n_main;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nt * nq; s += gridDim.x * blockDim.x) {
     const int it = s / nq, idx = s % nq;
@@ -77,7 +87,8 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
 __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, const double* __restrict__ tvals,
                                                              int nq, double lo, double hi,
                                                              const cplx* __restrict__ rz,
-                                                             const cplx* __restrict__ rw, State* __restrict__ st) {
+                                                             const cplx* __restrict__ rw, State* __restrict__ st,
+                                                             int nb, size_t bs) {
   __shared__ double red[kRuleSamples / 64];
   const int j = threadIdx.x;
   double err = 0.0;
@@ -105,12 +116,14 @@ __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, co
   if (j == 0) {
     double e = 0.0;
     for (int q = 0; q < kRuleSamples / 64; ++q) e = fmax(e, red[q]);
-    st->rule_err = e;
+    for (int r = 0; r < nb; ++r) bat(st, bs, r)->rule_err = e;
   }
 }
 
 template <typename T>
-__global__ void k_copy_in(int n, const T* __restrict__ b, T* __restrict__ w0) {
+__global__ void k_copy_in(int n, const T* __restrict__ b, int64_t ldb, T* __restrict__ w0, size_t bs) {
+  b += (int64_t)blockIdx.y * ldb;
+  w0 = bat(w0, bs);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += stride) w0[i] = b[i];
 }
@@ -139,9 +152,15 @@ __global__ __launch_bounds__(kThreads) void k_sqnorm(int n, const T* __restrict_
 __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, double* __restrict__ slots_start,
                                                     double* __restrict__ slots_step, size_t step_len,
                                                     double* __restrict__ U, double* __restrict__ R,
-                                                    State* __restrict__ st) {
+                                                    State* __restrict__ st, size_t bs) {
   __shared__ double part[kThreads / 64];
   __shared__ double s_alpha;
+  st = bat(st, bs);
+  if (st->done) return;
+  slots_start = bat(slots_start, bs);
+  slots_step = bat(slots_step, bs);
+  U = bat(U, bs);
+  R = bat(R, bs);
   double acc = 0.0;
   if (!plain) {
     for (int i = threadIdx.x; i < d; i += kThreads) {
@@ -211,7 +230,7 @@ __device__ __forceinline__ double sum8(double v) {  // over the 8 lanes of a col
 // after a barrier): T to global, s = T_m^{-1} t, Rt, the restart column of the pass coefficients,
 // and the scalars of the restart recursion.
 __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int mm, int brk, double* s_lds) {
-  State* st = a.st;
+  State* st = a.st;  // a: this member's arguments (already offset)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m = a.m, nt = a.nt, nthr = blockDim.x;
   const int cols = brk ? mm : mm + 1;
@@ -259,14 +278,16 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
 // the column is published in LDS (double-buffered), and every owner updates its own column in
 // registers: one barrier per column.
 template <int KR>
-__global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a) {
+__global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a0) {
   __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
   __shared__ double vcol[2][8 * KR];
   __shared__ double rfs[2][2];
   __shared__ double diagR[kMaxM + 1];
   __shared__ double tail2[kMaxM + 2];
   __shared__ double s_lds[kMaxM];
+  const SmallArgs a = member_args(a0);
   State* st = a.st;
+  if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = a.d;
   const int mm = st->meff;
@@ -362,13 +383,15 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a) {
 
 // Whitening QR for large d (> 512): the same column-parallel Householder QR with the basis in
 // global scratch (U copied to a.Uq).
-__global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a) {
+__global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a0) {
   __shared__ double Ts[(kMaxM + 1) * (kMaxM + 1)];
   __shared__ double rfs[2][2];
   __shared__ double diagR[kMaxM + 1];
   __shared__ double tail2[kMaxM + 2];
   __shared__ double s_lds[kMaxM];
+  const SmallArgs a = member_args(a0);
   State* st = a.st;
+  if (st->done) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = a.d;
   const int mm = st->meff;
@@ -460,11 +483,12 @@ __device__ __forceinline__ cplx crecip(cplx b) {
   return cplx{b.re * s, -b.im * s};
 }
 
-__global__ __launch_bounds__(64) void k_quad(SmallArgs a) {
+__global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
   extern __shared__ unsigned char smq[];
+  const SmallArgs a = member_args(a0);
   const State* st = a.st;
   const int mm = st->meff;
-  if (st->nonfinite || mm == 0) return;
+  if (st->done || st->nonfinite || mm == 0) return;
   const int ld = mm + 1;
   double* Xs = reinterpret_cast<double*>(smq);
   cplx* Us = reinterpret_cast<cplx*>(smq + (((size_t)mm * ld * 8 + 15) & ~(size_t)15));
@@ -526,8 +550,10 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a) {
 
 // Pass coefficients C[:, t] (t < nt) from the rule sums; the restart column C[:, nt] was written
 // by the whitening kernel.
-__global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a) {
+__global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a0) {
+  const SmallArgs a = member_args(a0);
   const State* st = a.st;
+  if (st->done) return;
   const int m = a.m, nt = a.nt, mm = st->meff;
   const bool zero = st->nonfinite || mm == 0;
   for (int e = threadIdx.x; e < (m + 1) * nt; e += kThreads) {
@@ -543,12 +569,18 @@ __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a) {
 // partial norms ||y_t||^2, ||x_t||^2 (added into kSlots copies).
 template <typename T, int NT>
 __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const double* __restrict__ C,
-                                                   T* __restrict__ W, double* __restrict__ x,
-                                                   double* __restrict__ norm_slots, const State* __restrict__ st) {
+                                                   T* __restrict__ W, double* __restrict__ x, int64_t ldx,
+                                                   double* __restrict__ norm_slots, const State* __restrict__ st,
+                                                   size_t bs) {
   __shared__ double Cs[(kMaxM + 1) * (NT + 1)];
   __shared__ double part[kThreads / 64][2 * NT];
+  st = bat(st, bs);
   const int mm = st->meff;
-  if (st->nonfinite || mm == 0) return;
+  if (st->done || st->nonfinite || mm == 0) return;
+  C = bat(C, bs);
+  W = bat(W, bs);
+  norm_slots = bat(norm_slots, bs);
+  x += (int64_t)blockIdx.y * nt * ldx;  // member r's time points are columns r nt .. r nt + nt - 1
   const int brk = st->brk;
   const int ncol = brk ? mm : mm + 1;
   for (int e = threadIdx.x; e < (m + 1) * (nt + 1); e += kThreads) {
@@ -572,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       if (q < nt) {
-        double* xp = x + (size_t)q * n + i;
+        double* xp = x + (size_t)q * ldx + i;
         const double xv = *xp + acc[q];
         *xp = xv;
         yn[q] += acc[q] * acc[q];
@@ -600,8 +632,15 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
 
 // Convergence test after the pass (Algorithm 2 stopping rule, relative form).
 __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, State* __restrict__ st,
-                        Report* __restrict__ rep) {
+                        Report* __restrict__ rep, size_t bs) {
   if (threadIdx.x != 0) return;
+  st = bat(st, bs);
+  norm_slots = bat(norm_slots, bs);
+  rep += blockIdx.y;
+  if (st->done) {  // finished in an earlier cycle: report unchanged
+    rep->done = 1;
+    return;
+  }
   double est = 0.0, qd = 0.0;
   for (int it = 0; it < nt; ++it) {
     double y2 = 0.0, x2 = 0.0;
@@ -626,6 +665,8 @@ __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, Sta
   rep->meff = st->meff;
   rep->nonfinite = st->nonfinite;
   rep->converged = st->converged;
+  st->done = (st->converged || st->brk || st->nonfinite || !(est <= kDivergedEst)) ? 1 : 0;
+  rep->done = st->done;
 }
 
 // Sum of the slot copies: out[i] = sum_c slots[c*len + i] (sketch test hook).
@@ -682,6 +723,14 @@ __global__ void k_dot_final(int nb, const double* __restrict__ part, double* __r
 }
 
 // ------------------------------------------------------------------------------------ launchers
+hipError_t launch_zero_strided(hipStream_t s, double* p, size_t count, int reps, size_t step_bytes) {
+  if (count == 0 || reps == 0) return hipSuccess;
+  int grid = (int)((count + 255) / 256);
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(k_zero_strided, dim3(grid, reps), dim3(256), 0, s, p, count, step_bytes);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(hipStream_t s, double* p, size_t count) {
   if (count == 0) return hipSuccess;
   int grid = (int)((count + 255) / 256);
@@ -691,18 +740,21 @@ hipError_t launch_zero(hipStream_t s, double* p, size_t count) {
 }
 
 hipError_t launch_rule(hipStream_t s, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
-                       cplx* rz, cplx* rw, cplx* psi, State* st) {
-  hipLaunchKernelGGL(k_rule, dim3(8), dim3(256), 0, s, fun, nt, tvals, n_main, lo, hi, rz, rw, psi);
+                       cplx* rz, cplx* rw, cplx* psi, State* st, int nb, size_t bs) {
+  hipLaunchKernelGGL(k_rule, dim3(8, nb), dim3(256), 0, s, fun, nt, tvals, n_main, lo, hi, rz, rw, psi, bs);
   const int nq = (fun == 0) ? n_main / 2 : n_main;
-  hipLaunchKernelGGL(k_rule_check, dim3(1), dim3(kRuleSamples), 0, s, fun, nt, tvals, nq, lo, hi, rz, rw, st);
+  hipLaunchKernelGGL(k_rule_check, dim3(1), dim3(kRuleSamples), 0, s, fun, nt, tvals, nq, lo, hi, rz, rw, st, nb,
+                     bs);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_in(hipStream_t s, int dtype, int grid, int n, const void* b, void* w0) {
+hipError_t launch_copy_in(hipStream_t s, int dtype, int grid, int n, const void* b, int64_t ldb, void* w0, int nb,
+                          size_t bs) {
+  const dim3 g(grid, nb);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_copy_in<double>, dim3(grid), dim3(256), 0, s, n, (const double*)b, (double*)w0);
+    hipLaunchKernelGGL(k_copy_in<double>, g, dim3(256), 0, s, n, (const double*)b, ldb, (double*)w0, bs);
   else
-    hipLaunchKernelGGL(k_copy_in<float>, dim3(grid), dim3(256), 0, s, n, (const float*)b, (float*)w0);
+    hipLaunchKernelGGL(k_copy_in<float>, g, dim3(256), 0, s, n, (const float*)b, ldb, (float*)w0, bs);
   return hipGetLastError();
 }
 
@@ -715,9 +767,9 @@ hipError_t launch_sqnorm(hipStream_t s, int dtype, int grid, int n, const void* 
 }
 
 hipError_t launch_start(hipStream_t s, int d, int m, int plain, double* slots_start, double* slots_step,
-                        size_t step_len, double* U, double* R, State* st) {
-  hipLaunchKernelGGL(k_start, dim3(1), dim3(kThreads), 0, s, d, m, plain, slots_start, slots_step, step_len, U, R,
-                     st);
+                        size_t step_len, double* U, double* R, State* st, int nb, size_t bs) {
+  hipLaunchKernelGGL(k_start, dim3(1, nb), dim3(kThreads), 0, s, d, m, plain, slots_start, slots_step, step_len, U,
+                     R, st, bs);
   return hipGetLastError();
 }
 
@@ -728,51 +780,57 @@ hipError_t configure_cycle_kernels() {
                              (int)quad_lds(kMaxM));
 }
 
-hipError_t launch_small(hipStream_t s, const SmallArgs& a) {
+// The cycle end of every batch member (a.bs apart): whitening, quadrature, coefficients.
+hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb) {
+  const dim3 g1(1, nb);
   if (a.plain || a.d <= 64)
-    hipLaunchKernelGGL(k_whiten<8>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+    hipLaunchKernelGGL(k_whiten<8>, g1, dim3(kWhitenThreads), 0, s, a);
   else if (a.d <= 256)
-    hipLaunchKernelGGL(k_whiten<32>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+    hipLaunchKernelGGL(k_whiten<32>, g1, dim3(kWhitenThreads), 0, s, a);
   else if (a.d <= 512)
-    hipLaunchKernelGGL(k_whiten<64>, dim3(1), dim3(kWhitenThreads), 0, s, a);
+    hipLaunchKernelGGL(k_whiten<64>, g1, dim3(kWhitenThreads), 0, s, a);
   else
-    hipLaunchKernelGGL(k_whiten_mem, dim3(1), dim3(kWhitenThreads), 0, s, a);
+    hipLaunchKernelGGL(k_whiten_mem, g1, dim3(kWhitenThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nsys = a.nt * a.nq;
-  hipLaunchKernelGGL(k_quad, dim3(nsys), dim3(64), quad_lds(a.m), s, a);
+  hipLaunchKernelGGL(k_quad, dim3(nsys, nb), dim3(64), quad_lds(a.m), s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_combine, dim3(1), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_combine, g1, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
 static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, const double* C, T* W, double* x,
-                          double* ns, const State* st) {
+                          int64_t ldx, double* ns, const State* st, int nb, size_t bs) {
+  const dim3 g(grid, nb);
+#define FAB_P(NTV) hipLaunchKernelGGL((k_pass<T, NTV>), g, dim3(kThreads), 0, s, n, m, nt, C, W, x, ldx, ns, st, bs)
   if (nt <= 1)
-    hipLaunchKernelGGL((k_pass<T, 1>), dim3(grid), dim3(kThreads), 0, s, n, m, nt, C, W, x, ns, st);
+    FAB_P(1);
   else if (nt <= 2)
-    hipLaunchKernelGGL((k_pass<T, 2>), dim3(grid), dim3(kThreads), 0, s, n, m, nt, C, W, x, ns, st);
+    FAB_P(2);
   else if (nt <= 4)
-    hipLaunchKernelGGL((k_pass<T, 4>), dim3(grid), dim3(kThreads), 0, s, n, m, nt, C, W, x, ns, st);
+    FAB_P(4);
   else if (nt <= 8)
-    hipLaunchKernelGGL((k_pass<T, 8>), dim3(grid), dim3(kThreads), 0, s, n, m, nt, C, W, x, ns, st);
+    FAB_P(8);
   else
-    hipLaunchKernelGGL((k_pass<T, 16>), dim3(grid), dim3(kThreads), 0, s, n, m, nt, C, W, x, ns, st);
+    FAB_P(16);
+#undef FAB_P
 }
 
 hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt, const double* C, void* W,
-                       double* x, double* norm_slots, const State* st) {
+                       double* x, int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs) {
   if (dtype == 0)
-    launch_pass_t<double>(s, grid, n, m, nt, C, (double*)W, x, norm_slots, st);
+    launch_pass_t<double>(s, grid, n, m, nt, C, (double*)W, x, ldx, norm_slots, st, nb, bs);
   else
-    launch_pass_t<float>(s, grid, n, m, nt, C, (float*)W, x, norm_slots, st);
+    launch_pass_t<float>(s, grid, n, m, nt, C, (float*)W, x, ldx, norm_slots, st, nb, bs);
   return hipGetLastError();
 }
 
-hipError_t launch_final(hipStream_t s, int nt, double tol, double* norm_slots, State* st, Report* rep) {
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, nt, tol, norm_slots, st, rep);
+hipError_t launch_final(hipStream_t s, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
+                        size_t bs) {
+  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, tol, norm_slots, st, rep, bs);
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ constexpr int kRuleMain = 128;     // default nodes of the quadrature rule
 constexpr int kRuleSamples = 256;  // sample points of the rule's accuracy check
 constexpr double kExpP = 3.0, kExpMu = 6.0, kExpL = 45.0;  // parabolic contour of the exp rule
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kMaxBatch = 1024;    // largest number of right-hand sides per batched solve
+constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which a member's solve is abandoned
 
 // ----------------------------------------------------------------------------------------------
 // Sparse-sign sketch specification (eq. sparse_sign_sketch): column j of S has zeta distinct
@@ -113,14 +115,25 @@ struct State {
   // per-cycle outputs read by the host
   double ynorm2[kMaxNt], xnorm2[kMaxNt];
   double est, rule_err;
-  int converged, pad0;
+  int converged, done;  // done: converged, broken down or non-finite; every kernel skips the member
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
 struct Report {
   double est, rule_err, alpha, beta;
-  int brk, meff, nonfinite, converged;
+  int brk, meff, nonfinite, converged, done, pad;
 };
+
+// Batched solves: member r of a batch owns a copy of the single-solve workspace at byte offset
+// r * bs; kernels launched with gridDim.y = members shift their workspace pointers with bat().
+template <typename P>
+__device__ __forceinline__ P* bat(P* p, size_t bs, int r) {
+  return reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)r * bs);
+}
+template <typename P>
+__device__ __forceinline__ P* bat(P* p, size_t bs) {
+  return bat(p, bs, (int)blockIdx.y);
+}
 
 // Arguments of the cycle-end kernel.
 struct SmallArgs {
@@ -137,7 +150,26 @@ struct SmallArgs {
   double* gbuf;     // nt x m: the rule sums of the cycle (restart coefficients before k_combine)
   double* C;        // (m+1) x (nt+1) pass coefficients (main rule), restart column last
   State* st;
+  size_t bs;        // batch stride in bytes (member blockIdx.y works at byte offset blockIdx.y * bs)
 };
+
+__device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
+  SmallArgs a = a0;
+  const size_t bs = a0.bs;
+  a.U = bat(a0.U, bs);
+  a.Uq = bat(a0.Uq, bs);
+  a.R = bat(a0.R, bs);
+  a.Tout = bat(a0.Tout, bs);
+  a.Xout = bat(a0.Xout, bs);
+  a.rz = bat(a0.rz, bs);
+  a.rw = bat(a0.rw, bs);
+  a.psi = bat(a0.psi, bs);
+  a.scr = bat(a0.scr, bs);
+  a.gbuf = bat(a0.gbuf, bs);
+  a.C = bat(a0.C, bs);
+  a.st = bat(a0.st, bs);
+  return a;
+}
 
 // Workspace carving, shared by the driver and workspace_size().
 struct Layout {

@@ -66,6 +66,57 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 constexpr int kChunk = 2048;
 constexpr int kGather = 8;
 
+// Stage nonzeros [cs, cs+len) of the tile into LDS (values and column indices).  All loads are
+// issued before the first LDS write, so the tile waits for one memory round trip rather than one
+// per element.  Barriers on both sides (the previous chunk has been consumed; this one is ready).
+template <typename T>
+__device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const int* __restrict__ colind, int cs,
+                                            int len, T* sv, int* sc) {
+  __syncthreads();
+  T tv[kChunk / kThreads];
+  int tc[kChunk / kThreads];
+#pragma unroll
+  for (int q = 0; q < kChunk / kThreads; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    if (e < len) {
+      tv[q] = vals[cs + e];
+      tc[q] = colind[cs + e];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kChunk / kThreads; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    if (e < len) {
+      sv[e] = tv[q];
+      sc[e] = tc[q];
+    }
+  }
+  __syncthreads();
+}
+
+// acc + sum of the row's entries [lo, hi) (LDS positions relative to cs) times x, in entry order,
+// kGather gathers of x in flight at a time.
+template <typename T>
+__device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* __restrict__ x, int lo, int hi, int cs,
+                                          double acc) {
+  for (int pg = lo; pg < hi; pg += kGather) {
+    T av[kGather], xv[kGather];
+#pragma unroll
+    for (int q = 0; q < kGather; ++q) {
+      const int p = pg + q;
+      av[q] = T(0);
+      xv[q] = T(0);
+      if (p < hi) {
+        av[q] = sv[p - cs];
+        xv[q] = x[sc[p - cs]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kGather; ++q) acc = fma((double)av[q], (double)xv[q], acc);
+  }
+  return acc;
+}
+
 template <typename T, int MODE, int ZMAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
@@ -73,15 +124,24 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           int d, int zeta, T scale, uint32_t k0, uint32_t k1,
                                                           double* __restrict__ slots,
-                                                          const State* __restrict__ st) {
+                                                          const State* __restrict__ st, int nb, int G, size_t bs) {
   extern __shared__ unsigned char smem_raw[];
-  const int bins_bytes = (MODE == 2) ? 0 : ((d * 8 + 15) & ~15);
+  // This block serves batch members r0 .. r0+gn-1 (one member for single solves): the CSR chunk is
+  // staged once and applied to every member's vector, and the rows of S are generated once per row.
+  const int r0 = blockIdx.y * G;
+  const int gn = min(G, nb - r0);
+  const int bins_bytes = (MODE == 2) ? 0 : ((G * d * 8 + 15) & ~15);
   double* bins = reinterpret_cast<double*>(smem_raw);
   T* sv = reinterpret_cast<T*>(smem_raw + bins_bytes);
   int* sc = reinterpret_cast<int*>(smem_raw + bins_bytes + kChunk * sizeof(T));
-  if (st != nullptr && st->brk) return;
+  uint32_t live_mask = 0;  // members still iterating (block-uniform)
+  for (int g = 0; g < gn; ++g) {
+    const State* sg = st ? bat(st, bs, r0 + g) : nullptr;
+    if (!sg || !(sg->brk || sg->done)) live_mask |= 1u << g;
+  }
+  if (live_mask == 0) return;
   if (MODE != 2) {
-    for (int i = threadIdx.x; i < d; i += kThreads) bins[i] = 0.0;
+    for (int i = threadIdx.x; i < gn * d; i += kThreads) bins[i] = 0.0;
     __syncthreads();
   }
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -92,76 +152,56 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
     const int row0 = tile * kThreads;
     const int row = row0 + threadIdx.x;
     const bool live = row < n;
-    T z = T(0);
+    int p0 = 0, p1 = 0, my_lo = 0, my_hi = 0;
+    bool one_chunk = true;
     if (MODE != 1) {
       const int rend = min(row0 + kThreads, n);
-      const int p0 = rowptr[row0], p1 = rowptr[rend];
-      const int my_lo = live ? rowptr[row] : 0, my_hi = live ? rowptr[row + 1] : 0;
-      double acc = 0.0;  // FP64 row sums for either value type (see the note above)
-      for (int cs = p0; cs < p1; cs += kChunk) {
-        const int len = min(kChunk, p1 - cs);
-        __syncthreads();  // the previous chunk has been consumed
-        // All loads of the chunk are issued before the first LDS write, so a tile waits for one
-        // memory round trip here rather than one per element.
-        T tv[kChunk / kThreads];
-        int tc[kChunk / kThreads];
-#pragma unroll
-        for (int q = 0; q < kChunk / kThreads; ++q) {
-          const int e = threadIdx.x + q * kThreads;
-          if (e < len) {
-            tv[q] = vals[cs + e];
-            tc[q] = colind[cs + e];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < kChunk / kThreads; ++q) {
-          const int e = threadIdx.x + q * kThreads;
-          if (e < len) {
-            sv[e] = tv[q];
-            sc[e] = tc[q];
-          }
-        }
-        __syncthreads();
-        // Row entries in groups of kGather: the gathers of x are all in flight together; the
-        // products are summed in entry order.
-        const int lo = max(my_lo, cs), hi = min(my_hi, cs + len);
-        for (int pg = lo; pg < hi; pg += kGather) {
-          T av[kGather], xv[kGather];
-#pragma unroll
-          for (int q = 0; q < kGather; ++q) {
-            const int p = pg + q;
-            av[q] = T(0);
-            xv[q] = T(0);
-            if (p < hi) {
-              av[q] = sv[p - cs];
-              xv[q] = x[sc[p - cs]];
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < kGather; ++q) acc = fma((double)av[q], (double)xv[q], acc);
-        }
-      }
-      z = (T)acc;
-      if (live) __builtin_nontemporal_store(z, &y[row]);
-    } else if (live) {
-      z = x[row];
+      p0 = rowptr[row0];
+      p1 = rowptr[rend];
+      my_lo = live ? rowptr[row] : 0;
+      my_hi = live ? rowptr[row + 1] : 0;
+      one_chunk = (p1 - p0) <= kChunk;
+      if (one_chunk) stage_chunk(vals, colind, p0, p1 - p0, sv, sc);
     }
-    if (MODE != 2 && live) {
-      const double zs = (double)z * (double)scale;
-      int rows[ZMAX];
-      uint32_t sb;
-      sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+    int rows[ZMAX];
+    uint32_t sb = 0;
+    if (MODE != 2 && live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+    for (int g = 0; g < gn; ++g) {
+      if (!((live_mask >> g) & 1u)) continue;  // uniform over the block
+      const T* xg = bat(x, bs, r0 + g);
+      T z = T(0);
+      if (MODE != 1) {
+        double acc = 0.0;  // FP64 row sums for either value type (see the note above)
+        if (one_chunk) {
+          acc = row_dot(sv, sc, xg, my_lo, my_hi, p0, acc);
+        } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
+          for (int cs = p0; cs < p1; cs += kChunk) {
+            const int len = min(kChunk, p1 - cs);
+            stage_chunk(vals, colind, cs, len, sv, sc);
+            acc = row_dot(sv, sc, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
+          }
+        }
+        z = (T)acc;
+        if (live) __builtin_nontemporal_store(z, bat(y, bs, r0 + g) + row);
+      } else if (live) {
+        z = xg[row];
+      }
+      if (MODE != 2 && live) {
+        const double zs = (double)z * (double)scale;
+        double* bg = bins + g * d;
 #pragma unroll
-      for (int l = 0; l < ZMAX; ++l)
-        if (l < zeta) unsafeAtomicAdd(&bins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+        for (int l = 0; l < ZMAX; ++l)
+          if (l < zeta) unsafeAtomicAdd(&bg[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+      }
     }
   }
   if (MODE != 2) {
     __syncthreads();
-    double* slot = slots + (size_t)(blockIdx.x % kSlots) * d;
-    for (int i = threadIdx.x; i < d; i += kThreads) {
+    for (int i = threadIdx.x; i < gn * d; i += kThreads) {
+      const int g = i / d, e = i - g * d;
       const double v = bins[i];
-      if (v != 0.0) unsafeAtomicAdd(slot + i, v);
+      if (v != 0.0 && ((live_mask >> g) & 1u))
+        unsafeAtomicAdd(bat(slots, bs, r0 + g) + (size_t)(blockIdx.x % kSlots) * d + e, v);
     }
   }
 }
@@ -175,8 +215,13 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
 template <int PER>
 __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ slots_cur,
                                              double* __restrict__ slots_next, double* __restrict__ U,
-                                             double* __restrict__ R, State* __restrict__ st) {
-  if (st->brk) return;
+                                             double* __restrict__ R, State* __restrict__ st, size_t bs) {
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  slots_cur = bat(slots_cur, bs);
+  slots_next = bat(slots_next, bs);
+  U = bat(U, bs);
+  R = bat(R, bs);
   const int lane = threadIdx.x;
   const int lo = max(0, j - k + 1);
   double u[PER];
@@ -246,8 +291,10 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
 // non-temporal (see the SpMV note on cache residency).
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict__ W,
-                                                     const State* __restrict__ st) {
-  if (st->brk) return;
+                                                     const State* __restrict__ st, size_t bs) {
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  W = bat(W, bs);
   const int lo = st->step_lo, nw = j - lo + 1;
   // FP64 arithmetic for either value type: z is nearly in the span of the window, so the
   // difference cancels; only the stored w_{j+1} is rounded to T.
@@ -374,30 +421,34 @@ __global__ void k_plain_finish(int j, int m, double* __restrict__ norm_slots, do
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v, const double* __restrict__ s_ptr,
-                                                        const State* __restrict__ st) {
-  if (st->brk) return;
+                                                        const State* __restrict__ st, size_t bs) {
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  v = bat(v, bs);
+  s_ptr = bat(s_ptr, bs);
   const T s = (T)(*s_ptr);
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) v[i] *= s;
 }
 
 // ------------------------------------------------------------------------------------ launchers
-size_t spmv_sketch_lds(int dtype, int mode, int d) {
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G) {
   const size_t es = dtype == 0 ? 8 : 4;
-  const size_t bins = (mode == 2) ? 0 : ((d * 8 + 15) & ~(size_t)15);
+  const size_t bins = (mode == 2) ? 0 : (((size_t)G * d * 8 + 15) & ~(size_t)15);
   return bins + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
 }
 
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
                                        const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
-                                       double* slots, const State* st) {
+                                       double* slots, const State* st, int nb, int G, size_t bs) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
-  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d);
-#define FAB_L(M, Z)                                                                                   \
-  hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), dim3(grid), dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, \
-                     zeta, scale, k0, k1, slots, st)
+  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G);
+  const dim3 g2(grid, (nb + G - 1) / G);
+#define FAB_L(M, Z)                                                                                              \
+  hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, scale, k0, \
+                     k1, slots, st, nb, G, bs)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -424,46 +475,49 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* slots, const State* st) {
+                              double* slots, const State* st, int nb, int G, size_t bs) {
   if (dtype == 0)
     return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, (const double*)va, (const double*)x,
-                                        (double*)y, d, zeta, seed, slots, st);
+                                        (double*)y, d, zeta, seed, slots, st, nb, G, bs);
   return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, (const float*)va, (const float*)x, (float*)y, d,
-                                     zeta, seed, slots, st);
+                                     zeta, seed, slots, st, nb, G, bs);
 }
 
 hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* cur, double* next, double* U,
-                       double* R, State* st) {
+                       double* R, State* st, int nb, size_t bs) {
+  const dim3 g(1, nb);
   if (d <= 256)
-    hipLaunchKernelGGL(k_orth<4>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+    hipLaunchKernelGGL(k_orth<4>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
   else if (d <= 512)
-    hipLaunchKernelGGL(k_orth<8>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+    hipLaunchKernelGGL(k_orth<8>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
   else if (d <= 1024)
-    hipLaunchKernelGGL(k_orth<16>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+    hipLaunchKernelGGL(k_orth<16>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
   else
-    hipLaunchKernelGGL(k_orth<32>, dim3(1), dim3(64), 0, s, j, k, m, d, cur, next, U, R, st);
+    hipLaunchKernelGGL(k_orth<32>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
   return hipGetLastError();
 }
 
 template <typename T>
-static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st) {
+static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st, int nb, size_t bs) {
+  const dim3 g(grid, nb);
   if (k <= 4)
-    hipLaunchKernelGGL((k_update<T, 4>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+    hipLaunchKernelGGL((k_update<T, 4>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else if (k <= 8)
-    hipLaunchKernelGGL((k_update<T, 8>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+    hipLaunchKernelGGL((k_update<T, 8>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else if (k <= 16)
-    hipLaunchKernelGGL((k_update<T, 16>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+    hipLaunchKernelGGL((k_update<T, 16>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else if (k <= 32)
-    hipLaunchKernelGGL((k_update<T, 32>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+    hipLaunchKernelGGL((k_update<T, 32>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else
-    hipLaunchKernelGGL((k_update<T, 64>), dim3(grid), dim3(kThreads), 0, s, n, j, W, st);
+    hipLaunchKernelGGL((k_update<T, 64>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
 }
 
-hipError_t launch_update(hipStream_t s, int dtype, int grid, int n, int j, int k, void* W, const State* st) {
+hipError_t launch_update(hipStream_t s, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
+                         size_t bs) {
   if (dtype == 0)
-    launch_update_t<double>(s, grid, n, j, k, (double*)W, st);
+    launch_update_t<double>(s, grid, n, j, k, (double*)W, st, nb, bs);
   else
-    launch_update_t<float>(s, grid, n, j, k, (float*)W, st);
+    launch_update_t<float>(s, grid, n, j, k, (float*)W, st, nb, bs);
   return hipGetLastError();
 }
 
@@ -495,11 +549,12 @@ hipError_t launch_plain_finish(hipStream_t s, int j, int m, double* norm_slots, 
 }
 
 hipError_t launch_scale_col(hipStream_t s, int dtype, int grid, int n, void* v, const double* s_ptr,
-                            const State* st) {
+                            const State* st, int nb, size_t bs) {
+  const dim3 g(grid, nb);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_scale_col<double>, dim3(grid), dim3(kThreads), 0, s, n, (double*)v, s_ptr, st);
+    hipLaunchKernelGGL(k_scale_col<double>, g, dim3(kThreads), 0, s, n, (double*)v, s_ptr, st, bs);
   else
-    hipLaunchKernelGGL(k_scale_col<float>, dim3(grid), dim3(kThreads), 0, s, n, (float*)v, s_ptr, st);
+    hipLaunchKernelGGL(k_scale_col<float>, g, dim3(kThreads), 0, s, n, (float*)v, s_ptr, st, bs);
   return hipGetLastError();
 }
 

@@ -360,6 +360,11 @@ FP32_TOL = 2e-6   # FP32 values and basis (FP64 row sums, bins and cycle end; x 
 # FP32 rounding of the basis perturbs the transient of the restarted iteration (measured
 # 3.7e-6 .. 1.6e-5 over seven runs).  Bar: 30 tol.
 FP32_FULL_TOL = 3e-5
+# Batched anisotropic FP32 workload (1024^2, t up to 1e-3, t lambda_max ~ 4e3, ~30 cycles): FP32
+# rounding of each cycle's basis sets a floor that a tighter tol does not move (measured, worst of
+# sampled members: 3e-7 at t = 1e-5 rising to 2.5e-5 at t = 1e-3, at tol 1e-6 and 1e-7 alike; FP64
+# at the same settings: 3.6e-7 at tol 1e-6, 7.6e-9 at tol 1e-7).  Bar: twice the floor.
+FP32_BATCH_TOL = 5e-5
 
 
 def test_fp32_exp_anisotropic(fab, ctx):
@@ -533,3 +538,91 @@ def test_exp_action_gradients_96_full_size(fab, ctx):
     assert err_t <= 1e-9
     assert abs(fd_b - gbu) <= 1e-4 * abs(gbu)
     assert abs(fd_t - gt) <= 1e-5 * abs(gt)
+
+
+# --------------------------------------------------------------- batched right-hand sides
+CFG4_T = [10.0 ** (-5 + 2 * i / 7) for i in range(8)]   # 8 time points, log-spaced in [1e-5, 1e-3]
+
+
+def test_batched_matches_single_solves(fab, ctx):
+    """Five right-hand sides in one batched solve against five single solves (same S) and the
+    closed form, three time points each."""
+    N = 48
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A)
+    nb, ts = 5, [1e-4, 5e-4, 1e-3]
+    Bm = np.stack([wl.gaussian_vector(A.n, 100 + r) for r in range(nb)], axis=1)
+    kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=100)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=ts, **kw)
+    assert X.shape == (A.n, nb, len(ts))
+    for r in range(nb):
+        assert infos[r]["status"] == "FAB_OK", (r, infos[r])
+        xs, info_s = fab.solve(op, torch.as_tensor(Bm[:, r], device="cuda"), "exp", t=ts, **kw)
+        assert infos[r]["cycles"] == info_s["cycles"]
+        for i, t in enumerate(ts):
+            xb = X[:, r, i].cpu().numpy()
+            assert _rel(xb, xs[:, i].cpu().numpy()) <= 1e-12
+            assert _rel(xb, exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)) <= 1e-9
+
+
+def test_batched_members_finish_differently(fab, ctx):
+    """One batch holding a zero right-hand side (exact at once), an eigenvector (breakdown after one
+    step) and random vectors (several cycles): per-member statuses and results."""
+    N = 32
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    Phi, _ = exact.sine_basis(N)
+    eig = np.kron(Phi[:, 2], Phi[:, 1])
+    Bm = np.stack([wl.gaussian_vector(A.n, 1), np.zeros(A.n), eig, wl.gaussian_vector(A.n, 2)], axis=1)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=1e-3, m=20, k=2, d=80, zeta=8,
+                                 seed=1, tol=1e-10)
+    assert [i["status"] for i in infos] == ["FAB_OK", "FAB_OK", "FAB_OK_BREAKDOWN", "FAB_OK"], infos
+    assert infos[1]["cycles"] == 1 and infos[2]["cycles"] == 1 and infos[0]["cycles"] > 1
+    for r in range(4):
+        ref = exact.sine_fab("exp", Bm[:, r], N, [1, 1], 0.0, t=1e-3)
+        got = X[:, r, 0].cpu().numpy()
+        if r == 1:
+            assert not np.any(got)
+        else:
+            assert _rel(got, ref) <= 1e-9
+
+
+def test_batched_fp32_anisotropic_eight_times(fab, ctx):
+    """The batched workload's shape on a small grid: FP32 anisotropic operator, 8 right-hand sides
+    x 8 log-spaced time points, m=20, k=2, d=80, tol 1e-6."""
+    N = 64
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A, torch.float32)
+    nb = 8
+    Bm = np.stack([wl.gaussian_vector(A.n, 200 + r) for r in range(nb)], axis=1)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, dtype=torch.float32, device="cuda"), "exp", t=CFG4_T,
+                                 m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6, max_cycles=200)
+    for r in range(nb):
+        assert infos[r]["status"] == "FAB_OK", infos[r]
+        for i, t in enumerate(CFG4_T):
+            ref = exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)
+            assert _rel(X[:, r, i].cpu().numpy(), ref) <= FP32_TOL, (r, t)
+
+
+def test_batched_1024_full_size(fab, ctx):
+    """The batched workload at full size: anisotropic 1024^2 operator (n = 1,048,576) in FP32, 64
+    right-hand sides x 8 time points in one batched solve; four sampled members against the
+    closed form on every time point (the oracle cannot afford all 512 results in seconds), every
+    member's status and finiteness checked."""
+    N, nb = 1024, 64
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A, torch.float32)
+    Bm = np.stack([wl.gaussian_vector(A.n, 300 + r) for r in range(nb)], axis=1).astype(np.float32)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=CFG4_T, m=20, k=2, d=80, zeta=8,
+                                 seed=1, tol=1e-6, max_cycles=200)
+    assert all(i["status"] == "FAB_OK" for i in infos), [i["status"] for i in infos]
+    assert bool(torch.isfinite(X).all())
+    worst = 0.0
+    for r in (0, 21, 42, 63):
+        b64 = Bm[:, r].astype(np.float64)
+        for i, t in enumerate(CFG4_T):
+            ref = exact.sine_fab("exp", b64, N, [1.0, 0.01], 0.0, t=t)
+            worst = max(worst, _rel(X[:, r, i].cpu().numpy(), ref))
+    print(f"batched 1024^2 x 64 x 8: cycles {max(i['cycles'] for i in infos)} worst sampled rel err {worst:.2e}",
+          flush=True)
+    assert worst <= FP32_BATCH_TOL
