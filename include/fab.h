@@ -79,7 +79,7 @@ typedef struct {
   int32_t status;          /* fab_status of the solve                               */
   int32_t cycles;          /* restart cycles run                                    */
   int32_t matvecs;         /* products with A                                       */
-  int32_t reserved;
+  int32_t group;           /* members per block of the fused product + sketch kernel */
   double est_rel_update;   /* max_t ||y_t|| / ||x_t|| of the last cycle             */
   double quad_rule_error;  /* error of the partial-fraction rule r against f over   *
                             * the spectral region, max over 256 samples and t: exp: *

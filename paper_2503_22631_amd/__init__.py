@@ -176,7 +176,8 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
 
 def _info_dict(info, code):
     return {"status": _lib.STATUS.get(info.status, info.status), "code": int(code), "cycles": info.cycles,
-            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update, "quad_rule_error": info.quad_rule_error}
+            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update, "quad_rule_error": info.quad_rule_error,
+            "group": info.group}
 
 
 def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None,

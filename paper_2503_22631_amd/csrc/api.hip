@@ -20,7 +20,7 @@ namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st, int nb, int G, size_t bs);
-size_t spmv_sketch_lds(int dtype, int mode, int d, int G);
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta);
 hipError_t configure_cycle_kernels();
 hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
                        double* R, State* st, int nb, size_t bs);
@@ -242,8 +242,8 @@ static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipE
 
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
 // Blocks of the fused SpMV + sketch kernel: as many as fit on the device at once (LDS-limited).
-static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1) {
-  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d, G), 1);
+static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1, int zeta = 1) {
+  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d, G, zeta), 1);
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, ctx->lds_per_cu / lds));
   return stream_grid(n, per_cu * ctx->num_cu);
 }
@@ -265,8 +265,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const int d = plain ? 1 : p->d;
   const int nb = B.nb;
   const size_t bs = B.bs;
-  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G);
-  const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G);
+  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta);
+  const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * n * es; };
   if (!plain) {
@@ -552,8 +552,8 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   float best_ms = 1e30f;
   hipError_t err = hipSuccess;
   for (int G = 1; G <= 16 && G <= nb && err == hipSuccess; G *= 2) {
-    if (spmv_sketch_lds(dt, 0, d, G) > 64 * 1024) break;
-    const int grid = spmv_grid(ctx, n, dt, 0, d, G);
+    if (spmv_sketch_lds(dt, 0, d, G, p->zeta) > 64 * 1024) break;
+    const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta);
     void* x0 = q.W;
     void* y0 = (char*)q.W + (size_t)n * es;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
@@ -736,6 +736,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
       h_info[r].matvecs = matvecs[r];
       h_info[r].est_rel_update = est[r];
       h_info[r].quad_rule_error = rule_err[r];
+      h_info[r].group = B.G;
     }
   }
   return worst;

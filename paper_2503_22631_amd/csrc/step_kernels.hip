@@ -117,6 +117,17 @@ __device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* _
   return acc;
 }
 
+// LDS layout of the fused kernel: bins (G*d FP64), then for member groups (G > 1) the tile's
+// products (kThreads*G values) and generated S entries (kThreads*zeta rows as uint16, kThreads sign
+// words), then the CSR chunk (kChunk values and column indices).
+__host__ __device__ inline size_t spmv_lds_bins(int mode, int d, int G) {
+  return (mode == 2) ? 0 : (((size_t)G * d * 8 + 15) & ~(size_t)15);
+}
+__host__ __device__ inline size_t spmv_lds_group(int mode, int G, int zeta, size_t es) {
+  if (mode == 2 || G <= 1) return 0;
+  return (((size_t)kThreads * G * es + (size_t)kThreads * zeta * 2 + (size_t)kThreads * 4) + 15) & ~(size_t)15;
+}
+
 template <typename T, int MODE, int ZMAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
@@ -130,10 +141,15 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
   // staged once and applied to every member's vector, and the rows of S are generated once per row.
   const int r0 = blockIdx.y * G;
   const int gn = min(G, nb - r0);
-  const int bins_bytes = (MODE == 2) ? 0 : ((G * d * 8 + 15) & ~15);
-  double* bins = reinterpret_cast<double*>(smem_raw);
-  T* sv = reinterpret_cast<T*>(smem_raw + bins_bytes);
-  int* sc = reinterpret_cast<int*>(smem_raw + bins_bytes + kChunk * sizeof(T));
+  const size_t o_grp = spmv_lds_bins(MODE, d, G);
+  const size_t o_chk = o_grp + spmv_lds_group(MODE, G, zeta, sizeof(T));
+  double* bins = reinterpret_cast<double*>(smem_raw);  // [bin][member]
+  T* ztile = reinterpret_cast<T*>(smem_raw + o_grp);   // [row][member]        (G > 1)
+  uint16_t* rtile = reinterpret_cast<uint16_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T));
+  uint32_t* stile = reinterpret_cast<uint32_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T) +
+                                                (size_t)kThreads * zeta * 2);
+  T* sv = reinterpret_cast<T*>(smem_raw + o_chk);
+  int* sc = reinterpret_cast<int*>(smem_raw + o_chk + kChunk * sizeof(T));
   uint32_t live_mask = 0;  // members still iterating (block-uniform)
   for (int g = 0; g < gn; ++g) {
     const State* sg = st ? bat(st, bs, r0 + g) : nullptr;
@@ -141,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
   }
   if (live_mask == 0) return;
   if (MODE != 2) {
-    for (int i = threadIdx.x; i < gn * d; i += kThreads) bins[i] = 0.0;
+    for (int i = threadIdx.x; i < G * d; i += kThreads) bins[i] = 0.0;
     __syncthreads();
   }
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -163,9 +179,16 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
       one_chunk = (p1 - p0) <= kChunk;
       if (one_chunk) stage_chunk(vals, colind, p0, p1 - p0, sv, sc);
     }
+    if (G > 1 && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
     int rows[ZMAX];
     uint32_t sb = 0;
     if (MODE != 2 && live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+    if (MODE != 2 && G > 1) {
+#pragma unroll
+      for (int l = 0; l < ZMAX; ++l)
+        if (l < zeta) rtile[threadIdx.x * zeta + l] = (uint16_t)(live ? rows[l] : 0);
+      stile[threadIdx.x] = sb;
+    }
     for (int g = 0; g < gn; ++g) {
       if (!((live_mask >> g) & 1u)) continue;  // uniform over the block
       const T* xg = bat(x, bs, r0 + g);
@@ -186,22 +209,42 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
       } else if (live) {
         z = xg[row];
       }
-      if (MODE != 2 && live) {
-        const double zs = (double)z * (double)scale;
-        double* bg = bins + g * d;
+      if (MODE != 2) {
+        if (G == 1) {  // single member: scatter straight from the row's lane
+          if (live) {
+            const double zs = (double)z * (double)scale;
 #pragma unroll
-        for (int l = 0; l < ZMAX; ++l)
-          if (l < zeta) unsafeAtomicAdd(&bg[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+            for (int l = 0; l < ZMAX; ++l)
+              if (l < zeta) unsafeAtomicAdd(&bins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+          }
+        } else {
+          ztile[threadIdx.x * G + g] = z;
+        }
+      }
+    }
+    if (MODE != 2 && G > 1) {
+      // Group scatter: consecutive lanes take consecutive members of one row, so simultaneous LDS
+      // atomics go to consecutive addresses of a bin row instead of colliding in random bins.
+      __syncthreads();
+      const int nrow = min(kThreads, n - row0);
+      for (int item = threadIdx.x; item < nrow * G; item += kThreads) {
+        const int rr = item / G, g = item - rr * G;
+        if (g >= gn || !((live_mask >> g) & 1u)) continue;
+        const double zs = (double)ztile[rr * G + g] * (double)scale;
+        const uint32_t sgn = stile[rr];
+        const uint16_t* rw = rtile + rr * zeta;
+        for (int l = 0; l < zeta; ++l)
+          unsafeAtomicAdd(&bins[(int)rw[l] * G + g], ((sgn >> l) & 1u) ? -zs : zs);
       }
     }
   }
   if (MODE != 2) {
     __syncthreads();
-    for (int i = threadIdx.x; i < gn * d; i += kThreads) {
-      const int g = i / d, e = i - g * d;
+    for (int i = threadIdx.x; i < G * d; i += kThreads) {
+      const int b = i / G, g = i - b * G;
       const double v = bins[i];
-      if (v != 0.0 && ((live_mask >> g) & 1u))
-        unsafeAtomicAdd(bat(slots, bs, r0 + g) + (size_t)(blockIdx.x % kSlots) * d + e, v);
+      if (g < gn && v != 0.0 && ((live_mask >> g) & 1u))
+        unsafeAtomicAdd(bat(slots, bs, r0 + g) + (size_t)(blockIdx.x % kSlots) * d + b, v);
     }
   }
 }
@@ -432,10 +475,9 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 }
 
 // ------------------------------------------------------------------------------------ launchers
-size_t spmv_sketch_lds(int dtype, int mode, int d, int G) {
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta) {
   const size_t es = dtype == 0 ? 8 : 4;
-  const size_t bins = (mode == 2) ? 0 : (((size_t)G * d * 8 + 15) & ~(size_t)15);
-  return bins + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
+  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, zeta, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
 }
 
 template <typename T>
@@ -444,7 +486,7 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
                                        double* slots, const State* st, int nb, int G, size_t bs) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
-  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G);
+  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta);
   const dim3 g2(grid, (nb + G - 1) / G);
 #define FAB_L(M, Z)                                                                                              \
   hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, scale, k0, \
