@@ -170,6 +170,11 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
                            void* W, double* U, double* R, double* T, double* Rt, double* h_scal,
                            void* work, size_t work_bytes);
 
+/* Members per block of the batched product + sketch kernel: 1, or 16 (the MFMA sketch
+ * path); 0 (the default) times both on the first batched solve of each operator and batch shape
+ * and keeps the faster.  Test hook: pins either path.  Errors: FAB_E_INVALID. */
+fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
+
 /* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on
  * the context's stream (instead of replaying the cycle graph: the same kernels with the same
  * launch configuration) and records HIP events around each launch of the fused SpMV + sketch

@@ -23,7 +23,7 @@ METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
 __all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "workspace_size", "spmv", "sketch_apply",
-           "sketch_table", "cycle_debug", "dot", "ExpAction", "exp_action", "timing_enable", "timing_read",
+           "sketch_table", "cycle_debug", "dot", "batch_group", "ExpAction", "exp_action", "timing_enable", "timing_read",
            "FabError", "lib_path"]
 
 
@@ -207,6 +207,11 @@ def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, wo
     if check:
         _lib.check(st, "fab_solve_batched")
     return x.view(nb, nt, op.n).permute(2, 0, 1), [_info_dict(infos[r], st) for r in range(nb)]
+
+
+def batch_group(ctx: Context, G: int = 0):
+    """Pin the members per block of the batched kernel (1 or 16); 0 = autotune (default)."""
+    _lib.check(ctx.lib.fab_batch_group(ctx.handle, int(G)), "fab_batch_group", ok=(0,))
 
 
 def timing_enable(ctx: Context, on: bool = True):

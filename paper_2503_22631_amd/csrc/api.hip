@@ -22,6 +22,8 @@ hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n,
                               double* slots, const State* st, int nb, int G, size_t bs);
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta);
 hipError_t configure_cycle_kernels();
+hipError_t configure_step_kernels();
+size_t group_lds_max();
 hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
                        double* R, State* st, int nb, size_t bs);
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
@@ -102,6 +104,7 @@ struct fab_ctx {
     int nb, d, zeta, dtype, G;
   };
   std::vector<Tuned> tuned;
+  int force_group = 0;  // fab_batch_group: 0 = autotune
   std::vector<Cached> graphs;
 };
 
@@ -373,7 +376,7 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
     c->num_cu = prop.multiProcessorCount;
     if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   }
-  if (configure_cycle_kernels() != hipSuccess) {
+  if (configure_cycle_kernels() != hipSuccess || configure_step_kernels() != hipSuccess) {
     delete c;
     return FAB_E_HIP;
   }
@@ -537,6 +540,10 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
                              int* G_out) {
   *G_out = 1;
   if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
+  if (ctx->force_group > 0) {
+    *G_out = ctx->force_group;
+    return FAB_OK;
+  }
   for (const auto& t : ctx->tuned)
     if (t.op == A && t.n == A->n && t.nb == nb && t.d == p->d && t.zeta == p->zeta && t.dtype == A->dtype) {
       *G_out = t.G;
@@ -551,8 +558,10 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   int best = 1;
   float best_ms = 1e30f;
   hipError_t err = hipSuccess;
-  for (int G = 1; G <= 16 && G <= nb && err == hipSuccess; G *= 2) {
-    if (spmv_sketch_lds(dt, 0, d, G, p->zeta) > 64 * 1024) break;
+  // candidates: one member per block, or a group of 16 (the MFMA sketch's N-tile; finished members
+  // and padding cost gathers of nothing)
+  for (int G = 1; G <= 16 && err == hipSuccess; G += 15) {
+    if (G > 1 && spmv_sketch_lds(dt, 0, d, G, p->zeta) > group_lds_max()) break;
     const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta);
     void* x0 = q.W;
     void* y0 = (char*)q.W + (size_t)n * es;
@@ -755,6 +764,12 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
                              const void* b, int64_t ldb, double* x, int64_t ldx, const fab_params* p, void* work,
                              size_t work_bytes, fab_info* h_info) {
   return solve_batch(ctx, A, fun, h_t, nt, nb, b, ldb, x, ldx, p, work, work_bytes, h_info);
+}
+
+fab_status fab_batch_group(fab_ctx* ctx, int32_t G) {
+  if (!ctx || (G != 0 && G != 1 && G != 16)) return FAB_E_INVALID;
+  ctx->force_group = G;
+  return FAB_OK;
 }
 
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on) {

@@ -128,7 +128,39 @@ __host__ __device__ inline size_t spmv_lds_group(int mode, int G, int zeta, size
   return (((size_t)kThreads * G * es + (size_t)kThreads * zeta * 2 + (size_t)kThreads * 4) + 15) & ~(size_t)15;
 }
 
-template <typename T, int MODE, int ZMAX>
+// row_dot for MU batch members at once (the same row, entries and values, MU vectors): all
+// MU x kGather gathers are issued before the first product, so a group of members costs one
+// memory round trip per pass instead of one per member.  Members with xs[u] == nullptr are skipped.
+template <typename T, int MU>
+__device__ __forceinline__ void row_dot_multi(const T* sv, const int* sc, const T* const* xs, int lo, int hi, int cs,
+                                              double* acc) {
+  for (int pg = lo; pg < hi; pg += kGather) {
+    T av[kGather];
+    int cv[kGather];
+#pragma unroll
+    for (int q = 0; q < kGather; ++q) {
+      const int p = pg + q;
+      av[q] = (p < hi) ? sv[p - cs] : T(0);
+      cv[q] = (p < hi) ? sc[p - cs] : -1;
+    }
+    T xv[MU][kGather];
+#pragma unroll
+    for (int u = 0; u < MU; ++u)
+#pragma unroll
+      for (int q = 0; q < kGather; ++q) xv[u][q] = (xs[u] != nullptr && cv[q] >= 0) ? xs[u][cv[q]] : T(0);
+#pragma unroll
+    for (int u = 0; u < MU; ++u)
+#pragma unroll
+      for (int q = 0; q < kGather; ++q) acc[u] = fma((double)av[q], (double)xv[u][q], acc[u]);
+  }
+}
+
+constexpr int kMembersInFlight = 4;  // batch members whose gathers are issued together
+constexpr int kGroup = 16;           // members per block in the grouped (batched) kernel: one MFMA N-tile
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T, int MODE, int ZMAX, bool GRP>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
                                                           const T* __restrict__ vals,
@@ -139,6 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
   extern __shared__ unsigned char smem_raw[];
   // This block serves batch members r0 .. r0+gn-1 (one member for single solves): the CSR chunk is
   // staged once and applied to every member's vector, and the rows of S are generated once per row.
+  if (!GRP) G = 1;  // the single-member instantiation
   const int r0 = blockIdx.y * G;
   const int gn = min(G, nb - r0);
   const size_t o_grp = spmv_lds_bins(MODE, d, G);
@@ -179,18 +212,35 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
       one_chunk = (p1 - p0) <= kChunk;
       if (one_chunk) stage_chunk(vals, colind, p0, p1 - p0, sv, sc);
     }
-    if (G > 1 && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
+    if (GRP && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
     int rows[ZMAX];
     uint32_t sb = 0;
-    if (MODE != 2 && live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
-    if (MODE != 2 && G > 1) {
+    if (MODE == 0 && GRP && one_chunk) {
+      // members in flights of kMembersInFlight: one round trip of gathers per flight
+      for (int g0 = 0; g0 < G; g0 += kMembersInFlight) {
+        const T* xs[kMembersInFlight];
+        double acc[kMembersInFlight];
 #pragma unroll
-      for (int l = 0; l < ZMAX; ++l)
-        if (l < zeta) rtile[threadIdx.x * zeta + l] = (uint16_t)(live ? rows[l] : 0);
-      stile[threadIdx.x] = sb;
-    }
-    for (int g = 0; g < gn; ++g) {
-      if (!((live_mask >> g) & 1u)) continue;  // uniform over the block
+        for (int u = 0; u < kMembersInFlight; ++u) {
+          const int g = g0 + u;
+          xs[u] = (g < gn && ((live_mask >> g) & 1u)) ? bat(x, bs, r0 + g) : nullptr;
+          acc[u] = 0.0;
+        }
+        row_dot_multi<T, kMembersInFlight>(sv, sc, xs, my_lo, my_hi, p0, acc);
+#pragma unroll
+        for (int u = 0; u < kMembersInFlight; ++u) {
+          const int g = g0 + u;
+          const T z = (T)acc[u];  // 0 for finished members and padding
+          if (xs[u] != nullptr && live) __builtin_nontemporal_store(z, bat(y, bs, r0 + g) + row);
+          ztile[threadIdx.x * G + g] = z;
+        }
+      }
+    } else
+    for (int g = 0; g < G; ++g) {
+      if (g >= gn || !((live_mask >> g) & 1u)) {  // uniform over the block
+        if (GRP) ztile[threadIdx.x * G + g] = T(0);
+        continue;
+      }
       const T* xg = bat(x, bs, r0 + g);
       T z = T(0);
       if (MODE != 1) {
@@ -210,8 +260,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
         z = xg[row];
       }
       if (MODE != 2) {
-        if (G == 1) {  // single member: scatter straight from the row's lane
+        if (!GRP) {  // single member: scatter straight from the row's lane
           if (live) {
+            sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
             const double zs = (double)z * (double)scale;
 #pragma unroll
             for (int l = 0; l < ZMAX; ++l)
@@ -222,19 +273,44 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
         }
       }
     }
-    if (MODE != 2 && G > 1) {
-      // Group scatter: consecutive lanes take consecutive members of one row, so simultaneous LDS
-      // atomics go to consecutive addresses of a bin row instead of colliding in random bins.
+    if (MODE != 2 && GRP) {
+      // The row's S entries are generated after the products (so the gathers are in flight first)
+      // and shared through LDS.  Then the tile's sketch for the kGroup members is a dense FP64
+      // contraction on the matrix cores, bins(d x 16) += S_tile(d x rows) Z_tile(rows x 16):
+      // wavefront w owns 16-bin slices w, w+4, ...; the +-1 entries of S_tile are formed on the fly
+      // from each row's zeta generated rows (no dense S in LDS), and the scale 1/sqrt(zeta) is
+      // applied to the result.  v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+      // and holds D[4r + l/16][l%16], r = 0..3.
+      if (live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+#pragma unroll
+      for (int l = 0; l < ZMAX; ++l)
+        if (l < zeta) rtile[threadIdx.x * zeta + l] = (uint16_t)(live ? rows[l] : 0);
+      stile[threadIdx.x] = sb;
       __syncthreads();
+      const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
       const int nrow = min(kThreads, n - row0);
-      for (int item = threadIdx.x; item < nrow * G; item += kThreads) {
-        const int rr = item / G, g = item - rr * G;
-        if (g >= gn || !((live_mask >> g) & 1u)) continue;
-        const double zs = (double)ztile[rr * G + g] * (double)scale;
-        const uint32_t sgn = stile[rr];
-        const uint16_t* rw = rtile + rr * zeta;
-        for (int l = 0; l < zeta; ++l)
-          unsafeAtomicAdd(&bins[(int)rw[l] * G + g], ((sgn >> l) & 1u) ? -zs : zs);
+      const int nmt = (d + 15) >> 4;
+      const double dscale = (double)scale;
+      for (int mt = wv; mt < nmt; mt += kThreads / 64) {
+        const int bq = mt * 16 + (lane & 15);  // this lane's bin in the A operand
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0r = 0; k0r < nrow; k0r += 4) {
+          const int k = k0r + (lane >> 4);
+          double a = 0.0, bz = 0.0;
+          if (k < nrow) {
+            const uint16_t* rk = rtile + k * zeta;
+            const uint32_t sg = stile[k];
+            for (int l = 0; l < zeta; ++l)
+              if ((int)rk[l] == bq) a = ((sg >> l) & 1u) ? -1.0 : 1.0;
+            bz = (double)ztile[k * G + (lane & 15)];
+          }
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int bb = mt * 16 + 4 * r + (lane >> 4);
+          if (bb < d) bins[bb * G + (lane & 15)] += acc[r] * dscale;  // owner-exclusive (bin, member)
+        }
       }
     }
   }
@@ -488,9 +564,13 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
   const T scale = (T)(1.0 / sqrt((double)zeta));
   const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta);
   const dim3 g2(grid, (nb + G - 1) / G);
-#define FAB_L(M, Z)                                                                                              \
-  hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, scale, k0, \
-                     k1, slots, st, nb, G, bs)
+#define FAB_L(M, Z)                                                                                             \
+  if (G > 1)                                                                                                    \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, \
+                       scale, k0, k1, slots, st, nb, G, bs);                                                    \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, \
+                       scale, k0, k1, slots, st, nb, 1, bs)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -514,6 +594,30 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
 #undef FAB_L
   return hipGetLastError();
 }
+
+constexpr int kGroupLdsMax = 96 * 1024;  // dynamic LDS the grouped kernel may use (2 blocks per CU)
+
+// The grouped instantiations need more than the default 64 KB of dynamic LDS for FP64 data.
+hipError_t configure_step_kernels() {
+  const void* fns[] = {
+      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 1, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 4, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 8, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 16, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 32, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 1, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 4, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 8, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 16, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 32, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 1, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 4, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 8, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 16, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 32, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 1, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 4, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 8, true>),
+      reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 16, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 32, true>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kGroupLdsMax);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t group_lds_max() { return kGroupLdsMax; }
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,

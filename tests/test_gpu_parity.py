@@ -544,9 +544,18 @@ def test_exp_action_gradients_96_full_size(fab, ctx):
 CFG4_T = [10.0 ** (-5 + 2 * i / 7) for i in range(8)]   # 8 time points, log-spaced in [1e-5, 1e-3]
 
 
-def test_batched_matches_single_solves(fab, ctx):
+@pytest.fixture
+def group(fab, ctx, request):
+    fab.batch_group(ctx, request.param)
+    yield request.param
+    fab.batch_group(ctx, 0)
+
+
+@pytest.mark.parametrize("group", [1, 16], indirect=True)
+def test_batched_matches_single_solves(fab, ctx, group):
     """Five right-hand sides in one batched solve against five single solves (same S) and the
-    closed form, three time points each."""
+    closed form, three time points each; one member per block and the 16-member MFMA sketch path
+    (11 padding members)."""
     N = 48
     A = wl.anisotropic_2d(N, 0.01)
     op = _op(fab, ctx, A)
@@ -555,6 +564,7 @@ def test_batched_matches_single_solves(fab, ctx):
     kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=100)
     X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=ts, **kw)
     assert X.shape == (A.n, nb, len(ts))
+    assert all(i["group"] == group for i in infos)
     for r in range(nb):
         assert infos[r]["status"] == "FAB_OK", (r, infos[r])
         xs, info_s = fab.solve(op, torch.as_tensor(Bm[:, r], device="cuda"), "exp", t=ts, **kw)
@@ -565,7 +575,8 @@ def test_batched_matches_single_solves(fab, ctx):
             assert _rel(xb, exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)) <= 1e-9
 
 
-def test_batched_members_finish_differently(fab, ctx):
+@pytest.mark.parametrize("group", [1, 16], indirect=True)
+def test_batched_members_finish_differently(fab, ctx, group):
     """One batch holding a zero right-hand side (exact at once), an eigenvector (breakdown after one
     step) and random vectors (several cycles): per-member statuses and results."""
     N = 32
@@ -587,7 +598,8 @@ def test_batched_members_finish_differently(fab, ctx):
             assert _rel(got, ref) <= 1e-9
 
 
-def test_batched_fp32_anisotropic_eight_times(fab, ctx):
+@pytest.mark.parametrize("group", [1, 16], indirect=True)
+def test_batched_fp32_anisotropic_eight_times(fab, ctx, group):
     """The batched workload's shape on a small grid: FP32 anisotropic operator, 8 right-hand sides
     x 8 log-spaced time points, m=20, k=2, d=80, tol 1e-6."""
     N = 64
