@@ -11,7 +11,7 @@ with HIP events on its own stream during the timed solves), the step-loop bandwi
 restarted Arnoldi comparator on the same GPU, and the CPU oracle timed on the host as baseline
 (which also gives the relative error of the GPU result against the exact FP64 solution).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--profile]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra] [--profile]
     python bench.py --summarize-pmc FETCH_DIR WRITE_DIR    # turn rocprofv3 --pmc output into traffic
 """
 import argparse
@@ -76,7 +76,7 @@ def cpu_info():
     return {"nproc": os.cpu_count(), "model": model or platform.processor()}
 
 
-def cpu_baseline_leg(A, b, x_gpu, x_plain):
+def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=()):
     """The oracle, as it stands, on the host: complete solves of the same workload by its FP64
     step-by-step twin (same sketch), with BLAS limited to one thread, repeated until about 10 s of
     CPU work (at most 4 solves).  Also the exact solution by the Kronecker-product closed form, for
@@ -97,6 +97,8 @@ def cpu_baseline_leg(A, b, x_gpu, x_plain):
             total += time.perf_counter() - t0
             solves += 1
     dt = total / solves
+    for rec, key, fn in checks:  # errors of the extra legs' GPU results against the exact FP64 results
+        rec[key] = fn(exact)
     factors, _ = exact.problem_factors("convdiff_3d", w["N"], peclet=w["peclet"])
     ref = exact.kron_exp_fab(b, factors, w["t"])
     rel = lambda v: float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
@@ -165,6 +167,130 @@ def summarize_trace(trace_dir: str, out_md: str, command: str):
     print(out_md)
 
 
+def _timed(fn, reps=1):
+    """(seconds per call, last result) of fn after one warm-up call, bracketed by device syncs."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, r
+
+
+def extra_legs(fab, ctx):
+    """The other workloads of the method on the same GPU: z^(-1/2) with FP32 against FP64 values
+    and basis; 64 right-hand sides x 8 time points in one batched FP32 solve against single FP64
+    solves; 32 Laplacians of uneven size in one ragged solve; the gradient of <c, exp(-tA) b>
+    (forward solve + adjoint solve on A^T).  Returns (results, checks): each check is
+    (record, key, fn) with fn(exact) the error of a kept GPU result against the exact FP64 result,
+    evaluated in the CPU leg (the oracle's closed forms run only there)."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out, checks = {}, []
+    # --- z^(-1/2) of the shifted 3-D Laplacian, 256^3 (n = 16.8M), FP32 vs FP64
+    N = 256
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    b = wl.gaussian_vector(A.n, 0)
+    lo = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2 + 1.0
+    spec = (lo, 12 * (N + 1) ** 2 + 1.0)
+    leg = {"workload": "shifted_laplacian_3d_N256 z^(-1/2)", "n": A.n, "nnz": A.nnz, "m": 30, "k": 2, "d": 120,
+           "zeta": 8, "tol": 1e-6}
+    for dt, name in ((torch.float32, "f32"), (torch.float64, "f64")):
+        op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=dt)
+        bt = torch.as_tensor(b, dtype=dt, device="cuda")
+        sec, (x, info) = _timed(lambda: fab.solve(op, bt, "invsqrt", m=30, k=2, d=120, zeta=8, seed=1, tol=1e-6,
+                                                  spec=spec, max_cycles=300))
+        leg[name] = {"solves_per_s": 1.0 / sec, "cycles": info["cycles"], "ms_per_cycle": 1e3 * sec / info["cycles"],
+                     "status": info["status"]}
+        xh = x[:, 0].cpu().numpy()
+        bb = b if dt == torch.float64 else b.astype(np.float32).astype(np.float64)
+        checks.append((leg[name], "rel_err",
+                       lambda ex, xh=xh, bb=bb, N=N: rel(xh, ex.sine_fab("invsqrt", bb, N, [1, 1, 1], 1.0))))
+        del op, bt, x
+        torch.cuda.empty_cache()
+    out["invsqrt_256"] = leg
+    del A
+    # --- batched: 64 right-hand sides x 8 time points, anisotropic 1024^2, FP32; single FP64 for comparison
+    N, nb = 1024, 64
+    T = [10.0 ** (-5 + 2 * i / 7) for i in range(8)]
+    A = wl.anisotropic_2d(N, 0.01)
+    Bm = np.stack([wl.gaussian_vector(A.n, 300 + r) for r in range(nb)], axis=1).astype(np.float32)
+    op32 = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=torch.float32)
+    Bt = torch.as_tensor(Bm, device="cuda")
+    kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6, max_cycles=300)
+    sec, (X, infos) = _timed(lambda: fab.solve_batched(op32, Bt, "exp", t=T, **kw))
+    samples = {(r, i): X[:, r, i].cpu().numpy() for r in (0, nb - 1) for i in range(len(T))}
+    op64 = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=torch.float64)
+    b64 = torch.as_tensor(Bm[:, 0].astype(np.float64), device="cuda")
+    sec1, (x1, info1) = _timed(lambda: fab.solve(op64, b64, "exp", t=T, **kw))
+    single = [x1[:, i].cpu().numpy() for i in range(len(T))]
+    leg = {"workload": "anisotropic_2d_N1024 (1, 0.01), exp, 64 rhs x 8 t in [1e-5, 1e-3]", "n": A.n,
+           "results": nb * len(T), "results_per_s": nb * len(T) / sec, "seconds": sec,
+           "cycles_max": max(i["cycles"] for i in infos), "group": infos[0]["group"], "values": "f32",
+           "single_f64": {"results_per_s": len(T) / sec1, "cycles": info1["cycles"]},
+           "speedup_vs_single_f64": (nb * len(T) / sec) / (len(T) / sec1)}
+    checks.append((leg, "rel_err_sampled_max", lambda ex, N=N, T=T, Bm=Bm, samples=samples: max(
+        rel(v, ex.sine_fab("exp", Bm[:, r].astype(np.float64), N, [1.0, 0.01], 0.0, t=T[i])) for (r, i), v in samples.items())))
+    checks.append((leg["single_f64"], "rel_err_max", lambda ex, N=N, T=T, Bm=Bm, single=single: max(
+        rel(single[i], ex.sine_fab("exp", Bm[:, 0].astype(np.float64), N, [1.0, 0.01], 0.0, t=t)) for i, t in enumerate(T))))
+    out["batched_1024"] = leg
+    del op32, op64, Bt, X, x1
+    torch.cuda.empty_cache()
+    # --- ragged: 32 Laplacians on grids 64^2 .. 512^2, FP32, one solve
+    Ns = [int(round(64 * 8 ** (i / 31))) for i in range(32)]
+    ops, bs, b64s = [], [], []
+    for i, Ng in enumerate(Ns):
+        Ag = wl.laplacian_2d(Ng)
+        bg = wl.gaussian_vector(Ag.n, 1000 + i).astype(np.float32)
+        ops.append(fab.CSROperator.from_arrays(ctx, Ag.rowptr, Ag.colind, Ag.vals, dtype=torch.float32))
+        bs.append(torch.as_tensor(bg, device="cuda"))
+        b64s.append(bg.astype(np.float64))
+    sec, (xs, infos) = _timed(lambda: fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw))
+    xr = [v[:, 0].cpu().numpy() for v in xs]
+    leg = {"workload": "32 laplacian_2d, N = 64 .. 512 (geometric), exp t = 1e-3", "values": "f32",
+           "rows_total": sum(Ng * Ng for Ng in Ns), "operators_per_s": 32 / sec, "seconds": sec,
+           "cycles_max": max(i["cycles"] for i in infos)}
+    checks.append((leg, "rel_err_max", lambda ex, xr=xr, b64s=b64s, Ns=Ns: max(
+        rel(xr[i], ex.sine_fab("exp", b64s[i], Ng, [1, 1], 0.0, t=1e-3)) for i, Ng in enumerate(Ns))))
+    out["ragged_32"] = leg
+    del ops, bs, xs
+    torch.cuda.empty_cache()
+    # --- gradient of <c, exp(-tA) b>: 96^3 convection-diffusion, Pe 20, t = 1e-4
+    N, t = 96, 1e-4
+    A = wl.convdiff_3d(N, 20.0)
+    op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals)
+    op_t = op.transpose()
+    bn, cn = wl.gaussian_vector(A.n, 0), wl.gaussian_vector(A.n, 7)
+    c = torch.as_tensor(cn, device="cuda")
+
+    def grad_once():
+        bb = torch.as_tensor(bn, device="cuda").requires_grad_(True)
+        tt = torch.tensor(t, dtype=torch.float64, requires_grad=True)
+        L = torch.dot(c, fab.exp_action(op, bb, tt, op_t=op_t, m=40, k=4, d=160, zeta=8, seed=1, tol=1e-10))
+        L.backward()
+        return bb.grad.cpu().numpy(), float(tt.grad)
+
+    sec, (gb, gt) = _timed(grad_once)
+    leg = {"workload": "convdiff_3d_N96_Pe20, d<c, exp(-tA) b>/db and /dt, t = 1e-4", "n": A.n,
+           "forward_plus_adjoint_ms": 1e3 * sec}
+
+    def grad_errs(ex):
+        factors, _ = ex.problem_factors("convdiff_3d", N, peclet=20.0)
+        _, gbo, gto = ex.exp_action_grads(factors, bn, cn, t)
+        leg["rel_err_dt"] = abs(gt - gto) / abs(gto)
+        return rel(gb, gbo)
+
+    checks.append((leg, "rel_err_db", grad_errs))
+    out["adjoint_96"] = leg
+    return out, checks
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +298,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain restarted Arnoldi comparator")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (FP32, batched, ragged, adjoint)")
     ap.add_argument("--profile", action="store_true",
                     help="few solves, no CPU leg, plus a device copy of known size for counter calibration")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -188,7 +315,8 @@ def main():
               "(the multi-GPU design is documented, not built).", file=sys.stderr)
         return 2
     if args.profile:
-        args.no_cpu_baseline, args.steps, args.warmup = True, min(args.steps, 3), min(args.warmup, 1)
+        args.no_cpu_baseline, args.no_extra = True, True
+        args.steps, args.warmup = min(args.steps, 3), min(args.warmup, 1)
 
     import numpy as np
     import torch
@@ -277,8 +405,13 @@ def main():
                     "bytes_per_step": step_bytes, "steps_timed": tm["loop_steps"],
                     "avg_step_us": 1e3 * tm["loop_ms"] / max(tm["loop_steps"], 1)},
            "comparison": comparison}
+    checks = []
+    if not args.no_extra:
+        del work, x
+        torch.cuda.empty_cache()
+        out["extra"], checks = extra_legs(fab, ctx)
     if not args.no_cpu_baseline:
-        cpu, errs = cpu_baseline_leg(A, b, x_gpu, x_plain)
+        cpu, errs = cpu_baseline_leg(A, b, x_gpu, x_plain, checks)
         cpu["host"] = cpu_info()
         out["cpu_baseline"] = cpu
         out["rel_err_vs_oracle"] = errs["gpu_rel_err"]

@@ -146,6 +146,19 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
                              int32_t nb, const void* b, int64_t ldb, double* x, int64_t ldx,
                              const fab_params* p, void* work, size_t work_bytes, fab_info* h_info);
 
+/* Ragged batches: nops operators of uneven size (any mix of n, nnz and dtype), one right-hand
+ * side each: x[i] (n_i x nt FP64) = f(A_i) b[i].  b and x are host arrays of nops device
+ * pointers.  Every operator runs the method of fab_solve in its own part of work
+ * (fab_workspace_size_ragged bytes); the cycles of all operators are captured into one graph
+ * (operators spread over 8 concurrent branches) that is replayed once per cycle until every
+ * operator has finished.  h_info has nops entries; the return value is the most severe status.
+ * 1 <= nops <= 1024; FAB_PLAIN_RESTART is not supported (FAB_E_UNSUPPORTED). */
+fab_status fab_workspace_size_ragged(int32_t nops, const fab_op* const* ops, const fab_params* p, int32_t nt,
+                                     size_t* h_bytes);
+fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops, int32_t fun,
+                            const double* h_t, int32_t nt, const void* const* b, double* const* x,
+                            const fab_params* p, void* work, size_t work_bytes, fab_info* h_info);
+
 /* ---- test hooks: the same kernels as fab_solve, exposed for parity tests ---- */
 
 /* y = A x (A's dtype for x and y). */

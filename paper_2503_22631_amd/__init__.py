@@ -22,7 +22,7 @@ FUN = {"exp": 0, "invsqrt": 1}
 METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
-__all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "workspace_size", "spmv", "sketch_apply",
+__all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "solve_ragged", "workspace_size", "spmv", "sketch_apply",
            "sketch_table", "cycle_debug", "dot", "batch_group", "ExpAction", "exp_action", "timing_enable", "timing_read",
            "FabError", "lib_path"]
 
@@ -207,6 +207,39 @@ def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, wo
     if check:
         _lib.check(st, "fab_solve_batched")
     return x.view(nb, nt, op.n).permute(2, 0, 1), [_info_dict(infos[r], st) for r in range(nb)]
+
+
+def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None, check: bool = True, **kw):
+    """[f(A_i) b_i] for operators of uneven size in one ragged solve (fab_solve_ragged).
+
+    ``ops`` and ``bs`` are equal-length lists (b_i on the device, in A_i's dtype).  Returns
+    (xs, infos): xs[i] of shape (n_i, nt) FP64, and one info dict per operator.
+    """
+    ctx = ops[0].ctx
+    nops = len(ops)
+    assert len(bs) == nops and all(op.ctx is ctx for op in ops)
+    p = kw.pop("params", None) or Params(**kw)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    nt = len(ts)
+    bs = [b.contiguous() for b in bs]
+    for op, b in zip(ops, bs):
+        assert b.is_cuda and b.dtype == op.dtype and b.numel() == op.n
+    xs = [torch.empty((nt, op.n), dtype=torch.float64, device=ctx.device) for op in ops]
+    handles = (ctypes.c_void_p * nops)(*[op.handle.value for op in ops])
+    nbytes = ctypes.c_size_t()
+    _lib.check(ctx.lib.fab_workspace_size_ragged(nops, handles, ctypes.byref(p), nt, ctypes.byref(nbytes)),
+               "fab_workspace_size_ragged", ok=(0,))
+    if work is None:
+        work = ctx.workspace(nbytes.value)
+    infos = (fab_info * nops)()
+    tarr = (ctypes.c_double * nt)(*ts.tolist())
+    bp = (ctypes.c_void_p * nops)(*[b.data_ptr() for b in bs])
+    xp = (ctypes.c_void_p * nops)(*[x.data_ptr() for x in xs])
+    st = ctx.lib.fab_solve_ragged(ctx.handle, nops, handles, FUN[fun], tarr, nt, bp, xp, ctypes.byref(p), _ptr(work),
+                                  work.numel(), infos)
+    if check:
+        _lib.check(st, "fab_solve_ragged")
+    return [x.t() for x in xs], [_info_dict(infos[i], st) for i in range(nops)]
 
 
 def batch_group(ctx: Context, G: int = 0):

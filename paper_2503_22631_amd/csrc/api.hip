@@ -105,6 +105,12 @@ struct fab_ctx {
   };
   std::vector<Tuned> tuned;
   int force_group = 0;  // fab_batch_group: 0 = autotune
+  // ragged solves: branch streams and fork/join events of the captured graph, and its cache
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  std::vector<uintptr_t> ragged_key;
+  hipGraphExec_t ragged_exec = nullptr;
   std::vector<Cached> graphs;
 };
 
@@ -399,6 +405,10 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
 fab_status fab_destroy(fab_ctx* c) {
   if (!c) return FAB_E_INVALID;
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->ragged_exec) (void)hipGraphExecDestroy(c->ragged_exec);
+  for (auto& st : c->branch) (void)hipStreamDestroy(st);
+  for (auto& e : c->join) (void)hipEventDestroy(e);
+  if (c->fork) (void)hipEventDestroy(c->fork);
   for (auto& e : c->tev) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(c->work);
   (void)hipStreamDestroy(c->work);
@@ -590,6 +600,59 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
 
 static int status_rank(fab_status s) { return s < 0 ? 100 - (int)s : (int)s; }  // errors above warnings
 
+// Per-member outcome of the restarted loop, updated from each cycle's report.
+struct Track {
+  fab_status status = FAB_W_NOT_CONVERGED;
+  int cycles = 0, matvecs = 0;
+  bool finished = false;
+  double est = 0.0, rule_err = 0.0;
+};
+
+// Returns true when this report finishes the member.
+static bool track_report(Track& t, const Report& rr, int c) {
+  t.cycles = c + 1;
+  t.matvecs += rr.meff;
+  t.est = rr.est;
+  t.rule_err = std::max(t.rule_err, rr.rule_err);
+  if (rr.nonfinite) {
+    t.status = FAB_E_NONFINITE;
+  } else if (rr.brk) {
+    t.status = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
+  } else if (rr.converged) {
+    t.status = FAB_OK;
+  } else if (!(rr.est <= kDivergedEst)) {
+    // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
+    // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
+    t.status = FAB_E_DIVERGED;
+  } else {
+    return false;
+  }
+  t.finished = true;
+  return true;
+}
+
+// Final statuses into h_info; returns the most severe.
+static fab_status finish_tracks(std::vector<Track>& tr, const fab_params* p, fab_info* h_info, int group) {
+  fab_status worst = FAB_OK;
+  for (size_t r = 0; r < tr.size(); ++r) {
+    Track& t = tr[r];
+    // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
+    // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
+    if ((t.status == FAB_OK || t.status == FAB_OK_BREAKDOWN) && t.rule_err > std::max(0.1 * p->tol, 1e-11))
+      t.status = FAB_W_QUADRATURE;
+    if (status_rank(t.status) > status_rank(worst)) worst = t.status;
+    if (h_info) {
+      h_info[r].status = t.status;
+      h_info[r].cycles = t.cycles;
+      h_info[r].matvecs = t.matvecs;
+      h_info[r].est_rel_update = t.est;
+      h_info[r].quad_rule_error = t.rule_err;
+      h_info[r].group = group;
+    }
+  }
+  return worst;
+}
+
 // The restarted loop of Algorithm 2 for nb right-hand sides (columns of b, leading dimension ldb)
 // sharing A; member r's result for time point i is column r nt + i of x (leading dimension ldx).
 static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, int nb,
@@ -679,10 +742,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
     }
     ctx->graphs.push_back({key, exec});
   }
-  std::vector<fab_status> status(nb, FAB_W_NOT_CONVERGED);
-  std::vector<int> cycles(nb, 0), matvecs(nb, 0);
-  std::vector<char> finished(nb, 0);
-  std::vector<double> est(nb, 0.0), rule_err(nb, 0.0);
+  std::vector<Track> tr(nb);
   int remaining = nb;
   for (int c = 0; c < p->max_cycles && remaining > 0; ++c) {
     if (ctx->timing) {
@@ -694,28 +754,10 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
     FAB_TRY(hipStreamSynchronize(s));
     int steps = 0;  // steps run this cycle: the longest among members still iterating
     for (int r = 0; r < nb; ++r) {
-      if (finished[r]) continue;
+      if (tr[r].finished) continue;
       const Report rr = ctx->h_rep[r];
       if (!rr.nonfinite) steps = std::max(steps, rr.meff);
-      cycles[r] = c + 1;
-      matvecs[r] += rr.meff;
-      est[r] = rr.est;
-      rule_err[r] = std::max(rule_err[r], rr.rule_err);
-      if (rr.nonfinite) {
-        status[r] = FAB_E_NONFINITE;
-      } else if (rr.brk) {
-        status[r] = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
-      } else if (rr.converged) {
-        status[r] = FAB_OK;
-      } else if (!(rr.est <= kDivergedEst)) {
-        // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
-        // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
-        status[r] = FAB_E_DIVERGED;
-      } else {
-        continue;
-      }
-      finished[r] = 1;
-      --remaining;
+      if (track_report(tr[r], rr, c)) --remaining;
     }
     if (ctx->timing) {
       for (int j = 0; j < steps; ++j) {
@@ -732,23 +774,151 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
       }
     }
   }
-  fab_status worst = FAB_OK;
-  for (int r = 0; r < nb; ++r) {
-    // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
-    // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
-    if ((status[r] == FAB_OK || status[r] == FAB_OK_BREAKDOWN) && rule_err[r] > std::max(0.1 * p->tol, 1e-11))
-      status[r] = FAB_W_QUADRATURE;
-    if (status_rank(status[r]) > status_rank(worst)) worst = status[r];
-    if (h_info) {
-      h_info[r].status = status[r];
-      h_info[r].cycles = cycles[r];
-      h_info[r].matvecs = matvecs[r];
-      h_info[r].est_rel_update = est[r];
-      h_info[r].quad_rule_error = rule_err[r];
-      h_info[r].group = B.G;
-    }
+  return finish_tracks(tr, p, h_info, B.G);
+}
+
+// ----------------------------------------------------------------------------- ragged batches
+constexpr int kBranches = 8;  // branch streams of the captured ragged graph
+
+fab_status fab_workspace_size_ragged(int32_t nops, const fab_op* const* ops, const fab_params* p, int32_t nt,
+                                     size_t* h_bytes) {
+  if (!ops || !p || !h_bytes || nops < 1 || nops > kMaxBatch) return FAB_E_INVALID;
+  size_t total = 0;
+  for (int i = 0; i < nops; ++i) {
+    if (!ops[i]) return FAB_E_INVALID;
+    size_t one = 0;
+    const fab_status st = fab_workspace_size(ops[i], p, nt, &one);
+    if (st != FAB_OK) return st;
+    total += align_up(one);
   }
-  return worst;
+  *h_bytes = total;
+  return FAB_OK;
+}
+
+// Operators of uneven size, one right-hand side each: every operator runs the single-solve cycle in
+// its own workspace; the cycles of all operators are captured once, on kBranches forked streams,
+// into one graph that is replayed once per cycle (finished operators' kernels return at once).
+fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops, int32_t fun, const double* h_t,
+                            int32_t nt, const void* const* b, double* const* x, const fab_params* p, void* work,
+                            size_t work_bytes, fab_info* h_info) {
+  for (int i = 0; i < nops && h_info; ++i) info_init(h_info + i, FAB_E_INVALID);
+  if (!ctx || !ops || !b || !x || !p || !work || nops < 1 || nops > kMaxBatch) return FAB_E_INVALID;
+  if (p->method == FAB_PLAIN_RESTART) return FAB_E_UNSUPPORTED;
+  if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
+  if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
+  for (int i = 0; i < nops; ++i) {
+    if (!ops[i] || !b[i] || !x[i]) return FAB_E_INVALID;
+    const fab_status ps = check_params(ops[i], p, fun, nt);
+    if (ps != FAB_OK) return ps;
+  }
+  if (fun == FAB_EXP_NEG)
+    for (int i = 0; i < nt; ++i)
+      if (!std::isfinite(h_t[i]) || !(h_t[i] > 0.0)) return FAB_E_INVALID;
+  size_t need = 0;
+  if (fab_workspace_size_ragged(nops, ops, p, nt, &need) != FAB_OK) return FAB_E_INVALID;
+  if (work_bytes < need) {
+    for (int i = 0; i < nops && h_info; ++i) info_init(h_info + i, FAB_E_WORKSPACE);
+    return FAB_E_WORKSPACE;
+  }
+  for (int i = 0; i < nops && h_info; ++i) info_init(h_info + i, FAB_E_HIP);
+  std::vector<Layout> L(nops);
+  std::vector<Ptrs> q(nops);
+  size_t off = 0;
+  for (int i = 0; i < nops; ++i) {
+    L[i] = make_layout(ops[i]->n, ops[i]->dtype, p, fun, nt);
+    q[i] = carve((char*)work + off, L[i], p, nt);
+    size_t one = 0;
+    (void)fab_workspace_size(ops[i], p, nt, &one);
+    off += align_up(one);
+  }
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
+  for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
+  for (int i = 0; i < nops; ++i) {  // per-operator set-up, as in a single solve
+    const int n = (int)ops[i]->n;
+    FAB_TRY(launch_zero(s, (double*)((char*)q[i].base + L[i].slots_step), (L[i].T - L[i].slots_step) / 8));
+    FAB_TRY(launch_zero(s, x[i], (size_t)n * nt));
+    FAB_TRY(hipMemcpyAsync(q[i].tvals, ctx->h_t, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    FAB_TRY(launch_rule(s, fun, nt, q[i].tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q[i].rz, q[i].rw,
+                        q[i].psi, q[i].st, 1, 0));
+    FAB_TRY(launch_copy_in(s, ops[i]->dtype, stream_grid(n, 2048), n, b[i], n, q[i].W, 1, 0));
+  }
+  const int nbr = std::min(nops, kBranches);
+  while ((int)ctx->branch.size() < kBranches) {
+    hipStream_t bs_ = nullptr;
+    hipEvent_t je = nullptr;
+    FAB_TRY(hipStreamCreateWithFlags(&bs_, hipStreamNonBlocking));
+    FAB_TRY(hipEventCreateWithFlags(&je, hipEventDisableTiming));
+    ctx->branch.push_back(bs_);
+    ctx->join.push_back(je);
+  }
+  if (!ctx->fork) FAB_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  std::vector<uintptr_t> key = {(uintptr_t)nops, (uintptr_t)fun, (uintptr_t)nt, (uintptr_t)work,
+                                (uintptr_t)p->m, (uintptr_t)p->k, (uintptr_t)p->d, (uintptr_t)p->zeta,
+                                (uintptr_t)p->seed, (uintptr_t)rule_nodes(fun, p)};
+  uint64_t tolbits;
+  std::memcpy(&tolbits, &p->tol, 8);
+  key.push_back((uintptr_t)tolbits);
+  for (int i = 0; i < nops; ++i) {
+    key.push_back((uintptr_t)ops[i]);
+    key.push_back((uintptr_t)x[i]);
+  }
+  auto cycle_of = [&](int i, hipStream_t st) {
+    Batch B;
+    B.ldx = ops[i]->n;
+    return enqueue_cycle(ctx, st, ops[i], p, fun, nt, L[i], q[i], x[i], ctx->h_rep + i, true, nullptr, B);
+  };
+  if (!ctx->timing && (key != ctx->ragged_key || !ctx->ragged_exec)) {
+    if (ctx->ragged_exec) {
+      (void)hipGraphExecDestroy(ctx->ragged_exec);
+      ctx->ragged_exec = nullptr;
+    }
+    FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    fab_status es = FAB_OK;
+    hipError_t he = hipEventRecord(ctx->fork, s);
+    for (int j = 0; j < nbr && he == hipSuccess; ++j) he = hipStreamWaitEvent(ctx->branch[j], ctx->fork, 0);
+    for (int i = 0; i < nops && he == hipSuccess && es == FAB_OK; ++i) es = cycle_of(i, ctx->branch[i % nbr]);
+    for (int j = 0; j < nbr && he == hipSuccess && es == FAB_OK; ++j) {
+      he = hipEventRecord(ctx->join[j], ctx->branch[j]);
+      if (he == hipSuccess) he = hipStreamWaitEvent(s, ctx->join[j], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s, &graph);  // always end the capture
+    if (es != FAB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return es;
+    }
+    if (he != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(he, "ragged capture", __LINE__);
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture", __LINE__);
+    const hipError_t ie = hipGraphInstantiate(&ctx->ragged_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      ctx->ragged_exec = nullptr;
+      return hip_fail(ie, "hipGraphInstantiate", __LINE__);
+    }
+    ctx->ragged_key = key;
+  }
+  std::vector<Track> tr(nops);
+  int remaining = nops;
+  for (int c = 0; c < p->max_cycles && remaining > 0; ++c) {
+    if (ctx->timing) {  // timing mode: the same cycles enqueued one operator after another
+      for (int i = 0; i < nops; ++i) {
+        const fab_status es = cycle_of(i, s);
+        if (es != FAB_OK) return es;
+      }
+    } else {
+      FAB_TRY(hipGraphLaunch(ctx->ragged_exec, s));
+    }
+    FAB_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < nops; ++i)
+      if (!tr[i].finished && track_report(tr[i], ctx->h_rep[i], c)) --remaining;
+  }
+  return finish_tracks(tr, p, h_info, 1);
 }
 
 fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt, const void* b,

