@@ -4,6 +4,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <type_traits>
+
 namespace fab {
 
 constexpr int kThreads = 256;      // threads per block of the streaming kernels
@@ -126,9 +128,12 @@ struct Report {
 
 // Batched solves: member r of a batch owns a copy of the single-solve workspace at byte offset
 // r * bs; kernels launched with gridDim.y = members shift their workspace pointers with bat().
+// (Byte arithmetic on a char pointer, not an integer, so the compiler still sees a pointer derived
+// from the kernel argument and keeps global-memory instructions.)
 template <typename P>
 __device__ __forceinline__ P* bat(P* p, size_t bs, int r) {
-  return reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)r * bs);
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(p) + (size_t)r * bs);
 }
 template <typename P>
 __device__ __forceinline__ P* bat(P* p, size_t bs) {

@@ -328,20 +328,18 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
 // ---------------------------------------------------------------------------------------------
 // Sketch-space modified Gram-Schmidt of step j, one wavefront (no barriers).  Element e of the
 // d-vector lives in lane e % 64, slot e / 64 (PER slots per lane, d <= 64 PER).
-// slots_cur: kSlots x d partial sketches of z; slots_next: the other set, zeroed here for step j+1.
-// U: d x (m+1) sketched basis (column j+1 written); R: (m+1) x m Hessenberg (column j written).
+// slots_cur: kSlots x d partial sketches of z (summed here in a fixed order); U: d x (m+1)
+// sketched basis.  When `coef` is given, lane 0 stores the window coefficients r_ij there (index
+// i - lo, i = lo..j), 1/rho in *inv and the outcome (1 = a new basis vector) in *ok; when `write`,
+// the wavefront also stores R column j, U column j+1 and the step's state, and zeroes slots_next
+// (the other set, accumulated by step j+1).
 // ---------------------------------------------------------------------------------------------
 template <int PER>
-__global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ slots_cur,
-                                             double* __restrict__ slots_next, double* __restrict__ U,
-                                             double* __restrict__ R, State* __restrict__ st, size_t bs) {
-  st = bat(st, bs);
-  if (st->brk || st->done) return;
-  slots_cur = bat(slots_cur, bs);
-  slots_next = bat(slots_next, bs);
-  U = bat(U, bs);
-  R = bat(R, bs);
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ slots_cur,
+                                          double* __restrict__ slots_next, double* __restrict__ U,
+                                          double* __restrict__ R, State* __restrict__ st, bool write,
+                                          double* coef, double* inv_out, int* ok_out) {
+  const int lane = threadIdx.x & 63;
   const int lo = max(0, j - k + 1);
   double u[PER];
 #pragma unroll
@@ -354,7 +352,8 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
     }
     u[q] = s;
   }
-  for (int i = lane; i < kSlots * d; i += 64) slots_next[i] = 0.0;
+  if (write)
+    for (int i = lane; i < kSlots * d; i += 64) slots_next[i] = 0.0;
   double loc = 0.0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
@@ -372,7 +371,8 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
     const double r = wave_sum(loc);
 #pragma unroll
     for (int q = 0; q < PER; ++q) u[q] -= r * ui[q];
-    if (lane == 0) {
+    if (coef && lane == 0) coef[i - lo] = r;
+    if (write && lane == 0) {
       R[(size_t)j * (m + 1) + i] = r;
       st->upd_coef[i - lo] = r;
     }
@@ -384,7 +384,11 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
   const bool finite = isfinite(rho) && isfinite(raw2);
   const bool breakdown = !(rho > 64.0 * 2.220446049250313e-16 * sqrt(raw2));
   if (!finite || breakdown) {
-    if (lane == 0) {
+    if (coef && lane == 0) {
+      *ok_out = 0;
+      *inv_out = 0.0;
+    }
+    if (write && lane == 0) {
       st->brk = 1;
       st->meff = j + 1;
       if (!finite) st->nonfinite = 1;
@@ -392,16 +396,91 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
     return;
   }
   const double inv = 1.0 / rho;
-  double* Un = U + (size_t)(j + 1) * d;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = lane + 64 * q;
-    if (e < d) Un[e] = u[q] * inv;
+  if (coef && lane == 0) {
+    *ok_out = 1;
+    *inv_out = inv;
   }
-  if (lane == 0) {
-    R[(size_t)j * (m + 1) + j + 1] = rho;
-    st->inv_rho = inv;
-    st->step_lo = lo;
+  if (write) {
+    double* Un = U + (size_t)(j + 1) * d;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = lane + 64 * q;
+      if (e < d) Un[e] = u[q] * inv;
+    }
+    if (lane == 0) {
+      R[(size_t)j * (m + 1) + j + 1] = rho;
+      st->inv_rho = inv;
+      st->step_lo = lo;
+    }
+  }
+}
+
+template <int PER>
+__global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ slots_cur,
+                                             double* __restrict__ slots_next, double* __restrict__ U,
+                                             double* __restrict__ R, State* __restrict__ st, size_t bs) {
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  orth_wave<PER>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, true, nullptr,
+                 nullptr, nullptr);
+}
+
+// Step j's Gram-Schmidt and window update in one launch (d <= 256).  Blocks of 1 + 4 wavefronts:
+// the first redoes the sketch-space Gram-Schmidt (the same fixed-order sums in every block, so
+// every block gets the same coefficients; block 0 also stores R, U and the state) while the other
+// four already load their elements (z and the window); after the barrier they update.  (A
+// wavefront's loads complete in order, so the Gram-Schmidt gets a wavefront of its own: streaming
+// loads issued by the same wavefront would hold up its reads of the sketch.)  Saves the separate
+// single-wavefront launch, whose latency would sit between product and update.
+constexpr int kUpdPer = 4;
+constexpr int kOuThreads = 64 + kThreads;
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
+                                                          const double* __restrict__ slots_cur,
+                                                          double* __restrict__ slots_next, double* __restrict__ U,
+                                                          double* __restrict__ R, State* __restrict__ st, size_t bs) {
+  __shared__ double s_coef[kMaxM + 1];
+  __shared__ double s_inv;
+  __shared__ int s_ok;
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  W = bat(W, bs);
+  const int lo = max(0, j - k + 1), nw = j - lo + 1;
+  T* out = W + (size_t)(j + 1) * n;
+  const T* base = W + (size_t)lo * n;
+  if (threadIdx.x < 64) {
+    orth_wave<4>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, blockIdx.x == 0,
+                 s_coef, &s_inv, &s_ok);
+    __syncthreads();
+    return;
+  }
+  const size_t i0 = (size_t)blockIdx.x * (kThreads * kUpdPer) + (threadIdx.x - 64);
+  T zv[kUpdPer], wv[kUpdPer][KMAX];
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    const size_t i = i0 + (size_t)e * kThreads;
+    const bool in = i < (size_t)n;
+    zv[e] = in ? __builtin_nontemporal_load(&out[i]) : T(0);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      wv[e][q] = (in && q < nw) ? __builtin_nontemporal_load(&base[(size_t)q * n + i]) : T(0);
+  }
+  __syncthreads();
+  if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
+  const double inv = s_inv;
+  double coef[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? s_coef[q] : 0.0;
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    const size_t i = i0 + (size_t)e * kThreads;
+    if (i < (size_t)n) {
+      double v = (double)zv[e];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
+      __builtin_nontemporal_store((T)(v * inv), &out[i]);
+    }
   }
 }
 
@@ -640,6 +719,24 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
     hipLaunchKernelGGL(k_orth<16>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
   else
     hipLaunchKernelGGL(k_orth<32>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth_update(hipStream_t s, int dtype, int n, int j, int k, int m, int d, void* W,
+                              const double* cur, double* next, double* U, double* R, State* st, int nb, size_t bs) {
+  const int grid = (int)((n + kThreads * kUpdPer - 1) / (kThreads * kUpdPer));
+  const dim3 g(grid, nb);
+  if (dtype == 0) {
+    if (k <= 4)
+      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, st, bs);
+    else
+      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, st, bs);
+  } else {
+    if (k <= 4)
+      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, st, bs);
+    else
+      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, st, bs);
+  }
   return hipGetLastError();
 }
 
