@@ -296,7 +296,9 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), d,
                                  p->zeta, p->seed, set_cur, q.st, nb, B.G, bs));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
-      if (d <= 256 && p->k <= 8) {  // Gram-Schmidt folded into the update launch
+      // Gram-Schmidt folded into the update launch for single solves (every block of the update
+      // redoes it; in a batch that redundancy would multiply by the members)
+      if (nb == 1 && d <= 256 && p->k <= 8) {
         FAB_TRY(launch_orth_update(s, dt, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
@@ -557,7 +559,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   *G_out = 1;
   if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
   if (ctx->force_group > 0) {
-    *G_out = ctx->force_group;
+    *G_out = (p->d <= 256) ? ctx->force_group : 1;  // the grouped kernel serves d <= 256
     return FAB_OK;
   }
   for (const auto& t : ctx->tuned)
@@ -577,7 +579,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   // candidates: one member per block, or a group of 16 (the MFMA sketch's N-tile; finished members
   // and padding cost gathers of nothing)
   for (int G = 1; G <= 16 && err == hipSuccess; G += 15) {
-    if (G > 1 && spmv_sketch_lds(dt, 0, d, G, p->zeta) > group_lds_max()) break;
+    if (G > 1 && (d > 256 || spmv_sketch_lds(dt, 0, d, G, p->zeta) > group_lds_max())) break;
     const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta);
     void* x0 = q.W;
     void* y0 = (char*)q.W + (size_t)n * es;

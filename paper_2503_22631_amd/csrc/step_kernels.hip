@@ -118,14 +118,17 @@ __device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* _
 }
 
 // LDS layout of the fused kernel: bins (G*d FP64), then for member groups (G > 1) the tile's
-// products (kThreads*G values) and generated S entries (kThreads*zeta rows as uint16, kThreads sign
-// words), then the CSR chunk (kChunk values and column indices).
+// products (kThreads*G values) and S's column masks (kThreads*ceil(d/16) words), then the CSR chunk
+// (kChunk values and column indices).
 __host__ __device__ inline size_t spmv_lds_bins(int mode, int d, int G) {
   return (mode == 2) ? 0 : (((size_t)G * d * 8 + 15) & ~(size_t)15);
 }
-__host__ __device__ inline size_t spmv_lds_group(int mode, int G, int zeta, size_t es) {
+// Grouped kernel (d <= 256): per tile row, one 32-bit word per 16-bin slice of S's column: bit b
+// = the row hits bin 16 slice + b, bit 16 + b = that entry is negative.
+__host__ __device__ inline size_t spmv_lds_group(int mode, int G, int d, size_t es) {
   if (mode == 2 || G <= 1) return 0;
-  return (((size_t)kThreads * G * es + (size_t)kThreads * zeta * 2 + (size_t)kThreads * 4) + 15) & ~(size_t)15;
+  const size_t nmt = (size_t)(d + 15) / 16;
+  return (((size_t)kThreads * G * es + (size_t)kThreads * nmt * 4) + 15) & ~(size_t)15;
 }
 
 // row_dot for MU batch members at once (the same row, entries and values, MU vectors): all
@@ -159,6 +162,12 @@ constexpr int kMembersInFlight = 4;  // batch members whose gathers are issued t
 constexpr int kGroup = 16;           // members per block in the grouped (batched) kernel: one MFMA N-tile
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// BF16 by truncation (the upper half of the FP32 bits) and back.
+__device__ __forceinline__ short bf16_trunc(float x) { return (short)(__float_as_uint(x) >> 16); }
+__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
 
 template <typename T, int MODE, int ZMAX, bool GRP>
 __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
@@ -175,12 +184,11 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
   const int r0 = blockIdx.y * G;
   const int gn = min(G, nb - r0);
   const size_t o_grp = spmv_lds_bins(MODE, d, G);
-  const size_t o_chk = o_grp + spmv_lds_group(MODE, G, zeta, sizeof(T));
+  const size_t o_chk = o_grp + spmv_lds_group(MODE, G, d, sizeof(T));
+  const int nmt = (d + 15) >> 4;                       // 16-bin slices of the sketch
   double* bins = reinterpret_cast<double*>(smem_raw);  // [bin][member]
   T* ztile = reinterpret_cast<T*>(smem_raw + o_grp);   // [row][member]        (G > 1)
-  uint16_t* rtile = reinterpret_cast<uint16_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T));
-  uint32_t* stile = reinterpret_cast<uint32_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T) +
-                                                (size_t)kThreads * zeta * 2);
+  uint32_t* mtile = reinterpret_cast<uint32_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T));  // [row][slice]
   T* sv = reinterpret_cast<T*>(smem_raw + o_chk);
   int* sc = reinterpret_cast<int*>(smem_raw + o_chk + kChunk * sizeof(T));
   uint32_t live_mask = 0;  // members still iterating (block-uniform)
@@ -275,41 +283,77 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
     }
     if (MODE != 2 && GRP) {
       // The row's S entries are generated after the products (so the gathers are in flight first)
-      // and shared through LDS.  Then the tile's sketch for the kGroup members is a dense FP64
+      // and kept as per-slice masks.  The tile's sketch for the kGroup members is then a dense
       // contraction on the matrix cores, bins(d x 16) += S_tile(d x rows) Z_tile(rows x 16):
-      // wavefront w owns 16-bin slices w, w+4, ...; the +-1 entries of S_tile are formed on the fly
-      // from each row's zeta generated rows (no dense S in LDS), and the scale 1/sqrt(zeta) is
-      // applied to the result.  v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]
-      // and holds D[4r + l/16][l%16], r = 0..3.
+      // wavefront w owns 16-bin slices w, w+4, ...; the +-1 entries of S_tile come from the masks
+      // (no dense S in LDS); the scale 1/sqrt(zeta) is applied to the result.
+      //   FP64 data: v_mfma_f64_16x16x4 (lane l: A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16]).
+      //   FP32 data: v_mfma_f32_16x16x16bf16 on three BF16 parts of z (hi, mid, lo by truncation;
+      //   they sum to z within 2^-24 |z|, and +-1 times a BF16 value is exact), FP32 accumulation
+      //   (lane l: A[l%16][4(l/16)+v], B[4(l/16)+v][l%16], D[4(l/16)+r][l%16]).
       if (live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+      for (int q = 0; q < nmt; ++q) mtile[threadIdx.x * nmt + q] = 0u;
+      if (live) {
 #pragma unroll
-      for (int l = 0; l < ZMAX; ++l)
-        if (l < zeta) rtile[threadIdx.x * zeta + l] = (uint16_t)(live ? rows[l] : 0);
-      stile[threadIdx.x] = sb;
+        for (int l = 0; l < ZMAX; ++l)
+          if (l < zeta) {
+            const int bq = rows[l];
+            mtile[threadIdx.x * nmt + (bq >> 4)] |= (1u << (bq & 15)) | ((((sb >> l) & 1u)) << (16 + (bq & 15)));
+          }
+      }
       __syncthreads();
       const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
       const int nrow = min(kThreads, n - row0);
-      const int nmt = (d + 15) >> 4;
       const double dscale = (double)scale;
+      const int col = lane & 15, bit = lane & 15;
       for (int mt = wv; mt < nmt; mt += kThreads / 64) {
-        const int bq = mt * 16 + (lane & 15);  // this lane's bin in the A operand
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0r = 0; k0r < nrow; k0r += 4) {
-          const int k = k0r + (lane >> 4);
-          double a = 0.0, bz = 0.0;
-          if (k < nrow) {
-            const uint16_t* rk = rtile + k * zeta;
-            const uint32_t sg = stile[k];
-            for (int l = 0; l < zeta; ++l)
-              if ((int)rk[l] == bq) a = ((sg >> l) & 1u) ? -1.0 : 1.0;
-            bz = (double)ztile[k * G + (lane & 15)];
+        if constexpr (sizeof(T) == 8) {
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          for (int k0r = 0; k0r < nrow; k0r += 4) {
+            const int kk = k0r + (lane >> 4);
+            double a = 0.0, bz = 0.0;
+            if (kk < nrow) {
+              const uint32_t mk = mtile[kk * nmt + mt];
+              a = ((mk >> bit) & 1u) ? (((mk >> (16 + bit)) & 1u) ? -1.0 : 1.0) : 0.0;
+              bz = (double)ztile[kk * G + col];
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc, 0, 0, 0);
           }
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc, 0, 0, 0);
-        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int bb = mt * 16 + 4 * r + (lane >> 4);
-          if (bb < d) bins[bb * G + (lane & 15)] += acc[r] * dscale;  // owner-exclusive (bin, member)
+          for (int r = 0; r < 4; ++r) {
+            const int bb = mt * 16 + 4 * r + (lane >> 4);
+            if (bb < d) bins[bb * G + col] += acc[r] * dscale;  // owner-exclusive (bin, member)
+          }
+        } else {
+          v4f acc = {0.f, 0.f, 0.f, 0.f};
+          for (int k0r = 0; k0r < nrow; k0r += 16) {
+            v4s a, b1, b2, b3;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int kk = k0r + 4 * (lane >> 4) + v;
+              float av = 0.f, zf = 0.f;
+              if (kk < nrow) {
+                const uint32_t mk = mtile[kk * nmt + mt];
+                av = ((mk >> bit) & 1u) ? (((mk >> (16 + bit)) & 1u) ? -1.f : 1.f) : 0.f;
+                zf = (float)ztile[kk * G + col];
+              }
+              a[v] = bf16_trunc(av);
+              const float h = bf16_value(bf16_trunc(zf));
+              const float r1 = zf - h;
+              const float mdl = bf16_value(bf16_trunc(r1));
+              b1[v] = bf16_trunc(h);
+              b2[v] = bf16_trunc(mdl);
+              b3[v] = bf16_trunc(r1 - mdl);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b2, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b3, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int bb = mt * 16 + 4 * (lane >> 4) + r;
+            if (bb < d) bins[bb * G + col] += (double)acc[r] * dscale;  // owner-exclusive (bin, member)
+          }
         }
       }
     }
@@ -632,7 +676,8 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 // ------------------------------------------------------------------------------------ launchers
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta) {
   const size_t es = dtype == 0 ? 8 : 4;
-  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, zeta, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
+  (void)zeta;
+  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, d, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
 }
 
 template <typename T>
