@@ -165,7 +165,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
 fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void* work, size_t work_bytes);
 
 /* Sx[d] (FP64) = S x for the sparse sign matrix defined by (n, d, zeta, seed);
- * x has dtype. */
+ * x has dtype.  work: at least 128 d bytes (the slot copies of the accumulators). */
 fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed,
                             int32_t dtype, const void* x, double* Sx, void* work, size_t work_bytes);
 

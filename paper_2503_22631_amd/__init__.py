@@ -19,6 +19,7 @@ from . import _lib
 from ._lib import FabError, fab_info, fab_params
 
 FUN = {"exp": 0, "invsqrt": 1}
+SKETCH_APPLY_WORK_PER_ROW = 128   # fab_sketch_apply's workspace: 128 bytes per sketch row
 METHOD = {"sketched": 0, "plain": 1}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
@@ -268,7 +269,7 @@ def spmv(op: CSROperator, xv: torch.Tensor) -> torch.Tensor:
 
 def sketch_apply(ctx: Context, xv: torch.Tensor, d: int, zeta: int, seed: int) -> torch.Tensor:
     out = torch.empty(d, dtype=torch.float64, device=ctx.device)
-    ws = torch.empty(8 * 8 * d + 256, dtype=torch.uint8, device=ctx.device)
+    ws = torch.empty(SKETCH_APPLY_WORK_PER_ROW * d + 256, dtype=torch.uint8, device=ctx.device)
     _lib.check(ctx.lib.fab_sketch_apply(ctx.handle, xv.numel(), d, zeta, int(seed), DTYPE[xv.dtype],
                                         _ptr(xv.contiguous()), _ptr(out), _ptr(ws), ws.numel()),
                "fab_sketch_apply", ok=(0,))

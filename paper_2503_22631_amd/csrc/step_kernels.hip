@@ -378,7 +378,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __re
 // the wavefront also stores R column j, U column j+1 and the step's state, and zeroes slots_next
 // (the other set, accumulated by step j+1).
 // ---------------------------------------------------------------------------------------------
-template <int PER>
+// KW > 0: the window's KW columns of U are loaded together with the slot sums (one memory round
+// trip instead of one per window column; requires j - lo + 1 <= KW).
+template <int PER, int KW>
 __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ slots_cur,
                                           double* __restrict__ slots_next, double* __restrict__ U,
                                           double* __restrict__ R, State* __restrict__ st, bool write,
@@ -386,6 +388,16 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
   const int lane = threadIdx.x & 63;
   const int lo = max(0, j - k + 1);
   double u[PER];
+  double upre[KW > 0 ? KW : 1][PER];
+  if (KW > 0) {
+#pragma unroll
+    for (int w = 0; w < (KW > 0 ? KW : 1); ++w)
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = lane + 64 * q;
+        upre[w][q] = (lo + w <= j && e < d) ? U[(size_t)(lo + w) * d + e] : 0.0;
+      }
+  }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = lane + 64 * q;
@@ -402,23 +414,34 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
 #pragma unroll
   for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
   const double raw2 = wave_sum(loc);
-  for (int i = lo; i <= j; ++i) {
-    const double* Ui = U + (size_t)i * d;
-    double ui[PER];
-    loc = 0.0;
+  // one modified Gram-Schmidt step against window column i (values ui)
+  auto mgs = [&](int i, const double* ui) {
+    double l2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = lane + 64 * q;
-      ui[q] = (e < d) ? Ui[e] : 0.0;
-      loc += ui[q] * u[q];
-    }
-    const double r = wave_sum(loc);
+    for (int q = 0; q < PER; ++q) l2 += ui[q] * u[q];
+    const double r = wave_sum(l2);
 #pragma unroll
     for (int q = 0; q < PER; ++q) u[q] -= r * ui[q];
     if (coef && lane == 0) coef[i - lo] = r;
     if (write && lane == 0) {
       R[(size_t)j * (m + 1) + i] = r;
       st->upd_coef[i - lo] = r;
+    }
+  };
+  if constexpr (KW > 0) {
+#pragma unroll
+    for (int w = 0; w < KW; ++w)
+      if (lo + w <= j) mgs(lo + w, upre[w]);
+  } else {
+    for (int i = lo; i <= j; ++i) {
+      const double* Ui = U + (size_t)i * d;
+      double ui[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = lane + 64 * q;
+        ui[q] = (e < d) ? Ui[e] : 0.0;
+      }
+      mgs(i, ui);
     }
   }
   loc = 0.0;
@@ -465,8 +488,8 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
                                              double* __restrict__ R, State* __restrict__ st, size_t bs) {
   st = bat(st, bs);
   if (st->brk || st->done) return;
-  orth_wave<PER>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, true, nullptr,
-                 nullptr, nullptr);
+  orth_wave<PER, 0>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, true, nullptr,
+                    nullptr, nullptr);
 }
 
 // Step j's Gram-Schmidt and window update in one launch (d <= 256).  Blocks of 1 + 4 wavefronts:
@@ -494,8 +517,8 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   T* out = W + (size_t)(j + 1) * n;
   const T* base = W + (size_t)lo * n;
   if (threadIdx.x < 64) {
-    orth_wave<4>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, blockIdx.x == 0,
-                 s_coef, &s_inv, &s_ok);
+    orth_wave<4, KMAX>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st,
+                       blockIdx.x == 0, s_coef, &s_inv, &s_ok);
     __syncthreads();
     return;
   }
