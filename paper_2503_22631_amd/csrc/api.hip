@@ -28,8 +28,8 @@ hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cu
                        double* R, State* st, int nb, size_t bs);
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
                          size_t bs);
-hipError_t launch_orth_update(hipStream_t, int dtype, int n, int j, int k, int m, int d, void* W, const double* cur,
-                              double* next, double* U, double* R, State* st, int nb, size_t bs);
+hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
+                              const double* cur, double* next, double* U, double* R, State* st, int nb, size_t bs);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -299,7 +299,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
       if (nb == 1 && d <= 256 && p->k <= 8) {
-        FAB_TRY(launch_orth_update(s, dt, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
+        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
         FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));

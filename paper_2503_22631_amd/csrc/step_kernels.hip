@@ -492,15 +492,87 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
                     nullptr, nullptr);
 }
 
-// Step j's Gram-Schmidt and window update in one launch (d <= 256).  Blocks of 1 + 4 wavefronts:
-// the first redoes the sketch-space Gram-Schmidt (the same fixed-order sums in every block, so
-// every block gets the same coefficients; block 0 also stores R, U and the state) while the other
-// four already load their elements (z and the window); after the barrier they update.  (A
-// wavefront's loads complete in order, so the Gram-Schmidt gets a wavefront of its own: streaming
-// loads issued by the same wavefront would hold up its reads of the sketch.)  Saves the separate
-// single-wavefront launch, whose latency would sit between product and update.
-constexpr int kUpdPer = 4;
-constexpr int kOuThreads = 64 + kThreads;
+// Step j's Gram-Schmidt and window update in one launch (d <= 256), with persistent blocks.
+// Blocks of 1 + 4 wavefronts: the first redoes the sketch-space Gram-Schmidt (the same
+// fixed-order sums in every block, so every block gets the same coefficients; block 0 also stores
+// R, U and the state) while the other four load their first batch of elements (z and the window).
+// After the barrier they stream the block's batches of kOuBatch elements, and the loads of the
+// next batch are issued before the current one is updated and stored, so reads and writes of the
+// whole grid overlap instead of running in two phases.  (A wavefront's loads complete in order, so
+// the Gram-Schmidt gets a wavefront of its own: streaming loads issued by the same wavefront would
+// hold up its reads of the sketch.)  Load indices are clamped into the vector instead of guarded:
+// with no branch around a load, the compiler can count the loads in flight and wait for one batch
+// only.  Saves the separate single-wavefront launch, whose latency would sit between product and
+// update, and runs the Gram-Schmidt once per block rather than once per 1024 elements.
+constexpr int kOuPer = 2;                     // elements per streaming thread and batch
+constexpr int kOuThreads = 64 + kThreads;     // Gram-Schmidt wavefront + streaming wavefronts
+constexpr int kOuBatch = kThreads * kOuPer;   // elements per block and batch
+constexpr int kOuBlocksPerCu = 2;
+
+// Raw buffer accesses (untyped, byte offsets): the hardware checks every lane's offset against the
+// resource's size, returns 0 for a load beyond it and drops a store beyond it, so a ragged batch
+// needs no branch.  Word 3 of the gfx9-family descriptor: 32-bit data format (a valid format is
+// required for untyped accesses), all other fields zero.  Cache policy 2 = non-temporal.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kBufNt = 2;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufWord3);
+}
+__device__ __forceinline__ double buf_load_nt(__amdgpu_buffer_rsrc_t r, int off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufNt));
+}
+__device__ __forceinline__ float buf_load_nt(__amdgpu_buffer_rsrc_t r, int off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kBufNt));
+}
+__device__ __forceinline__ void buf_store_nt(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kBufNt);
+}
+__device__ __forceinline__ void buf_store_nt(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kBufNt);
+}
+
+// Elements of one batch: those of [b0, b0 + kOuBatch) below n (none when b0 >= n: a size-0
+// resource, whose loads return 0 without touching memory).
+__device__ __forceinline__ int ou_count(int n, int64_t b0) {
+  return b0 < n ? (int)min((int64_t)kOuBatch, (int64_t)n - b0) : 0;
+}
+
+template <typename T, int KMAX>
+__device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, int nw,
+                                        int64_t b0, int t, T (&zv)[kOuPer], T (&wv)[kOuPer][KMAX]) {
+  const int cnt = ou_count(n, b0);
+  const int64_t o = cnt ? b0 : 0;
+  const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + o, cnt * (int)sizeof(T));
+  __amdgpu_buffer_rsrc_t rw[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q)  // columns beyond the window: size 0 (their coefficients are 0)
+    rw[q] = buf_rsrc(base + (size_t)min(q, nw - 1) * n + o, q < nw ? cnt * (int)sizeof(T) : 0);
+#pragma unroll
+  for (int e = 0; e < kOuPer; ++e) {
+    const int off = (e * kThreads + t) * (int)sizeof(T);
+    zv[e] = buf_load_nt(rz, off, T());
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) wv[e][q] = buf_load_nt(rw[q], off, T());
+  }
+}
+
+// FP64 arithmetic for either value type: z is nearly in the span of the window, so the difference
+// cancels; only the stored w_{j+1} is rounded to T.  coef is zero beyond the window.
+template <typename T, int KMAX>
+__device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0, int t, const double (&coef)[KMAX],
+                                         double inv, const T (&zv)[kOuPer], const T (&wv)[kOuPer][KMAX]) {
+  const int cnt = ou_count(n, b0);
+  const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + (cnt ? b0 : 0), cnt * (int)sizeof(T));
+#pragma unroll
+  for (int e = 0; e < kOuPer; ++e) {
+    double v = (double)zv[e];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
+    buf_store_nt((T)(v * inv), rz, (e * kThreads + t) * (int)sizeof(T));
+  }
+}
 
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
@@ -522,32 +594,28 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
     __syncthreads();
     return;
   }
-  const size_t i0 = (size_t)blockIdx.x * (kThreads * kUpdPer) + (threadIdx.x - 64);
-  T zv[kUpdPer], wv[kUpdPer][KMAX];
-#pragma unroll
-  for (int e = 0; e < kUpdPer; ++e) {
-    const size_t i = i0 + (size_t)e * kThreads;
-    const bool in = i < (size_t)n;
-    zv[e] = in ? __builtin_nontemporal_load(&out[i]) : T(0);
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      wv[e][q] = (in && q < nw) ? __builtin_nontemporal_load(&base[(size_t)q * n + i]) : T(0);
-  }
+  // batches blockIdx.x, blockIdx.x + gridDim.x, ...; the launch keeps gridDim.x <= the batch count
+  const int t = threadIdx.x - 64;
+  const int nbat = (n + kOuBatch - 1) / kOuBatch;
+  const int cnt = (nbat - 1 - (int)blockIdx.x) / (int)gridDim.x + 1;
+  auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * kOuBatch; };
+  T za[kOuPer], wa[kOuPer][KMAX], zb[kOuPer], wb[kOuPer][KMAX];
+  ou_load<T, KMAX>(out, base, n, nw, start(0), t, za, wa);
   __syncthreads();
   if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
   const double inv = s_inv;
   double coef[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? s_coef[q] : 0.0;
-#pragma unroll
-  for (int e = 0; e < kUpdPer; ++e) {
-    const size_t i = i0 + (size_t)e * kThreads;
-    if (i < (size_t)n) {
-      double v = (double)zv[e];
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
-      __builtin_nontemporal_store((T)(v * inv), &out[i]);
-    }
+  // two register sets in turn; the prefetch past the block's last batch has size 0 (no memory
+  // traffic), so every trip issues the same loads and stores
+  for (int it = 0;;) {
+    ou_load<T, KMAX>(out, base, n, nw, start(it + 1), t, zb, wb);
+    ou_store<T, KMAX>(out, n, start(it), t, coef, inv, za, wa);
+    if (++it >= cnt) break;
+    ou_load<T, KMAX>(out, base, n, nw, start(it + 1), t, za, wa);
+    ou_store<T, KMAX>(out, n, start(it), t, coef, inv, zb, wb);
+    if (++it >= cnt) break;
   }
 }
 
@@ -790,9 +858,10 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_orth_update(hipStream_t s, int dtype, int n, int j, int k, int m, int d, void* W,
+hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
                               const double* cur, double* next, double* U, double* R, State* st, int nb, size_t bs) {
-  const int grid = (int)((n + kThreads * kUpdPer - 1) / (kThreads * kUpdPer));
+  const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
+  const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
   if (dtype == 0) {
     if (k <= 4)
