@@ -100,8 +100,13 @@ fab_status fab_destroy(fab_ctx* ctx);
 
 /* Wrap a CSR matrix (n x n) without copying.  rowptr[n+1], colind[nnz] are
  * int32 (ascending columns per row are not required); vals[nnz] are FP64 or FP32
- * (dtype).  BORROWS the three arrays: they must outlive the operator.
- * Errors: FAB_E_INVALID (n <= 0, nnz < 0, nnz >= 2^31, null pointers). */
+ * (dtype).  BORROWS the three arrays: they must outlive the operator, and their
+ * structure must not change while it exists.  Creation checks the structure on
+ * the device (row pointers non-decreasing from 0 to nnz, column indices in
+ * [0, n)), after the work already queued on the caller's stream, and
+ * synchronises the context's stream.
+ * Errors: FAB_E_INVALID (n <= 0, nnz < 0, nnz >= 2^31, null pointers, a
+ * malformed CSR), FAB_E_UNSUPPORTED (n >= 2^31), FAB_E_HIP. */
 fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
                           const int32_t* colind, const void* vals, int32_t dtype, fab_op** op);
 fab_status fab_op_destroy(fab_op* op);

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfab.so")
-SOURCES = ["api.hip", "step_kernels.hip", "cycle_kernels.hip", "transpose.hip"]
+SOURCES = ["api.hip", "step_kernels.hip", "cycle_kernels.hip", "operator.hip"]
 ARCH = os.environ.get("FAB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -21,6 +21,7 @@ hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st, int nb, int G, size_t bs);
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta);
+int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta);
 hipError_t configure_cycle_kernels();
 hipError_t configure_step_kernels();
 size_t group_lds_max();
@@ -90,7 +91,6 @@ struct fab_ctx {
   double* d_part = nullptr;  // kDotBlocks partial sums of fab_dot (device)
   double* h_t = nullptr;  // pinned staging for the time points
   int num_cu = 256;
-  size_t lds_per_cu = 160 * 1024;
   // benchmark timing: events around each SpMV+sketch launch (2 per step) and the loop end
   bool timing = false;
   std::vector<hipEvent_t> tev;
@@ -252,10 +252,10 @@ static fab_status hip_fail(hipError_t e, const char* expr, int line) {
 static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s); }
 
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
-// Blocks of the fused SpMV + sketch kernel: as many as fit on the device at once (LDS-limited).
+// Blocks of the fused SpMV + sketch kernel: as many as are resident on the device at once (the
+// occupancy calculator's count per CU, at most 8).
 static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1, int zeta = 1) {
-  const size_t lds = std::max<size_t>(spmv_sketch_lds(dtype, mode, d, G, zeta), 1);
-  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, ctx->lds_per_cu / lds));
+  const int per_cu = std::max(1, std::min(8, spmv_blocks_per_cu(dtype, mode, d, G, zeta)));
   return stream_grid(n, per_cu * ctx->num_cu);
 }
 
@@ -388,7 +388,6 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
     c->num_cu = prop.multiProcessorCount;
-    if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   }
   if (configure_cycle_kernels() != hipSuccess || configure_step_kernels() != hipSuccess) {
     delete c;
@@ -428,6 +427,21 @@ fab_status fab_destroy(fab_ctx* c) {
   return FAB_OK;
 }
 
+// Check a new operator's CSR structure on the device (every product indexes with it): row pointers
+// non-decreasing from 0 to nnz, column indices in [0, n).  FAB_E_INVALID when it is malformed.
+static fab_status validate_op(fab_ctx* ctx, const fab_op* o) {
+  hipStream_t s = ctx->work;
+  int* dflag = reinterpret_cast<int*>(ctx->d_part);  // the context's reduction buffer, free between calls
+  int flag = 0;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));  // the arrays may still be written on the caller's stream
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  FAB_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  FAB_TRY(launch_csr_validate(s, (int)o->n, (int)o->nnz, o->rowptr, o->colind, dflag));
+  FAB_TRY(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FAB_TRY(hipStreamSynchronize(s));
+  return flag ? FAB_E_INVALID : FAB_OK;
+}
+
 fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
                           const void* vals, int32_t dtype, fab_op** op) {
   if (!ctx || !op || n <= 0 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !rowptr || (nnz > 0 && (!colind || !vals)))
@@ -436,6 +450,11 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
   if (n >= ((int64_t)1 << 31)) return FAB_E_UNSUPPORTED;
   fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype, nullptr};
   if (!o) return FAB_E_HIP;
+  const fab_status st = validate_op(ctx, o);
+  if (st != FAB_OK) {
+    delete o;
+    return st;
+  }
   *op = o;
   return FAB_OK;
 }

@@ -1,11 +1,15 @@
-// CSR transpose on the device, for the adjoint solve on A^T.  The derivative of <c, f(t A) b> with
-// respect to b is f(t A^T) c (the adjoint identity <c, f(A) b> = <f(A^T) c, b>); the adjoint runs
-// the same restarted sketched Krylov method on A^T, so A^T is stored as a CSR matrix of its own.
+// Operator set-up on the device.
 //
-// Steps: validate the CSR structure (every later step indexes with it); count the entries of
-// every column; exclusive scan of the counts gives the row pointers of A^T; scatter every entry
-// (i, c, v) to row c of A^T through a per-row cursor; sort every row of A^T by column index, so
-// the result is canonical (independent of the order of the scatter's atomics).
+// Validation: every product kernel indexes x with colind and walks rows with rowptr, so
+// fab_csr_create refuses a malformed CSR before anything else touches it.
+//
+// Transpose, for the adjoint solve on A^T.  The derivative of <c, f(t A) b> with respect to b is
+// f(t A^T) c (the adjoint identity <c, f(A) b> = <f(A^T) c, b>); the adjoint runs the same
+// restarted sketched Krylov method on A^T, so A^T is stored as a CSR matrix of its own.
+// Steps: count the entries of every column; exclusive scan of the counts gives the row pointers of
+// A^T; scatter every entry (i, c, v) to row c of A^T through a per-row cursor; sort every row of
+// A^T by column index, so the result is canonical (independent of the order of the scatter's
+// atomics).
 #include "fab_internal.h"
 
 namespace fab {
@@ -14,6 +18,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 8;                          // items per thread
 constexpr int kScanBlock = kScanThreads * kScanPer;  // items per block
 
+// ---------------------------------------------------------------------------------- validation
 // flag bit 0: rowptr not monotone or rowptr[0] != 0 or rowptr[n] != nnz; bit 1: column out of range.
 __global__ void k_csr_validate(int n, int nnz, const int* __restrict__ rowptr, const int* __restrict__ colind,
                                int* __restrict__ flag) {
@@ -136,6 +141,7 @@ __global__ void k_sort_rows(int n, const int* __restrict__ rowptrT, int* __restr
   }
 }
 
+// ---------------------------------------------------------------------------------- transpose
 static int grid_for(int64_t items, int threads, int cap) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;

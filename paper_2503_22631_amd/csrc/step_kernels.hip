@@ -834,6 +834,46 @@ hipError_t configure_step_kernels() {
 
 size_t group_lds_max() { return kGroupLdsMax; }
 
+// The instantiation launch_spmv_sketch picks, for the occupancy query below.
+template <typename T, int M, int Z>
+static const void* spmv_kernel_mz(int G) {
+  if (G > 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, true>);
+  return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false>);
+}
+
+template <typename T>
+static const void* spmv_kernel(int mode, int zeta, int G) {
+  if (mode == 2) return spmv_kernel_mz<T, 2, 1>(G);
+  const int Z = zeta <= 1 ? 1 : zeta <= 4 ? 4 : zeta <= 8 ? 8 : zeta <= 16 ? 16 : 32;
+  if (mode == 0) {
+    switch (Z) {
+      case 1: return spmv_kernel_mz<T, 0, 1>(G);
+      case 4: return spmv_kernel_mz<T, 0, 4>(G);
+      case 8: return spmv_kernel_mz<T, 0, 8>(G);
+      case 16: return spmv_kernel_mz<T, 0, 16>(G);
+      default: return spmv_kernel_mz<T, 0, 32>(G);
+    }
+  }
+  switch (Z) {
+    case 1: return spmv_kernel_mz<T, 1, 1>(G);
+    case 4: return spmv_kernel_mz<T, 1, 4>(G);
+    case 8: return spmv_kernel_mz<T, 1, 8>(G);
+    case 16: return spmv_kernel_mz<T, 1, 16>(G);
+    default: return spmv_kernel_mz<T, 1, 32>(G);
+  }
+}
+
+// Blocks of the fused kernel resident per CU, from the runtime's occupancy calculator (registers,
+// LDS with its allocation granularity, wavefront slots), so that a grid of that many blocks per CU
+// runs in one pass with no trailing partial wave of blocks.
+int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta) {
+  const size_t lds = spmv_sketch_lds(dtype, mode, d, G, zeta);
+  const void* f = dtype == 0 ? spmv_kernel<double>(mode, zeta, G) : spmv_kernel<float>(mode, zeta, G);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st, int nb, int G, size_t bs) {

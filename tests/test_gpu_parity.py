@@ -437,7 +437,8 @@ def test_transpose_bit_exact(fab, ctx, build, dtype):
 
 
 def test_transpose_ragged_rows_and_bad_input(fab, ctx):
-    """Empty rows and columns, long rows, unsorted input columns; a malformed CSR is refused."""
+    """Empty rows and columns, long rows, unsorted input columns; a malformed CSR is refused at
+    creation (before any kernel indexes with it)."""
     import scipy.sparse as sp
     rng = np.random.default_rng(11)
     n = 3001
@@ -457,10 +458,13 @@ def test_transpose_ragged_rows_and_bad_input(fab, ctx):
     assert np.array_equal(ci.cpu().numpy(), T.indices)
     assert np.array_equal(va.cpu().numpy(), T.data)
     bad = colind.copy()
-    bad[17] = n                                    # column out of range: caught by the device check
-    op_bad = fab.CSROperator.from_arrays(ctx, M.indptr, bad, vals)
+    bad[17] = n                                    # column out of range: refused when the operator is made
     with pytest.raises(fab.FabError):
-        op_bad.transpose()
+        fab.CSROperator.from_arrays(ctx, M.indptr, bad, vals)
+    bad_rp = M.indptr.copy()
+    bad_rp[100] = bad_rp[101] + 1                  # row pointers not monotone
+    with pytest.raises(fab.FabError):
+        fab.CSROperator.from_arrays(ctx, bad_rp, colind, vals)
 
 
 def test_adjoint_solve_vs_kronecker(fab, ctx):
