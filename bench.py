@@ -35,7 +35,8 @@ WORKLOAD = {"workload": "convdiff_3d_N128_Pe50", "operator": "3-D 7-point convec
             "sketch_seed": 1, "b_seed": 0, "tol": 1e-8, "values": "f64"}
 HBM_PEAK_GBS = 8000.0
 METRIC = "f(A)b solves/s at rel err 1e-8 vs FP64 oracle; loop HBM GB/s (% of peak)"
-KERNEL_SRC = os.path.join(ROOT, "paper_2503_22631_amd", "csrc", "step_kernels.hip")
+# the sources the fused SpMV + sketch kernel is compiled from (the kernel and its inlined helpers)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2503_22631_amd", "csrc", f) for f in ("step_kernels.hip", "fab_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_sketch_convdiff128_traffic.json")
 COPY_BYTES = 256 << 20
 
@@ -50,7 +51,10 @@ def algorithmic_bytes(n: int, nnz: int, k: int, es: int = 8):
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
