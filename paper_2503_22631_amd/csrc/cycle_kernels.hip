@@ -567,6 +567,8 @@ __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a0) {
 // ------------------------------------------------------------------------------ fused pass
 // x_t += W c_t for every time point, v_hat = W c_nt written over column 0, and per-block
 // partial norms ||y_t||^2, ||x_t||^2 (added into kSlots copies).
+constexpr int kPassGroup = 8;  // basis columns whose loads the pass issues together
+
 template <typename T, int NT>
 __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const double* __restrict__ C,
                                                    T* __restrict__ W, double* __restrict__ x, int64_t ldx,
@@ -596,10 +598,21 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
     double acc[NT + 1];
 #pragma unroll
     for (int q = 0; q <= NT; ++q) acc[q] = 0.0;
-    for (int j = 0; j < ncol; ++j) {
-      const double w = (double)W[(size_t)j * n + i];
+    // columns in groups of kPassGroup: all loads of a group are issued before its products (past
+    // the last column the index is clamped and the weight is 0, so no load is guarded); the
+    // basis is not read again before the next cycle overwrites it, hence non-temporal loads
+    for (int j0 = 0; j0 < ncol; j0 += kPassGroup) {
+      T wv[kPassGroup];
 #pragma unroll
-      for (int q = 0; q <= NT; ++q) acc[q] = fma(w, Cs[j * (NT + 1) + q], acc[q]);
+      for (int u = 0; u < kPassGroup; ++u)
+        wv[u] = __builtin_nontemporal_load(&W[(size_t)min(j0 + u, ncol - 1) * n + i]);
+#pragma unroll
+      for (int u = 0; u < kPassGroup; ++u) {
+        const int j = min(j0 + u, ncol - 1);
+        const double w = (j0 + u < ncol) ? (double)wv[u] : 0.0;
+#pragma unroll
+        for (int q = 0; q <= NT; ++q) acc[q] = fma(w, Cs[j * (NT + 1) + q], acc[q]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
