@@ -211,7 +211,20 @@ def extra_legs(fab, ctx):
         sec, (x, info) = _timed(lambda: fab.solve(op, bt, "invsqrt", m=30, k=2, d=120, zeta=8, seed=1, tol=1e-6,
                                                   spec=spec, max_cycles=300))
         leg[name] = {"solves_per_s": 1.0 / sec, "cycles": info["cycles"], "ms_per_cycle": 1e3 * sec / info["cycles"],
-                     "status": info["status"]}
+                     "status": info["status"], "kappa_T": info["kappa_T"]}
+        # HBM roofline of this workload's loop: three cycles again with HIP events around every launch
+        # of the fused SpMV + sketch kernel and every step loop (algorithmic bytes as for the headline)
+        fab.timing_enable(ctx, True)
+        fab.solve(op, bt, "invsqrt", m=30, k=2, d=120, zeta=8, seed=1, tol=1e-6, spec=spec, max_cycles=3,
+                  check=False)
+        tm = fab.timing_read(ctx)
+        fab.timing_enable(ctx, False)
+        sb, stb = algorithmic_bytes(A.n, A.nnz, 2, es=4 if dt == torch.float32 else 8)
+        spmv_gbs = sb / (tm["spmv_ms"] / tm["spmv_launches"] / 1e3) / 1e9
+        loop_gbs = stb * tm["loop_steps"] / (tm["loop_ms"] / 1e3) / 1e9
+        leg[name]["roofline"] = {"spmv_sketch_GB/s": spmv_gbs, "spmv_sketch_frac": spmv_gbs / HBM_PEAK_GBS,
+                                 "spmv_bytes_per_launch": sb, "loop_GB/s": loop_gbs,
+                                 "loop_frac": loop_gbs / HBM_PEAK_GBS, "bytes_per_step": stb}
         xh = x[:, 0].cpu().numpy()
         bb = b if dt == torch.float64 else b.astype(np.float32).astype(np.float64)
         checks.append((leg[name], "rel_err",

@@ -87,6 +87,10 @@ typedef struct {
                             * z^(-1/2): |r/f - 1| at z geometric in [lo, hi].  The   *
                             * restarted iteration with a fixed rule converges to     *
                             * r(A) b, so this bounds what the rule adds to the error */
+  double kappa_T;          /* conditioning of the sketched basis: max over cycles of *
+                            * max_i T_ii / min_i T_ii for the whitening factor T of  *
+                            * S W = Q T (appendix eq. A.1), a lower bound on         *
+                            * cond_2(S W); 1 for the plain method (T = I)            */
 } fab_info;
 
 typedef struct fab_ctx fab_ctx;

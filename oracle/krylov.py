@@ -261,6 +261,7 @@ class SolveInfo:
     matvecs: int = 0
     est_rel_update: float = np.inf
     quad_rule_error: float = 0.0
+    kappa_T: float = 1.0     # max over cycles of max_i T_ii / min_i T_ii (a lower bound on cond_2(S W))
     history: list = field(default_factory=list)
 
 
@@ -297,6 +298,8 @@ def restart_solve(A, b, fun, t: float = 1.0, m: int = 20, k: int | None = None, 
         x = x + y
         info.cycles = c + 1
         info.matvecs += cyc.m
+        dT = np.diag(cyc.T)
+        info.kappa_T = max(info.kappa_T, float(dT.max() / dT.min()))
         nx = np.linalg.norm(x)
         info.est_rel_update = np.linalg.norm(y) / nx if nx > 0 else 0.0
         rec = {"X": cyc.X, "h": cyc.h, "beta": cyc.beta, "alpha": cyc.alpha, "T": cyc.T,

@@ -171,14 +171,14 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
         _lib.check(st, "fab_solve")
     out = {"status": _lib.STATUS.get(info.status, info.status), "code": int(st), "cycles": info.cycles,
            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update,
-           "quad_rule_error": info.quad_rule_error}
+           "quad_rule_error": info.quad_rule_error, "kappa_T": info.kappa_T}
     return x.view(nt, op.n).t(), out
 
 
 def _info_dict(info, code):
     return {"status": _lib.STATUS.get(info.status, info.status), "code": int(code), "cycles": info.cycles,
             "matvecs": info.matvecs, "est_rel_update": info.est_rel_update, "quad_rule_error": info.quad_rule_error,
-            "group": info.group}
+            "kappa_T": info.kappa_T, "group": info.group}
 
 
 def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None,

@@ -632,7 +632,7 @@ struct Track {
   fab_status status = FAB_W_NOT_CONVERGED;
   int cycles = 0, matvecs = 0;
   bool finished = false;
-  double est = 0.0, rule_err = 0.0;
+  double est = 0.0, rule_err = 0.0, kappa_T = 1.0;
 };
 
 // Returns true when this report finishes the member.
@@ -641,6 +641,7 @@ static bool track_report(Track& t, const Report& rr, int c) {
   t.matvecs += rr.meff;
   t.est = rr.est;
   t.rule_err = std::max(t.rule_err, rr.rule_err);
+  if (rr.meff > 0 && std::isfinite(rr.kappa_T)) t.kappa_T = std::max(t.kappa_T, rr.kappa_T);
   if (rr.nonfinite) {
     t.status = FAB_E_NONFINITE;
   } else if (rr.brk) {
@@ -674,6 +675,7 @@ static fab_status finish_tracks(std::vector<Track>& tr, const fab_params* p, fab
       h_info[r].matvecs = t.matvecs;
       h_info[r].est_rel_update = t.est;
       h_info[r].quad_rule_error = t.rule_err;
+      h_info[r].kappa_T = t.kappa_T;
       h_info[r].group = group;
     }
   }

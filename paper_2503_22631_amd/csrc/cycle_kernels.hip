@@ -266,6 +266,12 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
     rcol[e] = brk ? 0.0 : (e < mm ? -s_lds[e] / tau : (e == mm ? 1.0 / tau : 0.0));
   if (tid == 0) {
     const double alpha = st->alpha;
+    double dmin = Ts[0], dmax = Ts[0];  // diagonal of T (positive): its spread bounds cond_2(T) below
+    for (int i = 1; i < cols; ++i) {
+      dmin = fmin(dmin, Ts[i * ldT + i]);
+      dmax = fmax(dmax, Ts[i * ldT + i]);
+    }
+    st->kappa_T = dmax / dmin;
     st->beta = alpha * Ts[0];
     st->h = brk ? 0.0 : r * tau / Ts[(mm - 1) * ldT + (mm - 1)];
     st->cpl = brk ? 0.0 : alpha * r * tau;
@@ -674,6 +680,7 @@ __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, Sta
   rep->rule_err = qd;
   rep->alpha = st->alpha;
   rep->beta = st->beta;
+  rep->kappa_T = st->kappa_T;
   rep->brk = st->brk;
   rep->meff = st->meff;
   rep->nonfinite = st->nonfinite;

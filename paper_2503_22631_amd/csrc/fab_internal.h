@@ -120,12 +120,13 @@ struct State {
   // per-cycle outputs read by the host
   double ynorm2[kMaxNt], xnorm2[kMaxNt];
   double est, rule_err;
+  double kappa_T;       // max_i T_ii / min_i T_ii of the cycle's whitening factor
   int converged, done;  // done: converged, broken down or non-finite; every kernel skips the member
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
 struct Report {
-  double est, rule_err, alpha, beta;
+  double est, rule_err, alpha, beta, kappa_T;
   int brk, meff, nonfinite, converged, done, pad;
 };
 

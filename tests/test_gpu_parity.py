@@ -139,6 +139,10 @@ def test_convdiff_vs_kronecker(fab, ctx, method):
     ref = exact.kron_exp_fab(b, factors, t)
     assert info["status"] == "FAB_OK", info
     assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
+    if method == "plain":
+        assert info["kappa_T"] == 1.0  # no whitening: T = I
+    else:
+        assert 1.0 <= info["kappa_T"] < 1e3
 
 
 def test_multiple_time_points(fab, ctx):
@@ -346,6 +350,7 @@ def test_hash_and_table_paths_match_oracle(fab, ctx, d, zeta):
     xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=24, k=3, S=S, tol=1e-12, max_cycles=30)
     assert info["cycles"] == io.cycles
     assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-11
+    assert info["kappa_T"] == pytest.approx(io.kappa_T, rel=1e-9)  # same S, same T up to rounding
     factors, _ = exact.problem_factors("convdiff_3d", 14, peclet=20.0)
     assert _rel(x[:, 0].cpu().numpy(), exact.kron_exp_fab(b, factors, t)) <= 1e-10
 

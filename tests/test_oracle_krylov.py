@@ -216,3 +216,25 @@ def test_fixed_rule_iteration_converges_to_r_of_A():
     assert np.linalg.norm(x - rA_b) <= 1e-11 * np.linalg.norm(rA_b)
     gap = np.linalg.norm(rA_b - fA_b) / np.linalg.norm(fA_b)
     assert 1e-8 < gap <= info.quad_rule_error
+
+
+def test_kappa_T_is_a_lower_bound_on_the_basis_condition():
+    """kappa_T (the spread of T's positive diagonal, max over cycles) is >= 1 and <= cond_2(S W) of
+    every cycle (a triangular matrix's condition number is at least its diagonal spread); the plain
+    method's T is the identity."""
+    A = wl.convdiff_3d(12, 20.0)
+    b = wl.gaussian_vector(A.n, 3)
+    S = sketch.sketch_matrix(A.n, 60, 4, seed=2)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "exp", 2e-3, m=20, k=2, S=S, tol=1e-12, max_cycles=6,
+                                   keep_cycles=True)
+    ratios = []
+    for rec in info.history:
+        cyc = rec["cycle"]
+        cols = cyc.m if cyc.breakdown else cyc.m + 1
+        dT = np.diag(cyc.T)
+        ratios.append(dT.max() / dT.min())
+        assert dT.max() / dT.min() <= np.linalg.cond(cyc.U[:, :cols]) * (1 + 1e-10)
+    assert info.kappa_T == pytest.approx(max(ratios), rel=0, abs=0)
+    assert info.kappa_T >= 1.0 and len(ratios) >= 2
+    _, plain = krylov.restart_solve(A.to_scipy(), b, "exp", 2e-3, m=20, method="plain", tol=1e-12, max_cycles=3)
+    assert plain.kappa_T == 1.0
