@@ -58,7 +58,13 @@ typedef enum {
 
 typedef enum { FAB_F64 = 0, FAB_F32 = 1 } fab_dtype;        /* A values and basis; x is FP64 */
 typedef enum { FAB_EXP_NEG = 0, FAB_INVSQRT = 1 } fab_fun;  /* exp(-t z) ; z^(-1/2)          */
-typedef enum { FAB_SKETCHED = 0, FAB_PLAIN_RESTART = 1 } fab_method;
+/* FAB_SKETCHED: the sketched cycles with the quadrature restart (fixed m x m work per cycle).
+ * FAB_PLAIN_RESTART: classical restarted Arnoldi (CGS2) with the same restart, as a comparator.
+ * FAB_SKETCHED_GROWING: the sketched cycles with the restart as Algorithm 2 states it, f applied
+ *   to the growing block matrix of all cycles so far; exp(-t z) only, one right-hand side, and
+ *   max_cycles * m <= 1024 (FAB_E_UNSUPPORTED otherwise; also when exp(-t M) e_1 would need more
+ *   than 16384 Taylor steps of norm 2, i.e. t ||M||_1 > 32768). */
+typedef enum { FAB_SKETCHED = 0, FAB_PLAIN_RESTART = 1, FAB_SKETCHED_GROWING = 2 } fab_method;
 
 /* Solver parameters (Algorithm 2's arguments plus the sketch). */
 typedef struct {

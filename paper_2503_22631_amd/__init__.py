@@ -20,7 +20,7 @@ from ._lib import FabError, fab_info, fab_params
 
 FUN = {"exp": 0, "invsqrt": 1}
 SKETCH_APPLY_WORK_PER_ROW = 128   # fab_sketch_apply's workspace: 128 bytes per sketch row
-METHOD = {"sketched": 0, "plain": 1}
+METHOD = {"sketched": 0, "plain": 1, "growing": 2}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
 __all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "solve_ragged", "workspace_size", "spmv", "sketch_apply",

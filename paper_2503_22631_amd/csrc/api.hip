@@ -48,7 +48,7 @@ hipError_t launch_sqnorm(hipStream_t, int dtype, int grid, int n, const void* v,
 hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_start, double* slots_step,
                         size_t step_len, double* U, double* R, State* st, int nb, size_t bs);
 
-hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb);
+hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb, const GrowBuffers* grow);
 hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, const double* C, void* W, double* x,
                        int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs);
 hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
@@ -160,6 +160,8 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.rule_w = take((size_t)L.nsys * sizeof(cplx));
   L.psi = take((size_t)L.nsys * sizeof(cplx));
   L.gbuf = take((size_t)nt * m * 8 + (size_t)nt * 8 /* t values */);
+  // growing restart: blocks (kGrowRows x m), couplings and sizes per cycle
+  L.grow = take(p->method == FAB_SKETCHED_GROWING ? (size_t)kGrowRows * m * 8 + (size_t)kGrowRows * 12 : 0);
   L.scratch = take(0);
   L.ldscr = m;
   L.report = 0;
@@ -170,8 +172,9 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
 static fab_status check_params(const fab_op* A, const fab_params* p, int fun, int nt) {
   if (!A || !p) return FAB_E_INVALID;
   if (p->m < 1 || p->m > kMaxM) return FAB_E_INVALID;
-  if (p->method != FAB_SKETCHED && p->method != FAB_PLAIN_RESTART) return FAB_E_INVALID;
-  if (p->method == FAB_SKETCHED) {
+  if (p->method != FAB_SKETCHED && p->method != FAB_PLAIN_RESTART && p->method != FAB_SKETCHED_GROWING)
+    return FAB_E_INVALID;
+  if (p->method != FAB_PLAIN_RESTART) {
     if (p->k < 1 || p->k > p->m) return FAB_E_INVALID;
     if (p->d < p->m + 1 || p->d > kMaxD) return FAB_E_INVALID;
     if (p->zeta < 1 || p->zeta > 32 || p->zeta > p->d) return FAB_E_INVALID;
@@ -187,6 +190,9 @@ static fab_status check_params(const fab_op* A, const fab_params* p, int fun, in
     return FAB_E_INVALID;
   }
   if (A->n >= (int64_t)1 << 31) return FAB_E_UNSUPPORTED;
+  if (p->method == FAB_SKETCHED_GROWING &&
+      (fun != FAB_EXP_NEG || (int64_t)p->max_cycles * p->m > kGrowRows))
+    return FAB_E_UNSUPPORTED;
   return FAB_OK;
 }
 
@@ -341,7 +347,15 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.C = q.C;
   a.st = q.st;
   a.bs = bs;
-  FAB_TRY(launch_small(s, a, nb));
+  GrowBuffers gb{};
+  if (p->method == FAB_SKETCHED_GROWING) {
+    char* g0 = q.base + L.grow;
+    gb.M = (double*)g0;
+    gb.K = (double*)(g0 + (size_t)kGrowRows * m * 8);
+    gb.sz = (int*)(g0 + (size_t)kGrowRows * m * 8 + (size_t)kGrowRows * 8);
+    gb.tvals = q.tvals;
+  }
+  FAB_TRY(launch_small(s, a, nb, p->method == FAB_SKETCHED_GROWING ? &gb : nullptr));
   if (with_pass) {
     FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, B.ldx, q.slots_norm, q.st, nb, bs));
     FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep, nb, bs));
@@ -644,6 +658,8 @@ static bool track_report(Track& t, const Report& rr, int c) {
   if (rr.meff > 0 && std::isfinite(rr.kappa_T)) t.kappa_T = std::max(t.kappa_T, rr.kappa_T);
   if (rr.nonfinite) {
     t.status = FAB_E_NONFINITE;
+  } else if (rr.grow_fail) {  // growing restart out of capacity or Taylor steps
+    t.status = FAB_E_UNSUPPORTED;
   } else if (rr.brk) {
     t.status = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
   } else if (rr.converged) {
@@ -666,6 +682,7 @@ static fab_status finish_tracks(std::vector<Track>& tr, const fab_params* p, fab
     Track& t = tr[r];
     // A fixed rule r makes the restarted iteration converge to r(A) b, so the rule adds at most its
     // error |r - f| over the spectral region to the result (k_rule_check samples it once per solve).
+    if (p->method == FAB_SKETCHED_GROWING) t.rule_err = 0.0;  // no quadrature rule in this restart
     if ((t.status == FAB_OK || t.status == FAB_OK_BREAKDOWN) && t.rule_err > std::max(0.1 * p->tol, 1e-11))
       t.status = FAB_W_QUADRATURE;
     if (status_rank(t.status) > status_rank(worst)) worst = t.status;
@@ -690,7 +707,10 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
   for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_INVALID);
   if (!ctx || !A || !b || !x || !p || !work) return FAB_E_INVALID;
   if (nb < 1 || nb > kMaxBatch || ldb < A->n || ldx < A->n) return FAB_E_INVALID;
-  if (nb > 1 && p->method == FAB_PLAIN_RESTART) return FAB_E_UNSUPPORTED;
+  if (nb > 1 && p->method != FAB_SKETCHED) {  // batches run the sketched method with the quadrature restart
+    for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_UNSUPPORTED);
+    return FAB_E_UNSUPPORTED;
+  }
   if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
   fab_status ps = check_params(A, p, fun, nt);
   if (ps != FAB_OK) {
@@ -832,7 +852,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
                             size_t work_bytes, fab_info* h_info) {
   for (int i = 0; i < nops && h_info; ++i) info_init(h_info + i, FAB_E_INVALID);
   if (!ctx || !ops || !b || !x || !p || !work || nops < 1 || nops > kMaxBatch) return FAB_E_INVALID;
-  if (p->method == FAB_PLAIN_RESTART) return FAB_E_UNSUPPORTED;
+  if (p->method != FAB_SKETCHED) return FAB_E_UNSUPPORTED;
   if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
   if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
   for (int i = 0; i < nops; ++i) {

@@ -570,6 +570,146 @@ __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a0) {
     for (int i = threadIdx.x; i <= m; i += kThreads) a.C[(size_t)nt * (m + 1) + i] = 0.0;
 }
 
+// ------------------------------------------------------------------------ growing restart
+// The restart of Algorithm 2 as the paper states it: f applied to the growing block matrix of all
+// cycles so far, instead of the fixed-size quadrature recursion.  In the basis the cycle end uses
+// (Rt = T_m^{-1} X T_m per cycle, the similarity above), that matrix is upper Hessenberg: diagonal
+// blocks Rt_1 .. Rt_c and, between cycles c-1 and c, the single entry r tau alpha_c in the first row
+// of block c and the last column of block c-1 (X's coupling h beta_c = r tau alpha_c T_11 / T_mm
+// carried through the two diagonal similarities).  With beta_1 = alpha_1 T_11 the pass coefficients
+// of cycle c are then c_t = alpha_1 [f(M_c) e_1] restricted to block c.  f = exp(-t z) only.
+//
+// Storage: block c (size sz_c <= m) column-major with leading dimension m at gM + m * (rows of
+// blocks 1..c-1); gK[c] its coupling to block c-1; gSz[c] its size.
+
+// One block: append this cycle's Rt and coupling.
+__global__ __launch_bounds__(kThreads) void k_grow_append(SmallArgs a, double* __restrict__ gM,
+                                                          double* __restrict__ gK, int* __restrict__ gSz) {
+  State* st = a.st;
+  if (st->done) return;
+  const int m = a.m, mm = st->meff;
+  if (st->nonfinite || mm == 0) return;
+  const int c = st->grow_c, p = st->grow_p;
+  if (p + mm > kGrowRows) {  // capacity (the host keeps max_cycles * m within it)
+    if (threadIdx.x == 0) st->grow_fail = 1;
+    return;
+  }
+  double* blk = gM + (size_t)p * m;
+  for (int e = threadIdx.x; e < mm * mm; e += kThreads) {
+    const int i = e % mm, j = e / mm;
+    blk[i + (size_t)j * m] = a.Xout[i + (size_t)j * m];
+  }
+  if (threadIdx.x == 0) {
+    gK[c] = (c == 0) ? 0.0 : st->grow_rt * st->alpha;
+    gSz[c] = mm;
+    if (c == 0) st->grow_alpha1 = st->alpha;
+    st->grow_rt = st->brk ? 0.0 : st->cpl / st->alpha;  // cpl = alpha r tau, alpha > 0 here
+    st->grow_c = c + 1;
+    st->grow_p = p + mm;
+  }
+}
+
+// exp(-t M) e_1 for the time point t = tvals[blockIdx.x] by the truncated Taylor series applied to a
+// vector (Al-Mohy and Higham 2011, the action of the matrix exponential): s steps of
+// v <- sum_{k <= K} (B^k / k!) v with B = -t M / s.  s = ceil(t ||M||_1 / 2), so ||B||_1 <= 2, and K
+// is the first degree whose next term bound eta^(K+1) / (K+1)! (eta = ||B||_1) is below 2^-53.
+// One thread per row of M (rows <= kGrowRows); the vector is in LDS.  Writes the pass
+// coefficients of the current cycle (column blockIdx.x of C), zeros past the basis.
+__global__ __launch_bounds__(kGrowRows) void k_grow_expmv(SmallArgs a, const double* __restrict__ gM,
+                                                          const double* __restrict__ gK,
+                                                          const int* __restrict__ gSz,
+                                                          const double* __restrict__ tvals) {
+  __shared__ double tv[kGrowRows];
+  __shared__ double colsum[kGrowRows];
+  __shared__ double red[kGrowRows / 64];
+  State* st = a.st;
+  if (st->done) return;
+  const int m = a.m, it = blockIdx.x, i = threadIdx.x;
+  double* Ccol = a.C + (size_t)it * (m + 1);
+  const int mm = st->meff;
+  if (st->nonfinite || mm == 0 || st->grow_fail) {
+    for (int e = i; e <= m; e += kGrowRows) Ccol[e] = 0.0;
+    if (it == 0)
+      for (int e = i; e <= m; e += kGrowRows) a.C[(size_t)a.nt * (m + 1) + e] = 0.0;
+    return;
+  }
+  const int p = st->grow_p;
+  // this thread's row: block c, local row li, first row of the block off
+  int c = 0, off = 0;
+  if (i < p)
+    while (off + gSz[c] <= i) off += gSz[c++];
+  const int li = i - off, sz = (i < p) ? gSz[c] : 0;
+  const double* blk = gM + (size_t)off * m;
+  const int j0 = li > 0 ? li - 1 : 0;  // Hessenberg: entries from column li - 1 on
+  const double kap = (i < p && li == 0 && c > 0) ? gK[c] : 0.0;
+  // ||M||_1: column sums
+  for (int e = i; e < p; e += kGrowRows) colsum[e] = 0.0;
+  __syncthreads();
+  if (i < p) {
+    for (int jj = j0; jj < sz; ++jj) atomicAdd(&colsum[off + jj], fabs(blk[li + (size_t)jj * m]));
+    if (kap != 0.0) atomicAdd(&colsum[off - 1], fabs(kap));
+  }
+  __syncthreads();
+  double cmax = 0.0;
+  for (int e = i; e < p; e += kGrowRows) cmax = fmax(cmax, colsum[e]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+  if ((i & 63) == 0) red[i >> 6] = cmax;
+  __syncthreads();
+  cmax = 0.0;
+  for (int q = 0; q < kGrowRows / 64; ++q) cmax = fmax(cmax, red[q]);
+  const double t = tvals[it];
+  const double anorm = t * cmax;
+  const double sd = fmax(1.0, ceil(anorm / 2.0));
+  if (!(sd <= (double)kGrowMaxSteps)) {  // also catches a non-finite norm
+    if (i == 0) st->grow_fail = 1;
+    for (int e = i; e <= m; e += kGrowRows) Ccol[e] = 0.0;
+    return;
+  }
+  const int steps = (int)sd;
+  const double eta = anorm / sd, scale = -t / sd;
+  int K = 1;  // first degree with eta^(K+1) / (K+1)! < 2^-53 (uniform over the block)
+  {
+    double b = eta;  // eta^k / k! at k = K
+    while (K < 60 && b * eta / (K + 1) >= 1.1102230246251565e-16) {
+      b = b * eta / (K + 1);
+      ++K;
+    }
+  }
+  double acc = (i == 0) ? 1.0 : 0.0;  // v = e_1
+  for (int sstep = 0; sstep < steps; ++sstep) {
+    __syncthreads();  // the previous step's readers of tv are done
+    if (i < p) tv[i] = acc;
+    double term = acc;
+    for (int k = 1; k <= K; ++k) {
+      __syncthreads();  // tv holds the previous term
+      double y = 0.0;
+      if (i < p) {
+        for (int jj = j0; jj < sz; ++jj) y = fma(blk[li + (size_t)jj * m], tv[off + jj], y);
+        if (kap != 0.0) y = fma(kap, tv[off - 1], y);
+      }
+      term = y * (scale / (double)k);
+      __syncthreads();  // every row has read the previous term
+      if (i < p) tv[i] = term;
+      acc += term;
+    }
+  }
+  // coefficients of the current (last) block
+  const int lastoff = p - mm;
+  const double a1 = st->grow_alpha1;
+  if (i >= lastoff && i < p) Ccol[i - lastoff] = a1 * acc;
+  for (int e = mm + i; e <= m; e += kGrowRows) Ccol[e] = 0.0;
+}
+
+hipError_t launch_small_grow(hipStream_t s, const SmallArgs& a, double* gM, double* gK, int* gSz,
+                             const double* tvals) {
+  hipLaunchKernelGGL(k_grow_append, dim3(1), dim3(kThreads), 0, s, a, gM, gK, gSz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grow_expmv, dim3(a.nt), dim3(kGrowRows), 0, s, a, gM, gK, gSz, tvals);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------ fused pass
 // x_t += W c_t for every time point, v_hat = W c_nt written over column 0, and per-block
 // partial norms ||y_t||^2, ||x_t||^2 (added into kSlots copies).
@@ -685,6 +825,7 @@ __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, Sta
   rep->meff = st->meff;
   rep->nonfinite = st->nonfinite;
   rep->converged = st->converged;
+  rep->grow_fail = st->grow_fail;
   st->done = (st->converged || st->brk || st->nonfinite || !(est <= kDivergedEst)) ? 1 : 0;
   rep->done = st->done;
 }
@@ -800,8 +941,12 @@ hipError_t configure_cycle_kernels() {
                              (int)quad_lds(kMaxM));
 }
 
-// The cycle end of every batch member (a.bs apart): whitening, quadrature, coefficients.
-hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb) {
+hipError_t launch_small_grow(hipStream_t s, const SmallArgs& a, double* gM, double* gK, int* gSz,
+                             const double* tvals);
+
+// The cycle end of every batch member (a.bs apart): whitening, then the restart coefficients, by
+// the quadrature recursion or (grow given; one member) by the growing block matrix.
+hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb, const GrowBuffers* grow) {
   const dim3 g1(1, nb);
   if (a.plain || a.d <= 64)
     hipLaunchKernelGGL(k_whiten<8>, g1, dim3(kWhitenThreads), 0, s, a);
@@ -813,6 +958,7 @@ hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb) {
     hipLaunchKernelGGL(k_whiten_mem, g1, dim3(kWhitenThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (grow) return launch_small_grow(s, a, grow->M, grow->K, grow->sz, grow->tvals);
   const int nsys = a.nt * a.nq;
   hipLaunchKernelGGL(k_quad, dim3(nsys, nb), dim3(64), quad_lds(a.m), s, a);
   e = hipGetLastError();

@@ -18,6 +18,8 @@ constexpr int kRuleSamples = 256;  // sample points of the rule's accuracy check
 constexpr double kExpP = 3.0, kExpMu = 6.0, kExpL = 45.0;  // parabolic contour of the exp rule
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMaxBatch = 1024;    // largest number of right-hand sides per batched solve
+constexpr int kGrowRows = 1024;    // largest growing block matrix (cycles x m) of the growing restart
+constexpr int kGrowMaxSteps = 1 << 14;  // Taylor steps of exp(-t M) e_1 beyond which the restart gives up
 constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which a member's solve is abandoned
 
 // ----------------------------------------------------------------------------------------------
@@ -122,12 +124,16 @@ struct State {
   double est, rule_err;
   double kappa_T;       // max_i T_ii / min_i T_ii of the cycle's whitening factor
   int converged, done;  // done: converged, broken down or non-finite; every kernel skips the member
+  // growing restart: alpha of cycle 1, r tau of the last cycle appended, cycles and rows so far,
+  // and whether exp(-t M) e_1 needed more than kGrowMaxSteps Taylor steps
+  double grow_alpha1, grow_rt;
+  int grow_c, grow_p, grow_fail;
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
 struct Report {
   double est, rule_err, alpha, beta, kappa_T;
-  int brk, meff, nonfinite, converged, done, pad;
+  int brk, meff, nonfinite, converged, done, grow_fail;
 };
 
 // Batched solves: member r of a batch owns a copy of the single-solve workspace at byte offset
@@ -181,9 +187,17 @@ __device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
 }
 
 // Workspace carving, shared by the driver and workspace_size().
+// Workspace of the growing restart (one member): blocks, couplings and sizes per cycle.
+struct GrowBuffers {
+  double* M;
+  double* K;
+  int* sz;
+  const double* tvals;
+};
+
 struct Layout {
   size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
-      scratch, report, total;
+      grow, scratch, report, total;
   int nsys, nq, ldscr;
 };
 

@@ -712,3 +712,63 @@ def test_ragged_32_laplacians_full_size(fab, ctx):
     print(f"ragged 32 Laplacians 64^2..512^2: cycles {max(i['cycles'] for i in infos)} worst rel err {worst:.2e}",
           flush=True)
     assert worst <= FP32_BATCH_TOL
+
+
+# --------------------------------------------------------------- growing-matrix restart (Alg. 2)
+@pytest.mark.parametrize("k,ts", [(3, [5e-4]), (24, [5e-4]), (4, [1e-4, 5e-4, 2e-3])])
+def test_growing_restart_matches_oracle(fab, ctx, k, ts):
+    """The restart as Algorithm 2 states it (exp of the growing block matrix) against the oracle's
+    GrowingRestart with the same S: same cycle count, results equal to rounding; both converge to
+    exp(-tA) b.  k = m = 24 is the paper's restart-rand (full sketched Gram-Schmidt)."""
+    N = 14
+    A = wl.convdiff_3d(N, 20.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 12)
+    kw = dict(m=24, k=k, d=80, zeta=8, seed=5, tol=1e-11, max_cycles=30)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=ts, method="growing", **kw)
+    assert info["status"] == "FAB_OK", info
+    assert info["quad_rule_error"] == 0.0
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=5)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=20.0)
+    for i, t in enumerate(ts):
+        xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=24, k=k, S=S, tol=1e-11, max_cycles=30,
+                                      evaluation="growing")
+        xg = x[:, i].cpu().numpy()
+        assert _rel(xg, xo) <= 1e-10
+        assert _rel(xg, exact.kron_exp_fab(b, factors, t)) <= 1e-9
+    if k == 24:
+        assert info["kappa_T"] == pytest.approx(1.0, abs=1e-10)  # full window: S W orthonormal, T = I
+
+
+def test_growing_restart_agrees_with_quadrature_restart(fab, ctx):
+    """Both restarts of the same sketched cycles reach exp(-tA) b; several cycles are needed."""
+    N = 24
+    A = wl.convdiff_3d(N, 50.0)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 0), device="cuda")
+    t = 60.0 / (12 * (N + 1) ** 2)
+    kw = dict(m=20, k=4, d=120, zeta=8, seed=1, tol=1e-10, max_cycles=40)
+    xq, iq = fab.solve(op, b, "exp", t=t, **kw)
+    xg, ig = fab.solve(op, b, "exp", t=t, method="growing", **kw)
+    assert iq["status"] == ig["status"] == "FAB_OK" and ig["cycles"] >= 3
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=50.0)
+    ref = exact.kron_exp_fab(b.cpu().numpy(), factors, t)
+    assert _rel(xg[:, 0].cpu().numpy(), ref) <= 1e-9
+    assert _rel(xq[:, 0].cpu().numpy(), ref) <= 1e-9
+
+
+def test_growing_restart_unsupported_cases(fab, ctx):
+    A = wl.laplacian_2d(32)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 1), device="cuda")
+    lo, hi = 4 * (33 ** 2) * np.sin(np.pi / 66) ** 2 * 2, 8 * 33 ** 2
+    codes = []
+    _, info = fab.solve(op, b, "invsqrt", m=20, k=2, d=80, zeta=8, spec=(lo, hi), method="growing", check=False)
+    codes.append(info["code"])
+    _, info = fab.solve(op, b, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, max_cycles=60, method="growing",
+                        check=False)
+    codes.append(info["code"])  # 60 cycles x m = 20 rows exceed the 1024-row matrix
+    B = torch.stack([b, b], dim=1)
+    _, infos = fab.solve_batched(op, B, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, method="growing", check=False)
+    codes.append(infos[0]["code"])
+    assert codes == [-2, -2, -2]  # FAB_E_UNSUPPORTED
