@@ -950,6 +950,8 @@ hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb, const GrowBuf
   const dim3 g1(1, nb);
   if (a.plain || a.d <= 64)
     hipLaunchKernelGGL(k_whiten<8>, g1, dim3(kWhitenThreads), 0, s, a);
+  else if (a.d <= 200)  // 25 rows per lane: no idle register rows at d = 200
+    hipLaunchKernelGGL(k_whiten<25>, g1, dim3(kWhitenThreads), 0, s, a);
   else if (a.d <= 256)
     hipLaunchKernelGGL(k_whiten<32>, g1, dim3(kWhitenThreads), 0, s, a);
   else if (a.d <= 512)
