@@ -169,8 +169,17 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ short bf16_trunc(float x) { return (short)(__float_as_uint(x) >> 16); }
 __device__ __forceinline__ float bf16_value(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
 
+// Occupancy hint of the fused kernel: for FP32 data one member per block, at least 8 waves per SIMD
+// (the register budget then fits 8 blocks per CU; LDS allows it, and the 256^3 FP32 product runs
+// 17% faster than at the default 7).  FP64 blocks are limited to 6 per CU by LDS anyway, and the
+// grouped kernel would spill under the tighter budget: no hint for them.
+template <typename T, bool GRP>
+constexpr int spmv_min_waves() {
+  return (sizeof(T) == 4 && !GRP) ? 8 : 1;
+}
+
 template <typename T, int MODE, int ZMAX, bool GRP>
-__global__ __launch_bounds__(kThreads) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
+__global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
                                                           const T* __restrict__ vals,
                                                           const T* __restrict__ x, T* __restrict__ y,
