@@ -10,6 +10,8 @@
 //   g_c = beta_c sum_l w_l psi_l (zeta_l I - X)^{-1} e_1,   psi_l <- psi_l beta_c h_c [(zeta_l - X)^{-1} e_1]_m,
 //   by block forward substitution of the block lower-bidiagonal M_c (eq. restart_combined).
 // The pass then adds x_t += W_m (T_m^{-1} g_t) and forms v_hat in one read of the basis.
+// The growing restart (k_grow_append, k_grow_expmv) evaluates exp on M_c itself instead, as
+// Algorithm 2 states it.
 #include "fab_internal.h"
 
 namespace fab {

@@ -2,9 +2,13 @@
 // classical Arnoldi comparator, for gfx950.
 //
 //   k_spmv_sketch : z = A w_j (CSR, one row per lane) fused with u = S z, the sparse-sign sketch
-//                   (the product and sketch of Algorithm 1).  S comes from its counter-based spec
-//                   (regenerated per row from its counter-based spec), scattered into per-block
-//                   LDS bins and added into kSlots global copies.
+//                   (the product and sketch of Algorithm 1).  S's rows and signs are regenerated
+//                   per row from its counter-based specification, scattered into per-block LDS
+//                   bins and added into kSlots global copies.  Batches: one member per block, or
+//                   16 per block with the tile sketch on the matrix cores.
+//   k_orth_update : one launch for step j's Gram-Schmidt and window update (single solves with a
+//                   small sketch): persistent blocks, each redoing the sketch-space Gram-Schmidt
+//                   in one wavefront while four stream the basis update.
 //   k_orth        : one wavefront; modified Gram-Schmidt of the sketch against the last k sketched
 //                   basis vectors, the Hessenberg column, rho and the breakdown test.
 //   k_update      : w_{j+1} = (z - sum_i r_ij w_i) / rho over the window (the basis update of Algorithm 1).
