@@ -772,3 +772,55 @@ def test_growing_restart_unsupported_cases(fab, ctx):
     _, infos = fab.solve_batched(op, B, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, method="growing", check=False)
     codes.append(infos[0]["code"])
     assert codes == [-2, -2, -2]  # FAB_E_UNSUPPORTED
+
+
+def test_unrestarted_large_sketch_matches_oracle(fab, ctx):
+    """One cycle (no restart) with full sketched Gram-Schmidt (k = m) and a large sketch, d = 1200:
+    the shape of the paper's unrestarted randomized Arnoldi; exercises the whitening with the
+    basis in global scratch (d > 512) and the large-d Gram-Schmidt wavefront."""
+    N = 20
+    A = wl.convdiff_3d(N, 20.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 21)
+    t = 2e-4
+    kw = dict(m=60, k=60, d=1200, zeta=8, seed=9, tol=1e-12, max_cycles=1)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, check=False, **kw)
+    assert info["cycles"] == 1 and info["code"] >= 0
+    S = sketch.sketch_matrix(A.n, 1200, 8, seed=9)
+    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=60, k=60, S=S, tol=1e-12, max_cycles=1)
+    assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-10
+    # full window: S W orthonormal up to the loss of orthogonality of one modified Gram-Schmidt pass
+    assert info["kappa_T"] == pytest.approx(1.0, abs=1e-7)
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=20.0)
+    assert _rel(x[:, 0].cpu().numpy(), exact.kron_exp_fab(b, factors, t)) <= 1e-9
+
+
+def test_growing_restart_fp32_values(fab, ctx):
+    """The growing restart with FP32 values and basis (the small matrices stay FP64)."""
+    N = 40
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A, torch.float32)
+    b = wl.gaussian_vector(A.n, 4).astype(np.float32)
+    t = 2e-3
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, m=20, k=2, d=80, zeta=8, seed=1,
+                        tol=1e-6, max_cycles=40, method="growing")
+    assert info["status"] == "FAB_OK"
+    ref = exact.sine_fab("exp", b.astype(np.float64), N, [1, 0.01], t=t)
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-5
+
+
+def test_full_window_with_quadrature_restart(fab, ctx):
+    """k = m (the paper's full randomized Gram-Schmidt) with the default quadrature restart,
+    several cycles, against the oracle twin with the same S."""
+    N = 16
+    A = wl.convdiff_3d(N, 20.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 8)
+    t = 3e-3
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, m=16, k=16, d=64, zeta=4, seed=3,
+                        tol=1e-10, max_cycles=40)
+    S = sketch.sketch_matrix(A.n, 64, 4, seed=3)
+    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=16, k=16, S=S, tol=1e-10, max_cycles=40)
+    assert info["status"] == "FAB_OK" and info["cycles"] == io.cycles >= 3
+    assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-10
+    assert info["kappa_T"] == pytest.approx(1.0, abs=1e-9)
