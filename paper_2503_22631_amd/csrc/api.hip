@@ -30,7 +30,8 @@ hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cu
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
                          size_t bs);
 hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* cur, double* next, double* U, double* R, State* st, int nb, size_t bs);
+                              const double* cur, double* next, double* U, double* R, double* G, State* st, int nb,
+                              size_t bs);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -145,7 +146,7 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
     off = align_up(off + bytes);
     return o;
   };
-  L.W = take((size_t)n * (m + 1) * es);
+  L.W = take(wcol(n, (int)es) * (m + 1) * es);
   L.U = take((size_t)d * (m + 1) * 8);
   L.R = take((size_t)(m + 1) * m * 8);
   L.slots_step = take(2 * step_len * 8);
@@ -162,6 +163,7 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.gbuf = take((size_t)nt * m * 8 + (size_t)nt * 8 /* t values */);
   // growing restart: blocks (kGrowRows x m), couplings and sizes per cycle
   L.grow = take(p->method == FAB_SKETCHED_GROWING ? (size_t)kGrowRows * m * 8 + (size_t)kGrowRows * 12 : 0);
+  L.G = take((size_t)(m + 1) * (m + 1) * 8);
   L.scratch = take(0);
   L.ldscr = m;
   L.report = 0;
@@ -206,7 +208,7 @@ static int stream_grid(int64_t n, int cap) {
 struct Ptrs {
   char* base;
   void* W;
-  double *U, *R, *slots_step, *slots_start, *slots_norm, *T, *Ut, *X, *C, *gbuf, *tvals;
+  double *U, *R, *slots_step, *slots_start, *slots_norm, *T, *Ut, *X, *C, *gbuf, *tvals, *G;
   State* st;
   cplx *rz, *rw, *psi, *scr;
   size_t step_len;
@@ -232,6 +234,7 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   q.gbuf = (double*)(q.base + L.gbuf);
   q.tvals = q.gbuf + (size_t)nt * p->m;
   q.scr = (cplx*)(q.base + L.scratch);
+  q.G = (double*)(q.base + L.G);
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   q.step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
   return q;
@@ -285,7 +288,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta);
   const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta);
   const int g_vec = stream_grid(n, 2048);
-  auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * n * es; };
+  auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * wcol(n, (int)es) * es; };
   if (!plain) {
     FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
                                p->seed, q.slots_start, q.st, nb, B.G, bs));
@@ -305,7 +308,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
       if (nb == 1 && d <= 256 && p->k <= 8) {
-        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
+        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.G, q.st,
+                                   nb, bs));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
         FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
@@ -345,6 +349,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.scr = q.scr;
   a.gbuf = q.gbuf;
   a.C = q.C;
+  a.G = q.G;
   a.st = q.st;
   a.bs = bs;
   GrowBuffers gb{};
@@ -615,7 +620,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
     if (G > 1 && (d > 256 || spmv_sketch_lds(dt, 0, d, G, p->zeta) > group_lds_max())) break;
     const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta);
     void* x0 = q.W;
-    void* y0 = (char*)q.W + (size_t)n * es;
+    void* y0 = (char*)q.W + wcol(n, (int)es) * es;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
       if (rep == 1) err = hipEventRecord(e0, s);
       if (err == hipSuccess)
@@ -1083,7 +1088,8 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
   FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, v, n, q.W, 1, 0));
   fab_status es2 = enqueue_cycle(ctx, s, A, p, FAB_EXP_NEG, 1, L, q, nullptr, nullptr, false, nullptr, Batch{});
   if (es2 != FAB_OK) return es2;
-  FAB_TRY(hipMemcpyAsync(W, q.W, (size_t)n * (m + 1) * es, hipMemcpyDeviceToDevice, s));
+  FAB_TRY(hipMemcpy2DAsync(W, (size_t)n * es, q.W, wcol(n, (int)es) * es, (size_t)n * es, m + 1,
+                           hipMemcpyDeviceToDevice, s));
   if (!plain) FAB_TRY(hipMemcpyAsync(U, q.U, (size_t)d * (m + 1) * 8, hipMemcpyDeviceToDevice, s));
   FAB_TRY(hipMemcpyAsync(R, q.R, (size_t)(m + 1) * m * 8, hipMemcpyDeviceToDevice, s));
   FAB_TRY(hipMemcpyAsync(T, q.T, (size_t)(m + 1) * (m + 1) * 8, hipMemcpyDeviceToDevice, s));

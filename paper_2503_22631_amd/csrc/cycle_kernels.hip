@@ -21,6 +21,23 @@ __device__ __forceinline__ double wave_sum_c(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+// Value of v in lane i (i the same in every lane), through the scalar unit.
+__device__ __forceinline__ double bcast_lane(double v, int i) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, i);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), i);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 // Fill a double buffer with zeros (used instead of memset so the same code can sit in a graph).
 __global__ void k_zero(double* p, size_t count) {
@@ -187,6 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, dou
     st->meff = m;
     st->brk = 0;
     st->nonfinite = 0;
+    st->gram_rows = 0;
     if (!isfinite(alpha)) {
       st->nonfinite = 1;
       st->brk = 1;
@@ -242,14 +260,38 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
   }
   for (int e = tid; e < nt * m; e += nthr) a.gbuf[e] = 0.0;  // rule sums of k_quad
   if (wv == 0) {  // s = T_m^{-1} t, column-oriented back substitution; lane i holds s_i
+    // reciprocal diagonal in lane i; the column entries T[lane, i] are read eight columns at a time
+    // ahead of the chain, whose step is then a multiply, a lane broadcast and an FMA
+    const double rd = (lane < mm) ? 1.0 / Ts[lane * ldT + lane] : 0.0;
     double rhs = (!brk && lane < mm) ? Ts[lane * ldT + mm] : 0.0;
     double sl = 0.0;
-    for (int i = mm - 1; i >= 0; --i) {
-      const double si = __shfl(rhs, i, 64) / Ts[i * ldT + i];
-      if (lane == i) sl = si;
-      if (lane < i) rhs -= Ts[lane * ldT + i] * si;
+    for (int i0 = mm - 1; i0 >= 0; i0 -= 8) {
+      double tc[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = i0 - r;
+        tc[r] = (i >= 0 && lane < i) ? Ts[lane * ldT + i] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = i0 - r;
+        if (i >= 0) {
+          const double si = bcast_lane(rhs * rd, i);
+          if (lane == i) sl = si;
+          rhs -= tc[r] * si;
+        }
+      }
     }
     if (lane < mm) s_lds[lane] = sl;
+    // spread of T's diagonal (positive): max_i T_ii / min_i T_ii bounds cond_2(T) below
+    double dmin = INFINITY, dmax = 0.0;
+    for (int i = lane; i < cols; i += 64) {
+      dmin = fmin(dmin, Ts[i * ldT + i]);
+      dmax = fmax(dmax, Ts[i * ldT + i]);
+    }
+    dmin = wave_min(dmin);
+    dmax = wave_max(dmax);
+    if (lane == 0) st->kappa_T = dmax / dmin;
   }
   __syncthreads();
   const double r = brk ? 0.0 : a.R[(size_t)(mm - 1) * (m + 1) + mm];
@@ -268,16 +310,55 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
     rcol[e] = brk ? 0.0 : (e < mm ? -s_lds[e] / tau : (e == mm ? 1.0 / tau : 0.0));
   if (tid == 0) {
     const double alpha = st->alpha;
-    double dmin = Ts[0], dmax = Ts[0];  // diagonal of T (positive): its spread bounds cond_2(T) below
-    for (int i = 1; i < cols; ++i) {
-      dmin = fmin(dmin, Ts[i * ldT + i]);
-      dmax = fmax(dmax, Ts[i * ldT + i]);
-    }
-    st->kappa_T = dmax / dmin;
     st->beta = alpha * Ts[0];
     st->h = brk ? 0.0 : r * tau / Ts[(mm - 1) * ldT + (mm - 1)];
     st->cpl = brk ? 0.0 : alpha * r * tau;
   }
+}
+
+// T from the sketched Gram matrix G = U^T U = T^T T (kept row by row by the steps): LDL^T in LDS
+// by columns, one barrier per column (wave w updates rows c+1+w, c+10+w, .., lane l column c+1+l),
+// then T_kk = sqrt(D_k) and T_ki = L_ik sqrt(D_k).  Cholesky squares the condition number, so it
+// is taken only while every pivot keeps at least kCholMinPivot of its column's squared norm
+// (cond_2(U) up to about 1e3, where T is still accurate to 1e-10 relative); otherwise it returns
+// false and the caller runs the Householder QR.  Every thread returns the same result.  (Measured
+// on the 128^3 workload: 38 us per cycle end against 114 us for the Householder QR.  Keeping the
+// trailing entries in registers and publishing each column was slower, 44 us.)
+constexpr double kCholMinPivot = 1e-6;
+
+__device__ bool whiten_gram(const SmallArgs& a, int cols, double* Ts, int ldT, double* gd) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = kWhitenThreads, nwv = kWhitenThreads / 64;
+  const int ldg = a.m + 1;
+  for (int e = tid; e < cols * cols; e += nthr) {
+    const int i = e / cols, k = e % cols;
+    if (k <= i) {
+      const double g = a.G[(size_t)i * ldg + k];
+      Ts[i * ldT + k] = g;
+      if (k == i) gd[i] = g;
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < cols; ++c) {
+    const double piv = Ts[c * ldT + c];
+    if (!(piv >= kCholMinPivot * gd[c]) || !(piv < INFINITY)) {  // the same outcome in every thread
+      __syncthreads();  // every thread has read piv and gd[c] before the caller reuses Ts and gd
+      return false;
+    }
+    const double inv = 1.0 / piv;
+    const int k = c + 1 + lane;  // k <= c + 64 covers every column up to kMaxM
+    for (int i = c + 1 + wv; i < cols; i += nwv)
+      if (k <= i) Ts[i * ldT + k] -= Ts[i * ldT + c] * (Ts[k * ldT + c] * inv);
+    __syncthreads();
+  }
+  for (int c = tid; c < cols; c += nthr) gd[c] = sqrt(Ts[c * ldT + c]);
+  __syncthreads();
+  for (int e = tid; e < cols * cols; e += nthr) {
+    const int i = e / cols, k = e % cols;
+    if (k < i) Ts[k * ldT + i] = Ts[i * ldT + k] / gd[k];  // upper triangle from the strict lower
+    else if (k == i) Ts[i * ldT + i] = gd[i];
+  }
+  __syncthreads();
+  return true;
 }
 
 // Whitening QR with the sketched basis in registers (d <= 8 KR).  Column q of U is owned by the
@@ -303,6 +384,12 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a0) {
   if (st->nonfinite || mm == 0) return;
   const int cols = brk ? mm : mm + 1;
   const int ldT = kMaxM + 1;
+  if constexpr (KR <= 32) {  // the steps keep G only for d <= 256
+    if (!a.plain && st->gram_rows >= cols && whiten_gram(a, cols, Ts, ldT, diagR)) {
+      whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+      return;
+    }
+  }
   for (int e = tid; e < cols * cols; e += kWhitenThreads) Ts[(e / cols) * ldT + (e % cols)] = 0.0;
   __syncthreads();  // the zeros land before any entry of T is written below
   if (!a.plain) {
@@ -741,6 +828,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
   double yn[NT], xn[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) yn[q] = xn[q] = 0.0;
+  const size_t ld = wcol(n, sizeof(T));
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
     double acc[NT + 1];
@@ -753,7 +841,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
       T wv[kPassGroup];
 #pragma unroll
       for (int u = 0; u < kPassGroup; ++u)
-        wv[u] = __builtin_nontemporal_load(&W[(size_t)min(j0 + u, ncol - 1) * n + i]);
+        wv[u] = __builtin_nontemporal_load(&W[(size_t)min(j0 + u, ncol - 1) * ld + i]);
 #pragma unroll
       for (int u = 0; u < kPassGroup; ++u) {
         const int j = min(j0 + u, ncol - 1);

@@ -128,6 +128,7 @@ struct State {
   // and whether exp(-t M) e_1 needed more than kGrowMaxSteps Taylor steps
   double grow_alpha1, grow_rt;
   int grow_c, grow_p, grow_fail;
+  int gram_rows;  // rows of the sketched Gram matrix G = U^T U complete in this cycle (0: none kept)
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
@@ -150,6 +151,17 @@ __device__ __forceinline__ P* bat(P* p, size_t bs) {
   return bat(p, bs, (int)blockIdx.y);
 }
 
+// Column stride of the basis W, in elements of es bytes: n rounded up to whole 4 KiB pages, and an
+// odd number of pages.  Columns a power of two apart (2^21 doubles are 16 MiB) start on the same
+// HBM channels, and the kernels that stream several columns in step (the window update, the pass)
+// then lose 5-9% of their bandwidth on MI355X.
+__host__ __device__ __forceinline__ size_t wcol(int64_t n, int es) {
+  const int64_t per = 4096 / es;
+  int64_t pages = (n + per - 1) / per;
+  if ((pages & 1) == 0) ++pages;
+  return (size_t)(pages * per);
+}
+
 // Arguments of the cycle-end kernel.
 struct SmallArgs {
   int d, m, nt, plain, fun, nq, ldscr;
@@ -164,6 +176,7 @@ struct SmallArgs {
   cplx* scr;        // per-system restart contributions, entry i of system s at scr[s * ldscr + i]
   double* gbuf;     // nt x m: the rule sums of the cycle (restart coefficients before k_combine)
   double* C;        // (m+1) x (nt+1) pass coefficients (main rule), restart column last
+  const double* G;  // (m+1) x (m+1) sketched Gram matrix, row-major lower triangle (st->gram_rows rows)
   State* st;
   size_t bs;        // batch stride in bytes (member blockIdx.y works at byte offset blockIdx.y * bs)
 };
@@ -182,6 +195,7 @@ __device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
   a.scr = bat(a0.scr, bs);
   a.gbuf = bat(a0.gbuf, bs);
   a.C = bat(a0.C, bs);
+  a.G = bat(a0.G, bs);
   a.st = bat(a0.st, bs);
   return a;
 }
@@ -197,7 +211,7 @@ struct GrowBuffers {
 
 struct Layout {
   size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
-      grow, scratch, report, total;
+      grow, G, scratch, report, total;
   int nsys, nq, ldscr;
 };
 

@@ -392,12 +392,13 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
 // (the other set, accumulated by step j+1).
 // ---------------------------------------------------------------------------------------------
 // KW > 0: the window's KW columns of U are loaded together with the slot sums (one memory round
-// trip instead of one per window column; requires j - lo + 1 <= KW).
+// trip instead of one per window column; requires j - lo + 1 <= KW).  When `unew` is given, the
+// lanes receive their PER entries of u_{j+1} there (unchanged on breakdown).
 template <int PER, int KW>
 __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ slots_cur,
                                           double* __restrict__ slots_next, double* __restrict__ U,
                                           double* __restrict__ R, State* __restrict__ st, bool write,
-                                          double* coef, double* inv_out, int* ok_out) {
+                                          double* coef, double* inv_out, int* ok_out, double* unew = nullptr) {
   const int lane = threadIdx.x & 63;
   const int lo = max(0, j - k + 1);
   double u[PER];
@@ -480,6 +481,10 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
     *ok_out = 1;
     *inv_out = inv;
   }
+  if (unew) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) unew[q] = u[q] * inv;
+  }
   if (write) {
     double* Un = U + (size_t)(j + 1) * d;
 #pragma unroll
@@ -553,15 +558,15 @@ __device__ __forceinline__ int ou_count(int n, int64_t b0) {
 }
 
 template <typename T, int KMAX>
-__device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, int nw,
-                                        int64_t b0, int t, T (&zv)[kOuPer], T (&wv)[kOuPer][KMAX]) {
+__device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, size_t ld,
+                                        int nw, int64_t b0, int t, T (&zv)[kOuPer], T (&wv)[kOuPer][KMAX]) {
   const int cnt = ou_count(n, b0);
   const int64_t o = cnt ? b0 : 0;
   const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + o, cnt * (int)sizeof(T));
   __amdgpu_buffer_rsrc_t rw[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)  // columns beyond the window: size 0 (their coefficients are 0)
-    rw[q] = buf_rsrc(base + (size_t)min(q, nw - 1) * n + o, q < nw ? cnt * (int)sizeof(T) : 0);
+    rw[q] = buf_rsrc(base + (size_t)min(q, nw - 1) * ld + o, q < nw ? cnt * (int)sizeof(T) : 0);
 #pragma unroll
   for (int e = 0; e < kOuPer; ++e) {
     const int off = (e * kThreads + t) * (int)sizeof(T);
@@ -587,11 +592,34 @@ __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0,
   }
 }
 
+// Row j+1 of the sketched Gram matrix G = U^T U, spread over the blocks of step j's update: entry
+// e = 0..j+1 is <u_{j+1}, u_e> (e = j+1: the new vector with itself), and step 0 adds <u_0, u_0>
+// as entry 2.  Block b takes entries b, b + gridDim.x, ... in groups of kGramGroup, whose columns
+// of U are loaded together, after the barrier that releases the streaming wavefronts (loading them
+// before the Gram-Schmidt delays that barrier: measured 0.6 us per step).  The cycle end factors G
+// by Cholesky instead of running a Householder QR of U (the whitening), which takes most of that
+// work off the path between the last step and the pass.
+constexpr int kGramGroup = 2;
+
+__device__ __forceinline__ int gram_entries(int j) { return j + 2 + (j == 0 ? 1 : 0); }
+
+__device__ __forceinline__ void gram_load(const double* __restrict__ U, int d, int j, int e, int lane,
+                                          double (&v)[4]) {
+  // U column of entry e: e itself for e <= j, column 0 for step 0's extra entry, none otherwise
+  const int col = (e <= j) ? e : ((j == 0 && e == 2) ? 0 : -1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    v[q] = (col >= 0 && i < d) ? U[(size_t)col * d + i] : 0.0;
+  }
+}
+
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
                                                           const double* __restrict__ slots_cur,
                                                           double* __restrict__ slots_next, double* __restrict__ U,
-                                                          double* __restrict__ R, State* __restrict__ st, size_t bs) {
+                                                          double* __restrict__ R, double* __restrict__ G,
+                                                          State* __restrict__ st, size_t bs) {
   __shared__ double s_coef[kMaxM + 1];
   __shared__ double s_inv;
   __shared__ int s_ok;
@@ -599,12 +627,39 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   if (st->brk || st->done) return;
   W = bat(W, bs);
   const int lo = max(0, j - k + 1), nw = j - lo + 1;
-  T* out = W + (size_t)(j + 1) * n;
-  const T* base = W + (size_t)lo * n;
+  const size_t ld = wcol(n, sizeof(T));
+  T* out = W + (size_t)(j + 1) * ld;
+  const T* base = W + (size_t)lo * ld;
   if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const double* Ub = bat(U, bs);
+    const int ne = gram_entries(j);
+    double gv[kGramGroup][4], un[4] = {0.0, 0.0, 0.0, 0.0};
     orth_wave<4, KMAX>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st,
-                       blockIdx.x == 0, s_coef, &s_inv, &s_ok);
+                       blockIdx.x == 0, s_coef, &s_inv, &s_ok, un);
     __syncthreads();
+    if (!s_ok) return;  // breakdown: row j+1 does not exist
+    double* Gb = bat(G, bs);
+    const int ldg = m + 1;
+    for (int e0 = (int)blockIdx.x; e0 < ne; e0 += kGramGroup * (int)gridDim.x) {
+#pragma unroll
+      for (int r = 0; r < kGramGroup; ++r) gram_load(Ub, d, j, e0 + r * (int)gridDim.x, lane, gv[r]);
+#pragma unroll
+      for (int r = 0; r < kGramGroup; ++r) {
+        const int e = e0 + r * (int)gridDim.x;
+        if (e >= ne) break;
+        const bool self0 = (j == 0 && e == 2);  // <u_0, u_0>
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += (self0 ? gv[r][q] : un[q]) * (e == j + 1 ? un[q] : gv[r][q]);
+        const double g = wave_sum(acc);
+        if (lane == 0) {
+          if (self0) Gb[0] = g;
+          else Gb[(size_t)(j + 1) * ldg + e] = g;
+        }
+      }
+    }
+    if (blockIdx.x == 0 && lane == 0) st->gram_rows = j + 2;
     return;
   }
   // batches blockIdx.x, blockIdx.x + gridDim.x, ...; the launch keeps gridDim.x <= the batch count
@@ -613,7 +668,7 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   const int cnt = (nbat - 1 - (int)blockIdx.x) / (int)gridDim.x + 1;
   auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * kOuBatch; };
   T za[kOuPer], wa[kOuPer][KMAX], zb[kOuPer], wb[kOuPer][KMAX];
-  ou_load<T, KMAX>(out, base, n, nw, start(0), t, za, wa);
+  ou_load<T, KMAX>(out, base, n, ld, nw, start(0), t, za, wa);
   __syncthreads();
   if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
   const double inv = s_inv;
@@ -623,10 +678,10 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   // two register sets in turn; the prefetch past the block's last batch has size 0 (no memory
   // traffic), so every trip issues the same loads and stores
   for (int it = 0;;) {
-    ou_load<T, KMAX>(out, base, n, nw, start(it + 1), t, zb, wb);
+    ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
     ou_store<T, KMAX>(out, n, start(it), t, coef, inv, za, wa);
     if (++it >= cnt) break;
-    ou_load<T, KMAX>(out, base, n, nw, start(it + 1), t, za, wa);
+    ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, za, wa);
     ou_store<T, KMAX>(out, n, start(it), t, coef, inv, zb, wb);
     if (++it >= cnt) break;
   }
@@ -648,14 +703,15 @@ __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict
   double coef[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? st->upd_coef[q] : 0.0;
-  T* out = W + (size_t)(j + 1) * n;
-  const T* base = W + (size_t)lo * n;
+  const size_t ld = wcol(n, sizeof(T));
+  T* out = W + (size_t)(j + 1) * ld;
+  const T* base = W + (size_t)lo * ld;
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
     double v = (double)__builtin_nontemporal_load(&out[i]);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (q < nw) v -= coef[q] * (double)__builtin_nontemporal_load(&base[(size_t)q * n + i]);
+      if (q < nw) v -= coef[q] * (double)__builtin_nontemporal_load(&base[(size_t)q * ld + i]);
     __builtin_nontemporal_store((T)(v * inv), &out[i]);
   }
 }
@@ -669,6 +725,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(int n, int j1, const T* __res
   __shared__ double part[kThreads / 64][kMaxM + 2];
   if (st->brk) return;
   const int ncol = j1 + (want_norm ? 1 : 0);
+  const size_t ld = wcol(n, sizeof(T));
   const size_t stride = (size_t)gridDim.x * kThreads;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int c0 = 0; c0 < ncol; c0 += 16) {
@@ -680,7 +737,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(int n, int j1, const T* __res
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int c = c0 + q;
-        if (c < j1) acc[q] += (double)V[(size_t)c * n + i] * zi;
+        if (c < j1) acc[q] += (double)V[(size_t)c * ld + i] * zi;
         else if (c == j1 && want_norm) acc[q] += zi * zi;
       }
     }
@@ -727,12 +784,13 @@ __global__ __launch_bounds__(kThreads) void k_cgs_update(int n, int j, int m, T*
     }
     for (int c = threadIdx.x; c < kSlots * (kMaxM + 2); c += kThreads) slots_zero[c] = 0.0;
   }
-  T* z = V + (size_t)j1 * n;
+  const size_t ld = wcol(n, sizeof(T));
+  T* z = V + (size_t)j1 * ld;
   const size_t stride = (size_t)gridDim.x * kThreads;
   double nrm = 0.0;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
     double v = (double)z[i];
-    for (int c = 0; c < j1; ++c) v -= h[c] * (double)V[(size_t)c * n + i];
+    for (int c = 0; c < j1; ++c) v -= h[c] * (double)V[(size_t)c * ld + i];
     const T vt = (T)v;
     z[i] = vt;
     nrm += (double)vt * (double)vt;
@@ -912,20 +970,21 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
 }
 
 hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* cur, double* next, double* U, double* R, State* st, int nb, size_t bs) {
+                              const double* cur, double* next, double* U, double* R, double* G, State* st, int nb,
+                              size_t bs) {
   const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
   if (dtype == 0) {
     if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, st, bs);
+      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, G, st, bs);
     else
-      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, st, bs);
+      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, G, st, bs);
   } else {
     if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, st, bs);
+      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, G, st, bs);
     else
-      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, st, bs);
+      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, G, st, bs);
   }
   return hipGetLastError();
 }

@@ -98,6 +98,49 @@ def test_cycle_matches_oracle_twin(fab, ctx, N, m, k, d, zeta):
     assert abs(g["beta"] - c.beta) <= 1e-13 * c.beta
 
 
+def _min_pivot(U, T):
+    """Smallest T_ii^2 / ||u_i||^2: the relative pivot of the Cholesky factorisation of U^T U."""
+    return float(np.min(np.diag(T) ** 2 / np.sum(np.asarray(U) ** 2, axis=0)))
+
+
+@pytest.mark.parametrize("name,m", [("lap32", 12), ("cd12", 20)])
+def test_whitening_from_the_gram_matrix_near_the_pivot_limit(fab, ctx, name, m):
+    """A window of one vector (k = 1) leaves the sketched basis ill-conditioned, cond_2(U) about 7e3
+    here, while every pivot of G = U^T U stays above the Cholesky limit (1e-6 of its column's
+    squared norm): T from the Gram matrix kept by the steps equals the oracle's Householder factor."""
+    A = wl.laplacian_2d(32) if name == "lap32" else wl.convdiff_3d(12, 50.0)
+    op = _op(fab, ctx, A)
+    v = wl.gaussian_vector(A.n, 3)
+    g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=m, k=1, d=40, zeta=4, seed=1)
+    S = sketch.sketch_matrix(A.n, 40, 4, seed=1)
+    c = krylov.sketched_cycle(A.to_scipy(), S, v, m, 1)
+    assert g["m"] == m
+    assert np.linalg.cond(c.U) > 5e3
+    assert 1e-6 < _min_pivot(c.U, c.T) < 1e-4   # near the limit, on the Cholesky side
+    assert _rel(g["U"].cpu().numpy(), c.U) <= 1e-10
+    assert _rel(g["T"].cpu().numpy(), c.T) <= 1e-10
+
+
+def test_whitening_falls_back_to_householder_for_an_ill_conditioned_basis(fab, ctx):
+    """cond_2(U) about 5e6 (k = 1, m = 20): a pivot of G drops to 1e-10 of its column, the Cholesky
+    is refused and the Householder QR runs.  Its factor keeps Q = U T^{-1} orthonormal to rounding
+    times cond_2(U); a Cholesky factor would lose about cond_2(U)^2 eps, here far above 1e-6."""
+    A = wl.laplacian_2d(32)
+    op = _op(fab, ctx, A)
+    v = wl.gaussian_vector(A.n, 3)
+    m = 20
+    g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=m, k=1, d=40, zeta=4, seed=1)
+    S = sketch.sketch_matrix(A.n, 40, 4, seed=1)
+    c = krylov.sketched_cycle(A.to_scipy(), S, v, m, 1)
+    assert g["m"] == m
+    assert np.linalg.cond(c.U) > 1e6 and _min_pivot(c.U, c.T) < 1e-8
+    U, T = g["U"].cpu().numpy(), g["T"].cpu().numpy()
+    Q = np.linalg.solve(T.T, U.T).T
+    assert np.linalg.norm(Q.T @ Q - np.eye(m + 1)) <= 1e-6
+    assert np.all(np.diag(T) > 0)
+    assert _rel(T, c.T) <= 1e-6
+
+
 def test_plain_cycle_matches_arnoldi(fab, ctx):
     A = wl.convdiff_3d(12, 50.0)
     op = _op(fab, ctx, A)
