@@ -125,6 +125,8 @@ __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, co
       f = 1.0 / sqrt(z);
     }
     cplx r = cmk(0.0, 0.0);
+    // four independent divisions per trip, so their dependent chains interleave
+#pragma unroll 4
     for (int l = 0; l < nq; ++l) r = cadd(r, cdiv(ww[l], csub(zz[l], cmk(z, 0.0))));
     const double rv = (fun == 0) ? 2.0 * r.re : r.re;  // conjugate-half exp rule: twice the real part
     err = fmax(err, (fun == 0) ? fabs(rv - f) : fabs(rv / f - 1.0));
@@ -296,14 +298,18 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
   __syncthreads();
   const double r = brk ? 0.0 : a.R[(size_t)(mm - 1) * (m + 1) + mm];
   const double tau = brk ? 1.0 : Ts[mm * ldT + mm];
-  for (int e = tid; e < m * m; e += nthr) {  // Rt, column-major with leading dimension m
-    const int i = e % m, c = e / m;
-    double v = 0.0;
-    if (i < mm && c < mm) {
-      v = a.R[(size_t)c * (m + 1) + i];
-      if (c == mm - 1) v += r * s_lds[i];
+  for (int e0 = 0; e0 < m * m; e0 += 8 * nthr) {  // Rt, column-major with leading dimension m
+    double v[8];  // eight loads of R in flight per thread
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr + tid, i = e % m, c = e / m;
+      v[u] = (e < m * m && i < mm && c < mm) ? a.R[(size_t)c * (m + 1) + i] : 0.0;
     }
-    a.Xout[e] = v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr + tid, i = e % m, c = e / m;
+      if (e < m * m) a.Xout[e] = v[u] + ((i < mm && c == mm - 1) ? r * s_lds[i] : 0.0);
+    }
   }
   double* rcol = a.C + (size_t)nt * (m + 1);
   for (int e = tid; e <= m; e += nthr)
@@ -329,12 +335,19 @@ constexpr double kCholMinPivot = 1e-6;
 __device__ bool whiten_gram(const SmallArgs& a, int cols, double* Ts, int ldT, double* gd) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = kWhitenThreads, nwv = kWhitenThreads / 64;
   const int ldg = a.m + 1;
-  for (int e = tid; e < cols * cols; e += nthr) {
-    const int i = e / cols, k = e % cols;
-    if (k <= i) {
-      const double g = a.G[(size_t)i * ldg + k];
-      Ts[i * ldT + k] = g;
-      if (k == i) gd[i] = g;
+  constexpr int kPer = ((kMaxM + 1) * (kMaxM + 1) + kWhitenThreads - 1) / kWhitenThreads;
+  double gv[kPer];  // all loads in flight together: one memory latency, not one per entry
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * nthr, i = e / cols, k = e % cols;
+    gv[u] = (e < cols * cols && k <= i) ? a.G[(size_t)i * ldg + k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * nthr, i = e / cols, k = e % cols;
+    if (e < cols * cols && k <= i) {
+      Ts[i * ldT + k] = gv[u];
+      if (k == i) gd[i] = gv[u];
     }
   }
   __syncthreads();
@@ -569,9 +582,8 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a0) {
 // back substitution needs one broadcast per row.  Adds alpha w_s psi_s y into the pass
 // coefficients of its rule (FP64 atomics into the zeroed g buffer) and advances
 // psi_s <- psi_s alpha r tau y_m.
-__device__ __forceinline__ cplx shfl_c(cplx v, int src) {
-  return cplx{__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
-}
+// v of lane src (src the same in every lane), through the scalar unit rather than an LDS permute
+__device__ __forceinline__ cplx bcast_c(cplx v, int src) { return cplx{bcast_lane(v.re, src), bcast_lane(v.im, src)}; }
 // 1 / b through one real division (the moduli met here are far from the FP64 range limits)
 __device__ __forceinline__ cplx crecip(cplx b) {
   const double s = 1.0 / (b.re * b.re + b.im * b.im);
@@ -588,9 +600,16 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
   double* Xs = reinterpret_cast<double*>(smq);
   cplx* Us = reinterpret_cast<cplx*>(smq + (((size_t)mm * ld * 8 + 15) & ~(size_t)15));
   const int sidx = blockIdx.x, lane = threadIdx.x;
-  for (int e = lane; e < mm * mm; e += 64) {  // Rt is m x m column-major in global memory
-    const int i = e % mm, l = e / mm;
-    Xs[i * ld + l] = a.Xout[(size_t)l * a.m + i];
+  // Rt (m x m column-major in global memory, written by the previous kernel) into LDS, row-major:
+  // lane i takes row i, sixteen columns per round trip (one load per trip costs a memory latency
+  // per column)
+  for (int l0 = 0; l0 < mm; l0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = (lane < mm && l0 + u < mm) ? a.Xout[(size_t)(l0 + u) * a.m + lane] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (lane < mm && l0 + u < mm) Xs[lane * ld + l0 + u] = v[u];
   }
   __syncthreads();
   const cplx zeta = a.rz[sidx];
@@ -602,9 +621,9 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
   cplx rc = cmk(1.0, 0.0);
   cplx r = cmk(0.0, 0.0);  // right-hand side entry of row `lane` after elimination
   for (int i = 0; i < mm - 1; ++i) {
-    const cplx av = shfl_c(carry, i);
+    const cplx av = bcast_c(carry, i);
     const cplx hb = (lane < mm) ? H(i + 1, lane) : cmk(0.0, 0.0);
-    const cplx bs = shfl_c(hb, i);
+    const cplx bs = bcast_c(hb, i);
     if (cabs1(bs) > cabs1(av)) {  // pivot on row i+1 (uniform branch)
       const cplx mult = cmul(av, crecip(bs));
       if (lane >= i && lane < mm) Us[i * ld + lane] = hb;
@@ -626,7 +645,7 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
   const cplx inv_ll = (lane < mm) ? crecip(Us[lane * ld + lane]) : cmk(0.0, 0.0);
   cplx y = cmk(0.0, 0.0);
   for (int i = mm - 1; i >= 0; --i) {
-    const cplx yi = cmul(shfl_c(r, i), shfl_c(inv_ll, i));
+    const cplx yi = cmul(bcast_c(r, i), bcast_c(inv_ll, i));
     if (lane == i) y = yi;
     if (lane < i) r = csub(r, cmul(Us[lane * ld + i], yi));
   }
@@ -639,7 +658,7 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
     const double fac = (a.fun == 0) ? 2.0 : 1.0;
     if (lane < mm) unsafeAtomicAdd(a.gbuf + (size_t)it * a.m + lane, fac * st->alpha * cmul(wp, y).re);
   }
-  const cplx ym = shfl_c(y, mm - 1);
+  const cplx ym = bcast_c(y, mm - 1);
   if (lane == 0) a.psi[sidx] = cscale(cmul(ps, ym), st->cpl);
 }
 
@@ -809,7 +828,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
                                                    T* __restrict__ W, double* __restrict__ x, int64_t ldx,
                                                    double* __restrict__ norm_slots, const State* __restrict__ st,
                                                    size_t bs) {
-  __shared__ double Cs[(kMaxM + 1) * (NT + 1)];
   __shared__ double part[kThreads / 64][2 * NT];
   st = bat(st, bs);
   const int mm = st->meff;
@@ -820,11 +838,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
   x += (int64_t)blockIdx.y * nt * ldx;  // member r's time points are columns r nt .. r nt + nt - 1
   const int brk = st->brk;
   const int ncol = brk ? mm : mm + 1;
-  for (int e = threadIdx.x; e < (m + 1) * (nt + 1); e += kThreads) {
-    const int i = e % (m + 1), c = e / (m + 1);
-    Cs[i * (NT + 1) + (c < nt ? c : NT)] = C[e];
-  }
-  __syncthreads();
   double yn[NT], xn[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) yn[q] = xn[q] = 0.0;
@@ -836,7 +849,9 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
     for (int q = 0; q <= NT; ++q) acc[q] = 0.0;
     // columns in groups of kPassGroup: all loads of a group are issued before its products (past
     // the last column the index is clamped and the weight is 0, so no load is guarded); the
-    // basis is not read again before the next cycle overwrites it, hence non-temporal loads
+    // basis is not read again before the next cycle overwrites it, hence non-temporal loads.  The
+    // weights C (time point q, basis index j) have addresses uniform over the block, so they come
+    // through scalar loads, not one LDS read per product (2.4% of the pass)
     for (int j0 = 0; j0 < ncol; j0 += kPassGroup) {
       T wv[kPassGroup];
 #pragma unroll
@@ -847,7 +862,10 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
         const int j = min(j0 + u, ncol - 1);
         const double w = (j0 + u < ncol) ? (double)wv[u] : 0.0;
 #pragma unroll
-        for (int q = 0; q <= NT; ++q) acc[q] = fma(w, Cs[j * (NT + 1) + q], acc[q]);
+        for (int q = 0; q <= NT; ++q) {  // q = NT: the restart column, stored after the nt time points
+          const double cq = (q < nt) ? C[(size_t)q * (m + 1) + j] : (q == NT ? C[(size_t)nt * (m + 1) + j] : 0.0);
+          acc[q] = fma(w, cq, acc[q]);
+        }
       }
     }
 #pragma unroll
