@@ -51,7 +51,7 @@ hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_star
 
 hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb, const GrowBuffers* grow);
 hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, const double* C, void* W, double* x,
-                       int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs);
+                       int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs, const PassSketch& ps);
 hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
                         size_t bs);
 hipError_t launch_reduce_slots(hipStream_t, int len, const double* slots, double* out);
@@ -276,6 +276,33 @@ struct Batch {
   int64_t ldx = 0;
 };
 
+// Sketched methods with zeta <= 8 sketch each cycle's start vector inside the previous cycle's
+// pass, so the captured cycle begins without a sketch-only pass over w_1; the solve's set-up
+// sketches b for the first cycle (enqueue_first_sketch).
+static bool pass_sketches(const fab_params* p) { return p->method != FAB_PLAIN_RESTART && p->zeta <= 8; }
+
+static PassSketch pass_sketch(const fab_params* p, int dtype, const Ptrs& q) {
+  PassSketch ps{};
+  ps.slots = q.slots_start;
+  ps.d = p->d;
+  ps.zeta = p->zeta;
+  ps.k0 = (uint32_t)p->seed;
+  ps.k1 = (uint32_t)(p->seed >> 32);
+  const double sc = 1.0 / std::sqrt((double)p->zeta);
+  ps.scale = (dtype == 0) ? sc : (double)(float)sc;  // the sketch-only pass scales by a value of type T
+  return ps;
+}
+
+static fab_status enqueue_first_sketch(const fab_ctx* ctx, hipStream_t s, const fab_op* A, const fab_params* p,
+                                       const Ptrs& q, const Batch& B) {
+  if (!pass_sketches(p)) return FAB_OK;
+  const int n = (int)A->n;
+  const int g_sk = spmv_grid(ctx, n, A->dtype, 1, p->d, B.G, p->zeta);
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 1, g_sk, n, A->rowptr, A->colind, A->vals, q.W, nullptr, p->d, p->zeta,
+                             p->seed, q.slots_start, q.st, B.nb, B.G, B.bs));
+  return FAB_OK;
+}
+
 static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op* A, const fab_params* p, int fun,
                                 int nt, const Layout& L, const Ptrs& q, double* x, Report* rep, bool with_pass,
                                 const std::vector<hipEvent_t>* tev, const Batch& B) {
@@ -289,9 +316,11 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * wcol(n, (int)es) * es; };
+  const bool pass_sk = with_pass && pass_sketches(p);
   if (!plain) {
-    FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
-                               p->seed, q.slots_start, q.st, nb, B.G, bs));
+    if (!pass_sk)  // otherwise the set-up or the previous cycle's pass accumulated S w_1 already
+      FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
+                                 p->seed, q.slots_start, q.st, nb, B.G, bs));
   } else {
     FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
   }
@@ -362,7 +391,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   }
   FAB_TRY(launch_small(s, a, nb, p->method == FAB_SKETCHED_GROWING ? &gb : nullptr));
   if (with_pass) {
-    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, B.ldx, q.slots_norm, q.st, nb, bs));
+    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, B.ldx, q.slots_norm, q.st, nb, bs,
+                        pass_sk ? pass_sketch(p, dt, q) : PassSketch{}));
     FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep, nb, bs));
   }
   return FAB_OK;
@@ -755,6 +785,10 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
   FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi, q.st, nb,
                       bs));
   FAB_TRY(launch_copy_in(s, A->dtype, stream_grid(n, 2048), n, b, ldb, q.W, nb, bs));
+  {
+    const fab_status fs = enqueue_first_sketch(ctx, s, A, p, q, B);
+    if (fs != FAB_OK) return fs;
+  }
 
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
@@ -898,6 +932,8 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
     FAB_TRY(launch_rule(s, fun, nt, q[i].tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q[i].rz, q[i].rw,
                         q[i].psi, q[i].st, 1, 0));
     FAB_TRY(launch_copy_in(s, ops[i]->dtype, stream_grid(n, 2048), n, b[i], n, q[i].W, 1, 0));
+    const fab_status fs = enqueue_first_sketch(ctx, s, ops[i], p, q[i], Batch{});
+    if (fs != FAB_OK) return fs;
   }
   const int nbr = std::min(nops, kBranches);
   while ((int)ctx->branch.size() < kBranches) {

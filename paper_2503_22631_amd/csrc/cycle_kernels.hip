@@ -823,12 +823,17 @@ hipError_t launch_small_grow(hipStream_t s, const SmallArgs& a, double* gM, doub
 // partial norms ||y_t||^2, ||x_t||^2 (added into kSlots copies).
 constexpr int kPassGroup = 8;  // basis columns whose loads the pass issues together
 
+// With ps.slots set, the pass also sketches v_hat for the next cycle's start (alpha = ||S v_hat||,
+// u_1 = S v_hat / alpha): each row's S column is regenerated as in the fused product and added
+// into d bins in LDS, which are flushed into one of the kSlots copies at the end.  That spares the
+// next cycle a sketch-only pass over v_hat; the extra ALU work hides under the pass's loads.
 template <typename T, int NT>
 __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const double* __restrict__ C,
                                                    T* __restrict__ W, double* __restrict__ x, int64_t ldx,
                                                    double* __restrict__ norm_slots, const State* __restrict__ st,
-                                                   size_t bs) {
+                                                   size_t bs, PassSketch ps) {
   __shared__ double part[kThreads / 64][2 * NT];
+  extern __shared__ double pbins[];  // ps.d bins when sketching
   st = bat(st, bs);
   const int mm = st->meff;
   if (st->done || st->nonfinite || mm == 0) return;
@@ -838,6 +843,11 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
   x += (int64_t)blockIdx.y * nt * ldx;  // member r's time points are columns r nt .. r nt + nt - 1
   const int brk = st->brk;
   const int ncol = brk ? mm : mm + 1;
+  const bool sk = ps.slots != nullptr && !brk;  // block-uniform
+  if (sk) {
+    for (int b = threadIdx.x; b < ps.d; b += kThreads) pbins[b] = 0.0;
+    __syncthreads();
+  }
   double yn[NT], xn[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) yn[q] = xn[q] = 0.0;
@@ -879,6 +889,15 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
       }
     }
     if (!brk) W[i] = (T)acc[NT];
+    if (sk) {
+      int rows[8];
+      uint32_t sb = 0;
+      sketch_column<8>((uint64_t)i, ps.d, ps.zeta, ps.k0, ps.k1, rows, sb);
+      const double zs = (double)(T)acc[NT] * ps.scale;  // the stored value, as the next cycle reads it
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+        if (l < ps.zeta) unsafeAtomicAdd(&pbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -894,6 +913,13 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
     double s = 0.0;
     for (int q = 0; q < kThreads / 64; ++q) s += part[q][threadIdx.x];
     unsafeAtomicAdd(norm_slots + (size_t)(blockIdx.x % kSlots) * (2 * kMaxNt) + threadIdx.x, s);
+  }
+  if (sk) {  // the barrier above ordered every bin update before these reads
+    double* sl = bat(ps.slots, bs) + (size_t)(blockIdx.x % kSlots) * ps.d;
+    for (int b = threadIdx.x; b < ps.d; b += kThreads) {
+      const double v = pbins[b];
+      if (v != 0.0) unsafeAtomicAdd(sl + b, v);
+    }
   }
 }
 
@@ -1079,9 +1105,11 @@ hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb, const GrowBuf
 
 template <typename T>
 static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, const double* C, T* W, double* x,
-                          int64_t ldx, double* ns, const State* st, int nb, size_t bs) {
+                          int64_t ldx, double* ns, const State* st, int nb, size_t bs, const PassSketch& ps) {
   const dim3 g(grid, nb);
-#define FAB_P(NTV) hipLaunchKernelGGL((k_pass<T, NTV>), g, dim3(kThreads), 0, s, n, m, nt, C, W, x, ldx, ns, st, bs)
+  const size_t lds = ps.slots ? (size_t)ps.d * sizeof(double) : 0;
+#define FAB_P(NTV) \
+  hipLaunchKernelGGL((k_pass<T, NTV>), g, dim3(kThreads), lds, s, n, m, nt, C, W, x, ldx, ns, st, bs, ps)
   if (nt <= 1)
     FAB_P(1);
   else if (nt <= 2)
@@ -1096,11 +1124,13 @@ static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, const d
 }
 
 hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt, const double* C, void* W,
-                       double* x, int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs) {
+                       double* x, int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs,
+                       const PassSketch& ps) {
+  if (ps.slots && (ps.zeta < 1 || ps.zeta > 8 || ps.d < 1 || ps.d > kMaxD)) return hipErrorInvalidValue;
   if (dtype == 0)
-    launch_pass_t<double>(s, grid, n, m, nt, C, (double*)W, x, ldx, norm_slots, st, nb, bs);
+    launch_pass_t<double>(s, grid, n, m, nt, C, (double*)W, x, ldx, norm_slots, st, nb, bs, ps);
   else
-    launch_pass_t<float>(s, grid, n, m, nt, C, (float*)W, x, ldx, norm_slots, st, nb, bs);
+    launch_pass_t<float>(s, grid, n, m, nt, C, (float*)W, x, ldx, norm_slots, st, nb, bs, ps);
   return hipGetLastError();
 }
 

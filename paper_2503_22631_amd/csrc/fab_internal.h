@@ -200,6 +200,15 @@ __device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
   return a;
 }
 
+// Sketch of the restart vector accumulated by the pass for the next cycle's start (slots ==
+// nullptr: the pass does not sketch, and the cycle starts with a sketch-only pass instead).
+struct PassSketch {
+  double* slots;  // kSlots x d accumulators of the next cycle's start (member r at r * bs)
+  int d, zeta;    // zeta <= 8
+  uint32_t k0, k1;
+  double scale;   // 1/sqrt(zeta) rounded to the value type, as the sketch-only pass applies it
+};
+
 // Workspace carving, shared by the driver and workspace_size().
 // Workspace of the growing restart (one member): blocks, couplings and sizes per cycle.
 struct GrowBuffers {
