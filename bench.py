@@ -80,7 +80,28 @@ def cpu_info():
     return {"nproc": os.cpu_count(), "model": model or platform.processor()}
 
 
-def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=()):
+def cpu_plain_leg(A, b):
+    """The plain restarted Arnoldi method on the host cores (cpu_baseline/, C++/OpenMP, FP64, CGS2,
+    the same quadrature restart and stopping test as the GPU comparator), on the same workload: one
+    warm-up solve and up to three timed ones, about 10 s of work at most."""
+    import cpu_baseline
+
+    w = WORKLOAD
+    run = lambda: cpu_baseline.expv(A.rowptr, A.colind, A.vals, b, w["t"], w["m"], tol=w["tol"], max_cycles=100)
+    x, info = run()
+    solves, total = 0, 0.0
+    while solves < 3 and (solves == 0 or total < 6.0):
+        t0 = time.perf_counter()
+        x, info = run()
+        total += time.perf_counter() - t0
+        solves += 1
+    dt = total / solves
+    return {"solves_per_s": 1.0 / dt, "seconds_per_solve": dt, "threads": cpu_baseline.threads(),
+            "cycles": info["cycles"], "matvecs": info["matvecs"], "status": info["status"],
+            "sample": f"{solves} timed solve(s) after one warm-up"}, x
+
+
+def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=(), x_cpu_plain=None):
     """The oracle, as it stands, on the host: complete solves of the same workload by its FP64
     step-by-step twin (same sketch), with BLAS limited to one thread, repeated until about 10 s of
     CPU work (at most 4 solves).  Also the exact solution by the Kronecker-product closed form, for
@@ -111,7 +132,8 @@ def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=()):
                        f"{info.matvecs} matvecs each, sketch generation included; scipy CSR products, 1 BLAS "
                        f"thread); {total:.1f} s in total",
              "seconds_per_solve": dt, "oracle_rel_err": rel(xo)},
-            {"gpu_rel_err": rel(x_gpu), "plain_rel_err": rel(x_plain) if x_plain is not None else None})
+            {"gpu_rel_err": rel(x_gpu), "plain_rel_err": rel(x_plain) if x_plain is not None else None,
+             "cpu_plain_rel_err": rel(x_cpu_plain) if x_cpu_plain is not None else None})
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str):
@@ -449,12 +471,17 @@ def main():
         torch.cuda.empty_cache()
         out["extra"], checks = extra_legs(fab, ctx)
     if not args.no_cpu_baseline:
-        cpu, errs = cpu_baseline_leg(A, b, x_gpu, x_plain, checks)
+        x_cpu_plain = None
+        if comparison is not None:  # the plain method on the host cores, beside the GPU comparator
+            comparison["cpu_plain_arnoldi"], x_cpu_plain = cpu_plain_leg(A, b)
+            comparison["sketched_gpu_vs_plain_cpu"] = value * comparison["cpu_plain_arnoldi"]["seconds_per_solve"]
+        cpu, errs = cpu_baseline_leg(A, b, x_gpu, x_plain, checks, x_cpu_plain)
         cpu["host"] = cpu_info()
         out["cpu_baseline"] = cpu
         out["rel_err_vs_oracle"] = errs["gpu_rel_err"]
         if comparison is not None:
             comparison["plain_rel_err_vs_oracle"] = errs["plain_rel_err"]
+            comparison["cpu_plain_arnoldi"]["rel_err_vs_oracle"] = errs["cpu_plain_rel_err"]
     print(json.dumps(out), flush=True)
     return 0
 
