@@ -193,7 +193,8 @@ fab_status fab_sketch_table(fab_ctx* ctx, int64_t col0, int64_t count, int32_t d
  * W n x (m+1) (A's dtype, column-major), U = S W d x (m+1), R (m+1) x m, T (m+1) x (m+1)
  * (all FP64 column-major), Rt m x m = R_m + r_{m+1,m} (T_m^{-1} t) e_m^T, the projected matrix
  * in the basis W (the whitened X of the appendix's eq. A.1 is T_m Rt T_m^{-1}), and
- * h_scal[4] = {alpha, beta, h, m_eff}. */
+ * h_scal[5] = {alpha, beta, h, m_eff, whitening}: whitening = 1 when T came from the Cholesky
+ * factor of the Gram matrix kept by the steps, 0 when from the Householder QR of U. */
 fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const fab_params* p,
                            void* W, double* U, double* R, double* T, double* Rt, double* h_scal,
                            void* work, size_t work_bytes);

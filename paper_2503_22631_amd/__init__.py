@@ -296,14 +296,14 @@ def cycle_debug(op: CSROperator, v: torch.Tensor, **kw):
     R = torch.empty((m, m + 1), dtype=torch.float64, device=dev)
     T = torch.empty((m + 1, m + 1), dtype=torch.float64, device=dev)
     X = torch.empty((m, m), dtype=torch.float64, device=dev)
-    scal = (ctypes.c_double * 4)()
+    scal = (ctypes.c_double * 5)()
     work = ctx.workspace(workspace_size(op, p, 1))
     st = ctx.lib.fab_cycle_debug(ctx.handle, op.handle, _ptr(v.contiguous()), ctypes.byref(p), _ptr(W), _ptr(U),
                                  _ptr(R), _ptr(T), _ptr(X), scal, _ptr(work), work.numel())
     _lib.check(st, "fab_cycle_debug", ok=(0,))
     meff = int(scal[3])
     return {"W": W.t(), "U": U.t(), "R": R.t(), "T": T.t(), "Rt": X.t(), "alpha": scal[0], "beta": scal[1],
-            "h": scal[2], "m": meff}
+            "h": scal[2], "m": meff, "whiten": "cholesky" if scal[4] == 1.0 else "householder"}
 
 
 def dot(ctx: Context, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:

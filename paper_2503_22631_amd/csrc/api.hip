@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -70,7 +71,7 @@ constexpr int kDotBlocks = 1024;  // partial sums of fab_dot (fixed grid: reprod
 using namespace fab;
 
 struct GraphKey {
-  const void* op;
+  uint64_t op;  // fab_op::serial
   const void* work;
   const void* x;
   int64_t n;
@@ -125,7 +126,14 @@ struct fab_op {
   const void* vals;
   int dtype;
   void* owned;  // device storage the library allocated for this operator (transposes), else null
+  uint64_t serial = 0;  // unique per operator for the process: keys the cached graphs, whose kernel
+                        // arguments hold this operator's arrays (an address can be reused after a destroy)
 };
+
+static uint64_t next_op_serial() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
+}
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -497,7 +505,7 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
     return FAB_E_INVALID;
   if (dtype != FAB_F64 && dtype != FAB_F32) return FAB_E_INVALID;
   if (n >= ((int64_t)1 << 31)) return FAB_E_UNSUPPORTED;
-  fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype, nullptr};
+  fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype, nullptr, next_op_serial()};
   if (!o) return FAB_E_HIP;
   const fab_status st = validate_op(ctx, o);
   if (st != FAB_OK) {
@@ -565,7 +573,7 @@ fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT) {
   FAB_TRYT(hipStreamSynchronize(s));
 #undef FAB_TRYT
   (void)hipFree(tmp);
-  fab_op* o = new (std::nothrow) fab_op{ctx, A->n, A->nnz, rowptrT, colT, valT, A->dtype, base};
+  fab_op* o = new (std::nothrow) fab_op{ctx, A->n, A->nnz, rowptrT, colT, valT, A->dtype, base, next_op_serial()};
   if (!o) {
     (void)hipFree(base);
     return FAB_E_HIP;
@@ -792,7 +800,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
 
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
-  key.op = A;
+  key.op = A->serial;
   key.work = work;
   key.x = x;
   key.n = A->n;
@@ -951,8 +959,8 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   uint64_t tolbits;
   std::memcpy(&tolbits, &p->tol, 8);
   key.push_back((uintptr_t)tolbits);
-  for (int i = 0; i < nops; ++i) {
-    key.push_back((uintptr_t)ops[i]);
+  for (int i = 0; i < nops; ++i) {  // operators by serial: a destroyed operator's address can be reused
+    key.push_back((uintptr_t)ops[i]->serial);
     key.push_back((uintptr_t)x[i]);
   }
   auto cycle_of = [&](int i, hipStream_t st) {
@@ -1137,6 +1145,7 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
   h_scal[1] = hst.beta;
   h_scal[2] = hst.h;
   h_scal[3] = (double)hst.meff;
+  h_scal[4] = (double)hst.whiten_chol;
   return hst.nonfinite ? FAB_E_NONFINITE : FAB_OK;
 }
 

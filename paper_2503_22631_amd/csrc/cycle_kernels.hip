@@ -324,16 +324,25 @@ __device__ void whiten_tail(const SmallArgs& a, const double* Ts, int ldT, int m
 
 // T from the sketched Gram matrix G = U^T U = T^T T (kept row by row by the steps): LDL^T in LDS
 // by columns, one barrier per column (wave w updates rows c+1+w, c+10+w, .., lane l column c+1+l),
-// then T_kk = sqrt(D_k) and T_ki = L_ik sqrt(D_k).  Cholesky squares the condition number, so it
-// is taken only while every pivot keeps at least kCholMinPivot of its column's squared norm
-// (cond_2(U) up to about 1e3, where T is still accurate to 1e-10 relative); otherwise it returns
-// false and the caller runs the Householder QR.  Every thread returns the same result.  (Measured
-// on the 128^3 workload: 38 us per cycle end against 114 us for the Householder QR.  Keeping the
-// trailing entries in registers and publishing each column was slower, 44 us.)
+// then T_kk = sqrt(D_k) and T_ki = L_ik sqrt(D_k).  Cholesky squares the condition number: its T
+// is off by about cond_2(U)^2 eps relative, against cond_2(U) eps for the Householder QR, and the
+// restarted iteration can amplify that difference (on a 256^3 z^(-1/2) solve with k = 2, a cycle
+// with cond_2(U) = 3e4 left T off by 1e-9 and moved the solve from 33 to 33-91 cycles).  So the
+// factor is kept only when kappa_F(T) = ||T||_F ||T^{-1}||_F, an upper bound on cond_2(U), is at
+// most kCholMaxCond; T^{-1} comes from a bottom-up row solve in one wavefront (lane = column).
+// Otherwise, and for a pivot below kCholMinPivot of its column's squared norm or more than 64
+// columns, it returns false and the caller runs the Householder QR.  Every thread returns the same
+// result.  (Measured on the 128^3 workload: 66 us per cycle end, 38 of them the LDL^T, against
+// 114 us for the Householder QR.  Keeping the trailing entries in registers and publishing each
+// column made the LDL^T slower, 44 us.)
 constexpr double kCholMinPivot = 1e-6;
+constexpr double kCholMaxCond = 1000.0;  // accepted factors stay within about 3e-13 of the Householder T
 
 __device__ bool whiten_gram(const SmallArgs& a, int cols, double* Ts, int ldT, double* gd) {
+  __shared__ double Xs[64 * 64];  // T^{-1}, row-major
+  __shared__ double s_inv2;       // ||T^{-1}||_F^2
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = kWhitenThreads, nwv = kWhitenThreads / 64;
+  if (cols > 64) return false;  // uniform: no barrier passed yet
   const int ldg = a.m + 1;
   constexpr int kPer = ((kMaxM + 1) * (kMaxM + 1) + kWhitenThreads - 1) / kWhitenThreads;
   double gv[kPer];  // all loads in flight together: one memory latency, not one per entry
@@ -371,7 +380,35 @@ __device__ bool whiten_gram(const SmallArgs& a, int cols, double* Ts, int ldT, d
     else if (k == i) Ts[i * ldT + i] = gd[i];
   }
   __syncthreads();
-  return true;
+  // kappa_F(T): ||T^{-1}||_F from X = T^{-1} (upper), row i from the rows below it, X[l][c] = 0 for
+  // l > c; ||T||_F from the upper triangle.  (Reading eight (T, X) pairs per round trip instead
+  // made this kernel slower on the 128^3 workload, 122 us against 66.)
+  if (wv == 0) {
+    double ss = 0.0;
+    for (int i = cols - 1; i >= 0; --i) {
+      double acc = (lane == i) ? 1.0 : 0.0;
+      for (int l = i + 1; l < cols; ++l) acc -= Ts[i * ldT + l] * Xs[l * 64 + lane];
+      const double xi = (lane >= i && lane < cols) ? acc / Ts[i * ldT + i] : 0.0;
+      Xs[i * 64 + lane] = xi;
+      ss += xi * xi;
+    }
+    ss = wave_sum_c(ss);
+    if (lane == 0) s_inv2 = ss;
+  }
+  double ts = 0.0;
+  for (int e = tid; e < cols * cols; e += nthr) {
+    const int i = e / cols, l = e % cols;
+    if (l >= i) ts += Ts[i * ldT + l] * Ts[i * ldT + l];
+  }
+  ts = wave_sum_c(ts);
+  __syncthreads();  // s_inv2 written; Xs no longer read
+  if (lane == 0) Xs[wv] = ts;
+  __syncthreads();
+  double t2 = 0.0;
+  for (int q = 0; q < nwv; ++q) t2 += Xs[q];
+  const bool ok = (t2 * s_inv2 <= kCholMaxCond * kCholMaxCond);  // the same values in every thread
+  __syncthreads();  // every thread has read Xs and s_inv2
+  return ok;
 }
 
 // Whitening QR with the sketched basis in registers (d <= 8 KR).  Column q of U is owned by the
@@ -400,6 +437,7 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a0) {
   if constexpr (KR <= 32) {  // the steps keep G only for d <= 256
     if (!a.plain && st->gram_rows >= cols && whiten_gram(a, cols, Ts, ldT, diagR)) {
       whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+      if (tid == 0) st->whiten_chol = 1;
       return;
     }
   }
@@ -487,6 +525,7 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten(SmallArgs a0) {
   }
   __syncthreads();
   whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+  if (tid == 0) st->whiten_chol = 0;
 }
 
 // Whitening QR for large d (> 512): the same column-parallel Householder QR with the basis in
@@ -574,6 +613,7 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a0) {
   }
   __syncthreads();
   whiten_tail(a, Ts, ldT, mm, brk, s_lds);
+  if (tid == 0) st->whiten_chol = 0;
 }
 
 // Quadrature solves, one wavefront per system s: (zeta_s I - Rt) y = e_1 with Rt upper Hessenberg.

@@ -129,6 +129,7 @@ struct State {
   double grow_alpha1, grow_rt;
   int grow_c, grow_p, grow_fail;
   int gram_rows;  // rows of the sketched Gram matrix G = U^T U complete in this cycle (0: none kept)
+  int whiten_chol;  // this cycle's T: 1 from the Cholesky factor of G, 0 from the Householder QR
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
