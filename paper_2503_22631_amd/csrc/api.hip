@@ -172,8 +172,6 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   // growing restart: blocks (kGrowRows x m), couplings and sizes per cycle
   L.grow = take(p->method == FAB_SKETCHED_GROWING ? (size_t)kGrowRows * m * 8 + (size_t)kGrowRows * 12 : 0);
   L.G = take((size_t)(m + 1) * (m + 1) * 8);
-  L.scratch = take(0);
-  L.ldscr = m;
   L.report = 0;
   L.total = off;
   return L;
@@ -218,7 +216,7 @@ struct Ptrs {
   void* W;
   double *U, *R, *slots_step, *slots_start, *slots_norm, *T, *Ut, *X, *C, *gbuf, *tvals, *G;
   State* st;
-  cplx *rz, *rw, *psi, *scr;
+  cplx *rz, *rw, *psi;
   size_t step_len;
 };
 
@@ -241,7 +239,6 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   q.psi = (cplx*)(q.base + L.psi);
   q.gbuf = (double*)(q.base + L.gbuf);
   q.tvals = q.gbuf + (size_t)nt * p->m;
-  q.scr = (cplx*)(q.base + L.scratch);
   q.G = (double*)(q.base + L.G);
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   q.step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
@@ -374,7 +371,6 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.plain = plain ? 1 : 0;
   a.fun = fun;
   a.nq = L.nq;
-  a.ldscr = L.ldscr;
   a.U = q.U;
   a.Uq = q.Ut;
   a.R = q.R;
@@ -383,7 +379,6 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   a.rz = q.rz;
   a.rw = q.rw;
   a.psi = q.psi;
-  a.scr = q.scr;
   a.gbuf = q.gbuf;
   a.C = q.C;
   a.G = q.G;

@@ -165,7 +165,7 @@ __host__ __device__ __forceinline__ size_t wcol(int64_t n, int es) {
 
 // Arguments of the cycle-end kernel.
 struct SmallArgs {
-  int d, m, nt, plain, fun, nq, ldscr;
+  int d, m, nt, plain, fun, nq;
   const double* U;
   double* Uq;       // d x (m+1) scratch for the Householder QR
   const double* R;  // (m+1) x m
@@ -174,7 +174,6 @@ struct SmallArgs {
   const cplx* rz;
   const cplx* rw;
   cplx* psi;
-  cplx* scr;        // per-system restart contributions, entry i of system s at scr[s * ldscr + i]
   double* gbuf;     // nt x m: the rule sums of the cycle (restart coefficients before k_combine)
   double* C;        // (m+1) x (nt+1) pass coefficients (main rule), restart column last
   const double* G;  // (m+1) x (m+1) sketched Gram matrix, row-major lower triangle (st->gram_rows rows)
@@ -193,7 +192,6 @@ __device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
   a.rz = bat(a0.rz, bs);
   a.rw = bat(a0.rw, bs);
   a.psi = bat(a0.psi, bs);
-  a.scr = bat(a0.scr, bs);
   a.gbuf = bat(a0.gbuf, bs);
   a.C = bat(a0.C, bs);
   a.G = bat(a0.G, bs);
@@ -221,8 +219,8 @@ struct GrowBuffers {
 
 struct Layout {
   size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
-      grow, G, scratch, report, total;
-  int nsys, nq, ldscr;
+      grow, G, report, total;
+  int nsys, nq;
 };
 
 }  // namespace fab
