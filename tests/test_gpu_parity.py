@@ -327,6 +327,29 @@ def test_breakdown_on_eigenvector(fab, ctx):
     assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-12
 
 
+def test_cached_graph_follows_the_operator_not_its_address(fab, ctx):
+    """Operators of the same size created one after another, each destroyed before the next: the
+    allocator tends to hand the next one the same host address, and the solves share one x and the
+    context's workspace.  The destroyed operators' arrays are kept alive, so the new ones live
+    elsewhere; every solve must use its own operator's arrays, not a graph cached for a destroyed
+    one (a cache keyed on the operator's address replays the previous operator here)."""
+    N, t = 32, 1e-3
+    A = wl.laplacian_2d(N)
+    b = wl.gaussian_vector(A.n, 5)
+    bt = torch.as_tensor(b, device="cuda")
+    xbuf = torch.empty((1, A.n), dtype=torch.float64, device="cuda")  # one x for every solve
+    keep = []
+    for scale in (1.0, 2.0, 0.5):
+        op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals * scale)
+        x, info = fab.solve(op, bt, "exp", t=t, x=xbuf, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10)
+        ref = exact.sine_fab("exp", b, N, [scale, scale], t=t)
+        assert info["status"] == "FAB_OK"
+        assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-9, scale
+        keep.append((op.rowptr, op.colind, op.vals))
+        op.close()
+        del op, x
+
+
 def test_zero_rhs_gives_zero(fab, ctx):
     A = wl.laplacian_2d(20)
     op = _op(fab, ctx, A)
