@@ -685,11 +685,16 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? s_coef[q] : 0.0;
   // two register sets in turn; the prefetch past the block's last batch has size 0 (no memory
   // traffic), so every trip issues the same loads and stores
+  // (loads at raised wave priority, as in the fused product: measured 0.1 us per step)
   for (int it = 0;;) {
+    __builtin_amdgcn_s_setprio(2);
     ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
+    __builtin_amdgcn_s_setprio(0);
     ou_store<T, KMAX>(out, n, start(it), t, coef, inv, za, wa);
     if (++it >= cnt) break;
+    __builtin_amdgcn_s_setprio(2);
     ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, za, wa);
+    __builtin_amdgcn_s_setprio(0);
     ou_store<T, KMAX>(out, n, start(it), t, coef, inv, zb, wb);
     if (++it >= cnt) break;
   }
