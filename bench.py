@@ -41,11 +41,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_sketch_convdiff128_traffic.j
 COPY_BYTES = 256 << 20
 
 
-def algorithmic_bytes(n: int, nnz: int, k: int, es: int = 8):
-    """Bytes the method must move (int32 indices): per launch of the fused SpMV + sketch kernel
-    (values + column indices + row pointers + read w_j + write z; S is generated, not read) and
-    per Arnoldi step (that plus the window update: read z and k basis columns, write w_{j+1})."""
-    spmv = (es + 4) * nnz + 4 * (n + 1) + 2 * es * n
+def algorithmic_bytes(n: int, nnz: int, k: int, es: int = 8, ib: int = 4):
+    """Bytes the method must move: per launch of the fused SpMV + sketch kernel (values + column
+    indices of ib bytes, the operator's stored form + row pointers + read w_j + write z; S is
+    generated, not read) and per Arnoldi step (that plus the window update: read z and k basis
+    columns, write w_{j+1})."""
+    spmv = (es + ib) * nnz + 4 * (n + 1) + 2 * es * n
     step = spmv + (2 + k) * es * n
     return spmv, step
 
@@ -262,7 +263,7 @@ def extra_legs(fab, ctx):
                   check=False)
         tm = fab.timing_read(ctx)
         fab.timing_enable(ctx, False)
-        sb, stb = algorithmic_bytes(A.n, A.nnz, 2, es=4 if dt == torch.float32 else 8)
+        sb, stb = algorithmic_bytes(A.n, A.nnz, 2, es=4 if dt == torch.float32 else 8, ib=op.index_bytes())
         spmv_gbs = sb / (tm["spmv_ms"] / tm["spmv_launches"] / 1e3) / 1e9
         loop_gbs = stb * tm["loop_steps"] / (tm["loop_ms"] / 1e3) / 1e9
         leg[name]["roofline"] = {"spmv_sketch_GB/s": spmv_gbs, "spmv_sketch_frac": spmv_gbs / HBM_PEAK_GBS,
@@ -419,7 +420,7 @@ def main():
     tm = fab.timing_read(ctx)
     fab.timing_enable(ctx, False)
 
-    spmv_bytes, step_bytes = algorithmic_bytes(A.n, A.nnz, w["k"])
+    spmv_bytes, step_bytes = algorithmic_bytes(A.n, A.nnz, w["k"], ib=op.index_bytes())
     spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_launches"], 1) / 1e3
     achieved = spmv_bytes / spmv_avg_s / 1e9
     loop_gbs = step_bytes * tm["loop_steps"] / (tm["loop_ms"] / 1e3) / 1e9 if tm["loop_ms"] > 0 else None

@@ -114,7 +114,12 @@ fab_status fab_destroy(fab_ctx* ctx);
  * structure must not change while it exists.  Creation checks the structure on
  * the device (row pointers non-decreasing from 0 to nnz, column indices in
  * [0, n)), after the work already queued on the caller's stream, and
- * synchronises the context's stream.
+ * synchronises the context's stream.  When every column index lies within
+ * [-32768, 32767] of the first row of its row's 256-row tile (bandwidth below
+ * 32K, e.g. grid operators in natural order), creation also derives a 16-bit
+ * copy of the column indices (2 bytes per nonzero, library-owned, freed by
+ * fab_op_destroy) that the products read instead of colind; see
+ * fab_op_index_bytes.
  * Errors: FAB_E_INVALID (n <= 0, nnz < 0, nnz >= 2^31, null pointers, a
  * malformed CSR), FAB_E_UNSUPPORTED (n >= 2^31), FAB_E_HIP. */
 fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
@@ -129,6 +134,12 @@ fab_status fab_op_destroy(fab_op* op);
  * to nnz, column indices in [0, n)).  Errors: FAB_E_INVALID (null arguments or
  * a malformed CSR), FAB_E_HIP (allocation or launch failure). */
 fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT);
+
+/* *h_bytes = bytes per column index the products read: 2 when the operator
+ * carries the 16-bit tile offsets described at fab_csr_create (also derived
+ * for fab_op_transpose results), else 4.  Errors: FAB_E_INVALID (null
+ * arguments). */
+fab_status fab_op_index_bytes(const fab_op* A, int32_t* h_bytes);
 
 /* Copy an operator's arrays (rowptr[n+1], colind[nnz], vals[nnz] in its dtype)
  * into caller-provided device buffers (test hook for fab_op_transpose). */

@@ -98,6 +98,12 @@ class CSROperator:
         op.n, op.nnz, op.dtype, op.handle = self.n, self.nnz, self.dtype, h
         return op
 
+    def index_bytes(self) -> int:
+        """Bytes per column index the products read (2 with the 16-bit tile offsets, else 4)."""
+        v = ctypes.c_int32()
+        _lib.check(self.ctx.lib.fab_op_index_bytes(self.handle, ctypes.byref(v)), "fab_op_index_bytes", ok=(0,))
+        return v.value
+
     def arrays(self):
         """Copies of the operator's (rowptr, colind, vals) as device tensors."""
         dev = self.ctx.device

@@ -19,7 +19,7 @@
 
 namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
-                              const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
+                              const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st, int nb, int G, size_t bs);
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta);
 int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta);
@@ -61,6 +61,7 @@ hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, 
 hipError_t launch_dot(hipStream_t, int64_t n, const double* x, const double* y, double* part, int max_blocks,
                       double* out);
 hipError_t launch_csr_validate(hipStream_t, int n, int nnz, const int* rowptr, const int* colind, int* flag);
+hipError_t launch_col_offsets(hipStream_t, int n, const int* rowptr, const int* colind, int16_t* off, int* flag);
 size_t transpose_scan_blocks(int64_t len);
 hipError_t launch_transpose(hipStream_t, int dtype, int n, int nnz, const int* rowptr, const int* colind,
                             const void* vals, int* rowptrT, int* colT, void* valT, int* cursor, int* sums);
@@ -128,6 +129,7 @@ struct fab_op {
   void* owned;  // device storage the library allocated for this operator (transposes), else null
   uint64_t serial = 0;  // unique per operator for the process: keys the cached graphs, whose kernel
                         // arguments hold this operator's arrays (an address can be reused after a destroy)
+  int16_t* colrel = nullptr;  // library-owned 16-bit column offsets (see derive_col_offsets), else null
 };
 
 static uint64_t next_op_serial() {
@@ -303,8 +305,8 @@ static fab_status enqueue_first_sketch(const fab_ctx* ctx, hipStream_t s, const 
   if (!pass_sketches(p)) return FAB_OK;
   const int n = (int)A->n;
   const int g_sk = spmv_grid(ctx, n, A->dtype, 1, p->d, B.G, p->zeta);
-  FAB_TRY(launch_spmv_sketch(s, A->dtype, 1, g_sk, n, A->rowptr, A->colind, A->vals, q.W, nullptr, p->d, p->zeta,
-                             p->seed, q.slots_start, q.st, B.nb, B.G, B.bs));
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 1, g_sk, n, A->rowptr, A->colind, A->colrel, A->vals, q.W, nullptr, p->d,
+                             p->zeta, p->seed, q.slots_start, q.st, B.nb, B.G, B.bs));
   return FAB_OK;
 }
 
@@ -324,8 +326,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const bool pass_sk = with_pass && pass_sketches(p);
   if (!plain) {
     if (!pass_sk)  // otherwise the set-up or the previous cycle's pass accumulated S w_1 already
-      FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->vals, col(0), nullptr, d, p->zeta,
-                                 p->seed, q.slots_start, q.st, nb, B.G, bs));
+      FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->colrel, A->vals, col(0), nullptr, d,
+                                 p->zeta, p->seed, q.slots_start, q.st, nb, B.G, bs));
   } else {
     FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
   }
@@ -336,8 +338,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
     double* set_nxt = q.slots_step + (size_t)((j + 1) & 1) * q.step_len;
     if (!plain) {
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
-      FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), d,
-                                 p->zeta, p->seed, set_cur, q.st, nb, B.G, bs));
+      FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
+                                 d, p->zeta, p->seed, set_cur, q.st, nb, B.G, bs));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
@@ -352,8 +354,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
-      FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->vals, col(j), col(j + 1), 1, 1, 0,
-                                 nullptr, q.st, 1, 1, 0));
+      FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
+                                 1, 1, 0, nullptr, q.st, 1, 1, 0));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
@@ -494,6 +496,34 @@ static fab_status validate_op(fab_ctx* ctx, const fab_op* o) {
   return flag ? FAB_E_INVALID : FAB_OK;
 }
 
+// The fused product reads a column index as a 16-bit offset from the first row of its row's
+// kThreads-row tile when every column of the matrix lies within [-32768, 32767] of that row
+// (matrices of bandwidth below 32K rows, such as grid operators in natural ordering): 10 instead
+// of 12 bytes per FP64 nonzero.  The offsets are derived once, from column indices already checked
+// to lie in [0, n), so a decoded index stays in range.  Any other matrix, or a failed allocation of
+// the 2 bytes per nonzero, leaves colrel null and the product reads colind.
+static fab_status derive_col_offsets(fab_ctx* ctx, fab_op* o) {
+  if (o->nnz == 0) return FAB_OK;
+  int16_t* off = nullptr;
+  if (hipMalloc((void**)&off, sizeof(int16_t) * (size_t)o->nnz) != hipSuccess) {
+    (void)hipGetLastError();  // out of memory: keep the 32-bit indices
+    return FAB_OK;
+  }
+  hipStream_t s = ctx->work;
+  int* dflag = reinterpret_cast<int*>(ctx->d_part);  // the context's reduction buffer, free between calls
+  int flag = 0;
+  hipError_t e = hipMemsetAsync(dflag, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_col_offsets(s, (int)o->n, o->rowptr, o->colind, off, dflag);
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess || flag != 0) {
+    (void)hipFree(off);
+    return e != hipSuccess ? hip_fail(e, "column offsets", __LINE__) : FAB_OK;
+  }
+  o->colrel = off;
+  return FAB_OK;
+}
+
 fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
                           const void* vals, int32_t dtype, fab_op** op) {
   if (!ctx || !op || n <= 0 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !rowptr || (nnz > 0 && (!colind || !vals)))
@@ -502,7 +532,8 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
   if (n >= ((int64_t)1 << 31)) return FAB_E_UNSUPPORTED;
   fab_op* o = new (std::nothrow) fab_op{ctx, n, nnz, rowptr, colind, vals, dtype, nullptr, next_op_serial()};
   if (!o) return FAB_E_HIP;
-  const fab_status st = validate_op(ctx, o);
+  fab_status st = validate_op(ctx, o);
+  if (st == FAB_OK) st = derive_col_offsets(ctx, o);
   if (st != FAB_OK) {
     delete o;
     return st;
@@ -514,6 +545,7 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
 fab_status fab_op_destroy(fab_op* op) {
   if (!op) return FAB_E_INVALID;
   if (op->owned) (void)hipFree(op->owned);  // hipFree waits for the device
+  if (op->colrel) (void)hipFree(op->colrel);
   delete op;
   return FAB_OK;
 }
@@ -573,7 +605,18 @@ fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT) {
     (void)hipFree(base);
     return FAB_E_HIP;
   }
+  const fab_status st = derive_col_offsets(ctx, o);
+  if (st != FAB_OK) {
+    (void)fab_op_destroy(o);
+    return st;
+  }
   *AT = o;
+  return FAB_OK;
+}
+
+fab_status fab_op_index_bytes(const fab_op* A, int32_t* h_bytes) {
+  if (!A || !h_bytes) return FAB_E_INVALID;
+  *h_bytes = A->colrel ? 2 : 4;
   return FAB_OK;
 }
 
@@ -657,8 +700,8 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
       if (rep == 1) err = hipEventRecord(e0, s);
       if (err == hipSuccess)
-        err = launch_spmv_sketch(s, dt, 0, grid, n, A->rowptr, A->colind, A->vals, x0, y0, d, p->zeta, p->seed,
-                                 q.slots_step, nullptr, nb, G, bs);
+        err = launch_spmv_sketch(s, dt, 0, grid, n, A->rowptr, A->colind, A->colrel, A->vals, x0, y0, d, p->zeta,
+                                 p->seed, q.slots_step, nullptr, nb, G, bs);
     }
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -1068,7 +1111,7 @@ fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void*
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
   FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1, 1), (int)A->n, A->rowptr, A->colind,
-                             A->vals, x, y, 1, 1, 0, nullptr, nullptr, 1, 1, 0));
+                             A->colrel, A->vals, x, y, 1, 1, 0, nullptr, nullptr, 1, 1, 0));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }
@@ -1084,7 +1127,7 @@ fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, ui
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
   double* slots = (double*)work;
   FAB_TRY(launch_zero(s, slots, (size_t)kSlots * d));
-  FAB_TRY(launch_spmv_sketch(s, dtype, 1, spmv_grid(ctx, n, dtype, 1, d), (int)n, nullptr, nullptr, nullptr, x,
+  FAB_TRY(launch_spmv_sketch(s, dtype, 1, spmv_grid(ctx, n, dtype, 1, d), (int)n, nullptr, nullptr, nullptr, nullptr, x,
                              nullptr, d, zeta, seed, slots, nullptr, 1, 1, 0));
   FAB_TRY(launch_reduce_slots(s, d, slots, Sx));
   FAB_TRY(hipStreamSynchronize(s));

@@ -35,6 +35,25 @@ __global__ void k_csr_validate(int n, int nnz, const int* __restrict__ rowptr, c
   if (bad) atomicOr(flag, bad);
 }
 
+// off[p] = colind[p] - (first row of the row's kThreads-row tile), the fused product's 16-bit column
+// form; flag = 1 when some offset does not fit in 16 bits (off is then not used).
+__global__ void k_col_offsets(int n, const int* __restrict__ rowptr, const int* __restrict__ colind,
+                              int16_t* __restrict__ off, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n; i += stride) {
+    const int row0 = (int)(i - i % kThreads);
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+      const int dlt = colind[p] - row0;
+      if (dlt < -32768 || dlt > 32767)
+        bad = 1;
+      else
+        off[p] = (int16_t)dlt;
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 __global__ void k_count_cols(int nnz, const int* __restrict__ colind, int* __restrict__ cnt) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < (int64_t)nnz; p += stride)
@@ -152,6 +171,11 @@ static int grid_for(int64_t items, int threads, int cap) {
 hipError_t launch_csr_validate(hipStream_t s, int n, int nnz, const int* rowptr, const int* colind, int* flag) {
   const int64_t items = (int64_t)(n > nnz ? n : nnz);
   hipLaunchKernelGGL(k_csr_validate, dim3(grid_for(items, 256, 4096)), dim3(256), 0, s, n, nnz, rowptr, colind, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_offsets(hipStream_t s, int n, const int* rowptr, const int* colind, int16_t* off, int* flag) {
+  hipLaunchKernelGGL(k_col_offsets, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, rowptr, colind, off, flag);
   return hipGetLastError();
 }
 

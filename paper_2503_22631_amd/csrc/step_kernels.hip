@@ -73,26 +73,50 @@ constexpr int kGather = 8;
 // Stage nonzeros [cs, cs+len) of the tile into LDS (values and column indices).  All loads are
 // issued before the first LDS write, so the tile waits for one memory round trip rather than one
 // per element.  Barriers on both sides (the previous chunk has been consumed; this one is ready).
+// With colrel (operators whose columns all lie within 16 bits of their tile's first row, row0) the
+// columns are read as those 16-bit offsets: 2 bytes per nonzero instead of 4.  The offsets are
+// added to row0 only when written to LDS, so no load waits for another.
 template <typename T>
-__device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const int* __restrict__ colind, int cs,
-                                            int len, T* sv, int* sc) {
+__device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const int* __restrict__ colind,
+                                            const int16_t* __restrict__ colrel, int row0, int cs, int len, T* sv,
+                                            int* sc) {
   __syncthreads();
   T tv[kChunk / kThreads];
-  int tc[kChunk / kThreads];
+  if (colrel) {  // uniform over the grid
+    int tr[kChunk / kThreads];  // one register per offset: 16-bit pairs would make each load wait
 #pragma unroll
-  for (int q = 0; q < kChunk / kThreads; ++q) {
-    const int e = threadIdx.x + q * kThreads;
-    if (e < len) {
-      tv[q] = vals[cs + e];
-      tc[q] = colind[cs + e];
+    for (int q = 0; q < kChunk / kThreads; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < len) {
+        tv[q] = vals[cs + e];
+        tr[q] = colrel[cs + e];
+      }
     }
-  }
 #pragma unroll
-  for (int q = 0; q < kChunk / kThreads; ++q) {
-    const int e = threadIdx.x + q * kThreads;
-    if (e < len) {
-      sv[e] = tv[q];
-      sc[e] = tc[q];
+    for (int q = 0; q < kChunk / kThreads; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < len) {
+        sv[e] = tv[q];
+        sc[e] = row0 + (int)tr[q];
+      }
+    }
+  } else {
+    int tc[kChunk / kThreads];
+#pragma unroll
+    for (int q = 0; q < kChunk / kThreads; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < len) {
+        tv[q] = vals[cs + e];
+        tc[q] = colind[cs + e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kChunk / kThreads; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      if (e < len) {
+        sv[e] = tv[q];
+        sc[e] = tc[q];
+      }
     }
   }
   __syncthreads();
@@ -185,6 +209,7 @@ constexpr int spmv_min_waves() {
 template <typename T, int MODE, int ZMAX, bool GRP>
 __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
+                                                          const int16_t* __restrict__ colrel,
                                                           const T* __restrict__ vals,
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           int d, int zeta, T scale, uint32_t k0, uint32_t k1,
@@ -236,7 +261,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
       // waiting waves first and the ALU work of the sketch fills the gaps between (159 against
       // 153.5 solves/s on the 128^3 workload; the fused kernel 38.7 against 41.0 us)
       __builtin_amdgcn_s_setprio(2);
-      if (one_chunk) stage_chunk(vals, colind, p0, p1 - p0, sv, sc);
+      if (one_chunk) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc);
     }
     if (GRP && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
     int rows[ZMAX];
@@ -276,7 +301,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
         } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
           for (int cs = p0; cs < p1; cs += kChunk) {
             const int len = min(kChunk, p1 - cs);
-            stage_chunk(vals, colind, cs, len, sv, sc);
+            stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc);
             acc = row_dot(sv, sc, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
           }
         }
@@ -857,7 +882,7 @@ size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta) {
 
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
-                                       const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
+                                       const int16_t* cr, const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
                                        double* slots, const State* st, int nb, int G, size_t bs) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
@@ -865,10 +890,10 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
   const dim3 g2(grid, (nb + G - 1) / G);
 #define FAB_L(M, Z)                                                                                             \
   if (G > 1)                                                                                                    \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
                        scale, k0, k1, slots, st, nb, G, bs);                                                    \
   else                                                                                                          \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false>), g2, dim3(kThreads), lds, s, n, rp, ci, va, x, y, d, zeta, \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
                        scale, k0, k1, slots, st, nb, 1, bs)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
@@ -959,12 +984,12 @@ int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta) {
 }
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
-                              const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
+                              const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
                               double* slots, const State* st, int nb, int G, size_t bs) {
   if (dtype == 0)
-    return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, (const double*)va, (const double*)x,
+    return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, cr, (const double*)va, (const double*)x,
                                         (double*)y, d, zeta, seed, slots, st, nb, G, bs);
-  return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, (const float*)va, (const float*)x, (float*)y, d,
+  return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, cr, (const float*)va, (const float*)x, (float*)y, d,
                                      zeta, seed, slots, st, nb, G, bs);
 }
 

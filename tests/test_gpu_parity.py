@@ -74,6 +74,61 @@ def test_spmv(fab, ctx, build, dtype):
     assert _rel(y, ref) <= (1e-15 if dtype == torch.float64 else 1e-6)
 
 
+def _offset_limit_matrix(n, reach_hi, reach_lo):
+    """Banded test matrix for the 16-bit column offsets (relative to the first row of the row's
+    256-row tile; they hold -32768 .. 32767): every row has its diagonal, neighbours at +1 and
+    -300, and columns exactly reach_hi above and reach_lo below its tile's first row; row 40000
+    is long (3000 entries, more than one 2048-entry LDS chunk) within the same reach."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(21)
+    rows, cols = [], []
+    for i in range(n):
+        t0 = i - i % 256
+        for c in {i, i + 1, i - 300, t0 + reach_hi, t0 - reach_lo}:
+            if 0 <= c < n:
+                rows.append(i)
+                cols.append(c)
+    t0 = 40000 - 40000 % 256
+    lo, hi = max(t0 - reach_lo, 0), min(t0 + reach_hi, n - 1)
+    extra = rng.choice(np.arange(lo, hi + 1), size=3000, replace=False)
+    rows += [40000] * len(extra)
+    cols += list(extra)
+    vals = rng.standard_normal(len(rows))
+    M = sp.csr_matrix((vals, (np.array(rows), np.array(cols))), shape=(n, n))
+    M.sum_duplicates()
+    return M
+
+
+@pytest.mark.parametrize("reach_hi,reach_lo,ib", [(32767, 32768, 2), (32768, 0, 4), (0, 32769, 4)])
+def test_spmv_column_offsets_at_their_limits(fab, ctx, reach_hi, reach_lo, ib):
+    """Operators whose columns all fit the 16-bit tile offsets are read through them (offsets at
+    both limits decode to the right columns); one column past either limit keeps the int32
+    indices.  Products of A and of A^T (whose offsets are derived again) against scipy's; the bar
+    is the rounding order of FP64 row sums."""
+    M = _offset_limit_matrix(70000, reach_hi, reach_lo)
+    op = fab.CSROperator.from_arrays(ctx, M.indptr, M.indices, M.data)
+    assert op.index_bytes() == ib
+    x = wl.gaussian_vector(M.shape[0], 4)
+    xt = torch.as_tensor(x, device="cuda")
+    assert _rel(fab.spmv(op, xt).cpu().numpy(), M @ x) <= 1e-14
+    opt = op.transpose()
+    assert opt.index_bytes() in (2, 4)
+    assert _rel(fab.spmv(opt, xt).cpu().numpy(), M.T @ x) <= 1e-14
+
+
+def test_index_form_of_the_grid_operators(fab, ctx):
+    """The widest coupling of an N^3 grid operator in natural order is +-N^2: at N = 128 it fits
+    the 16-bit offsets, at N = 256 it does not (three N^2-row planes stand in for the grid)."""
+    for N, ib in [(128, 2), (256, 4)]:
+        n = 3 * N * N
+        i = np.arange(n, dtype=np.int64)
+        cols = np.stack([np.clip(i - N * N, 0, n - 1), i, np.clip(i + N * N, 0, n - 1)], axis=1).ravel()
+        rowptr = np.arange(0, 3 * n + 1, 3, dtype=np.int32)
+        op = fab.CSROperator.from_arrays(ctx, rowptr, cols.astype(np.int32), np.ones(3 * n))
+        assert op.index_bytes() == ib, N
+        op.close()
+
+
 # ------------------------------------------------------------------------ one cycle (twin)
 @pytest.mark.parametrize("N,m,k,d,zeta", [(64, 20, 2, 80, 8), (30, 12, 4, 50, 4), (17, 8, 8, 40, 1)])
 def test_cycle_matches_oracle_twin(fab, ctx, N, m, k, d, zeta):
