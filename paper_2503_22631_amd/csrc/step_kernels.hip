@@ -64,8 +64,9 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 // of a smooth w is ~lambda_min |w|, so FP32 sums would lose log10(kappa) digits on exactly the
 // slowly converging components; products of FP32 values are exact in FP64, and only the stored z
 // is rounded to FP32.
-// The product z is stored non-temporally: the next reader is the window update, and the 256 MB
-// memory-side cache is better spent on the CSR arrays, which every step reads again.
+// The product z is stored with the default cache policy: the window update reads it right after.
+// With 16-bit column offsets the CSR arrays of the 128^3 operator take 154 MB of the 256 MB
+// memory-side cache, which leaves room for z (non-temporal stores measured 2% slower per solve).
 // ---------------------------------------------------------------------------------------------
 constexpr int kChunk = 2048;
 constexpr int kGather = 8;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
         for (int u = 0; u < kMembersInFlight; ++u) {
           const int g = g0 + u;
           const T z = (T)acc[u];  // 0 for finished members and padding
-          if (xs[u] != nullptr && live) __builtin_nontemporal_store(z, bat(y, bs, r0 + g) + row);
+          if (xs[u] != nullptr && live) bat(y, bs, r0 + g)[row] = z;
           ztile[threadIdx.x * G + g] = z;
         }
       }
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
           }
         }
         z = (T)acc;
-        if (live) __builtin_nontemporal_store(z, bat(y, bs, r0 + g) + row);
+        if (live) bat(y, bs, r0 + g)[row] = z;
       } else if (live) {
         z = xg[row];
       }
@@ -561,25 +562,28 @@ constexpr int kOuBlocksPerCu = 2;
 // Raw buffer accesses (untyped, byte offsets): the hardware checks every lane's offset against the
 // resource's size, returns 0 for a load beyond it and drops a store beyond it, so a ragged batch
 // needs no branch.  Word 3 of the gfx9-family descriptor: 32-bit data format (a valid format is
-// required for untyped accesses), all other fields zero.  Cache policy 2 = non-temporal.
+// required for untyped accesses), all other fields zero.  Loads and stores use the default cache
+// policy: the new basis vector is gathered by the next step's product and read by the next
+// windows, and z and the window columns were written moments ago (non-temporal hints on these
+// accesses measured 0.5 us per step slower once the operator's CSR arrays left room in the
+// memory-side cache).
 constexpr int kBufWord3 = 0x00020000;
-constexpr int kBufNt = 2;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufWord3);
 }
-__device__ __forceinline__ double buf_load_nt(__amdgpu_buffer_rsrc_t r, int off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufNt));
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
-__device__ __forceinline__ float buf_load_nt(__amdgpu_buffer_rsrc_t r, int off, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kBufNt));
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
-__device__ __forceinline__ void buf_store_nt(double v, __amdgpu_buffer_rsrc_t r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kBufNt);
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
-__device__ __forceinline__ void buf_store_nt(float v, __amdgpu_buffer_rsrc_t r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kBufNt);
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
 // Elements of one batch: those of [b0, b0 + kOuBatch) below n (none when b0 >= n: a size-0
@@ -601,9 +605,9 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
 #pragma unroll
   for (int e = 0; e < kOuPer; ++e) {
     const int off = (e * kThreads + t) * (int)sizeof(T);
-    zv[e] = buf_load_nt(rz, off, T());
+    zv[e] = buf_load(rz, off, T());
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) wv[e][q] = buf_load_nt(rw[q], off, T());
+    for (int q = 0; q < KMAX; ++q) wv[e][q] = buf_load(rw[q], off, T());
   }
 }
 
@@ -619,7 +623,7 @@ __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0,
     double v = (double)zv[e];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
-    buf_store_nt((T)(v * inv), rz, (e * kThreads + t) * (int)sizeof(T));
+    buf_store((T)(v * inv), rz, (e * kThreads + t) * (int)sizeof(T));
   }
 }
 
@@ -727,7 +731,7 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
 
 // w_{j+1} = (z - sum_{i=lo..j} r_i w_i) / rho, in place on column j+1 of W (n x (m+1)).
 // KMAX bounds the window so the coefficients live in registers.  Streaming loads and stores are
-// non-temporal (see the SpMV note on cache residency).
+// non-temporal: a batch's basis columns exceed the memory-side cache many times over.
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict__ W,
                                                      const State* __restrict__ st, size_t bs) {
