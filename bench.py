@@ -182,7 +182,7 @@ def summarize_trace(trace_dir: str, out_md: str, command: str):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = list(csv.DictReader(open(f)))
-    lines = [f"# rocprofv3 kernel statistics: {WORKLOAD['workload']}", "", "Command (from the repository root on the GPU box):",
+    lines = [f"# rocprofv3 kernel statistics: {WORKLOAD['workload']}", "", "Command (from the repository root, on the MI355X machine):",
              "", "```", command, "```", "",
              "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in rows:
