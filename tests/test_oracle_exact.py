@@ -95,3 +95,27 @@ def test_exp_action_grads_against_finite_differences():
     assert abs(fdt - gt) <= 1e-7 * abs(gt)
     # the adjoint differs from the forward operator for this nonsymmetric A
     assert np.linalg.norm(gb - exact.kron_exp_fab(c, factors, t)) > 1e-3 * np.linalg.norm(gb)
+
+
+@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0)])
+def test_dense_fab_matches_sine_closed_form(fun, t):
+    """O1c (dense f of the assembled matrix, for tiny operators of any structure) against the sine
+    eigenbasis closed form on the 2-D Laplacian shifted by 1 (SPD, so z^(-1/2) is defined)."""
+    N = 9
+    factors, shift = [exact.laplace_factor(N)] * 2, 1.0
+    A = exact.assemble_dense(factors, shift)
+    b = wl.gaussian_vector(N * N, 3)
+    x1 = exact.dense_fab(fun, A, b, t)
+    x2 = exact.sine_fab(fun, b, N, [1, 1], shift, t)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+
+
+def test_dense_fab_matches_kronecker_exp_nonsymmetric():
+    """O1c against the Kronecker-exp identity (O1b) on a non-symmetric convection-diffusion operator."""
+    N = 5
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=30.0)
+    A = exact.assemble_dense(factors)
+    b = wl.gaussian_vector(N ** 3, 4)
+    x1 = exact.dense_fab("exp", A, b, 3e-3)
+    x2 = exact.kron_exp_fab(b, factors, 3e-3)
+    assert np.linalg.norm(x1 - x2) <= 1e-13 * np.linalg.norm(x2)

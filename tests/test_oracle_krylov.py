@@ -238,3 +238,67 @@ def test_kappa_T_is_a_lower_bound_on_the_basis_condition():
     assert info.kappa_T >= 1.0 and len(ratios) >= 2
     _, plain = krylov.restart_solve(A.to_scipy(), b, "exp", 2e-3, m=20, method="plain", tol=1e-12, max_cycles=3)
     assert plain.kappa_T == 1.0
+
+
+def test_full_space_window_with_k_at_least_m_is_classical_arnoldi():
+    """O2d (full-space inner products) with k >= m is modified Gram-Schmidt Arnoldi, which spans the
+    same Krylov basis as the CGS2 Arnoldi twin: W equals V and R equals H (Section 2.2)."""
+    A = _rand_nonsym(90, 12)
+    b = wl.gaussian_vector(90, 13)
+    S = sketch.sketch_matrix(90, 40, 8, seed=3)
+    W, U, R, alpha, m_eff, brk = krylov.randomized_arnoldi_window(A, S, b, 12, 12, orth="full")
+    c = krylov.arnoldi_cycle(A, b, m=12)
+    assert not brk and m_eff == 12
+    assert abs(alpha - np.linalg.norm(b)) <= 1e-14 * np.linalg.norm(b)
+    assert np.allclose(W, c.W, atol=1e-12)
+    assert np.allclose(R, c.R, atol=1e-11 * np.abs(c.R).max())
+    assert np.allclose(U, S @ W, atol=1e-13)
+
+
+def test_full_space_window_is_incomplete_orthogonalization():
+    """O2d with k < m: A W_m = W_{m+1} R with R upper Hessenberg and banded (entries i >= j - k + 1
+    only), every w_j of unit 2-norm and orthogonal to the k vectors before it (incomplete
+    orthogonalization, Section 3), while vectors further back are not orthogonal."""
+    A = wl.convdiff_3d(9, 40.0).to_scipy()
+    n = A.shape[0]
+    b = wl.gaussian_vector(n, 14)
+    S = sketch.sketch_matrix(n, 60, 8, seed=5)
+    m, k = 16, 3
+    W, U, R, alpha, m_eff, brk = krylov.randomized_arnoldi_window(A, S, b, m, k, orth="full")
+    assert not brk
+    assert np.linalg.norm(A @ W[:, :m] - W @ R) <= 1e-12 * np.linalg.norm(A @ W[:, :m])
+    i, j = np.indices(R.shape)
+    assert np.all(R[(i < j - k + 1) | (i > j + 1)] == 0.0)
+    assert np.allclose(np.linalg.norm(W, axis=0), 1.0, atol=1e-13)
+    G = W.T @ W
+    for jj in range(1, m + 1):
+        for ii in range(max(0, jj - k), jj):
+            assert abs(G[ii, jj]) <= 1e-12
+    assert np.max(np.abs(np.triu(G, k + 1))) > 1e-6
+    assert np.allclose(U, S @ W, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [2, 16])
+def test_identity_sketch_makes_both_inner_products_equal(k):
+    """With S = I_n the sketched and the full-space inner products coincide, so the two
+    orthogonalizations of O2 produce the same window-truncated basis for any k."""
+    A = _rand_nonsym(70, 15)
+    b = wl.gaussian_vector(70, 16)
+    S = sp.identity(70, format="csr")
+    r1 = krylov.randomized_arnoldi_window(A, S, b, 16, k, orth="sketch")
+    r2 = krylov.randomized_arnoldi_window(A, S, b, 16, k, orth="full")
+    assert np.allclose(r1[0], r2[0], atol=1e-12)
+    assert np.allclose(r1[2], r2[2], atol=1e-11 * np.abs(r2[2]).max())
+    assert r1[4:] == r2[4:]
+
+
+def test_full_space_window_solve_meets_the_closed_form():
+    """The O2d restarted solve (full-space truncated orthogonalization, whitened by the sketch)
+    converges to the same f(A) b as the sketched method on the 2-D Laplacian."""
+    A = wl.laplacian_2d(24)
+    b = wl.gaussian_vector(A.n, 17)
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    ref = exact.sine_fab("exp", b, 24, [1, 1], t=1e-3)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "exp", 1e-3, m=20, k=2, S=S, tol=1e-11, orth="full")
+    assert info.status == "ok"
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
