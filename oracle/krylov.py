@@ -33,8 +33,9 @@ Restart evaluations of block c of f(M_c) e_1:
   g_c = beta_c sum_l w_l psi_l Y_l,  psi_l <- psi_l beta_c h_c [Y_l]_m,
   Y_l = (zeta_l I - X^(c))^{-1} e_1, psi = 1 at the first cycle.
 
-Stopping (Alg. 2 and the error estimate after it): stop when
-||y_c|| <= tol ||x_c|| (relative reading), y_c = V^(c) g_c the increment.
+Stopping (Alg. 2 and the error estimate after it): the difference of two
+successive cycles, y_c = V^(c) g_c, continued by the geometric tail of the
+increments (``tail_estimate``); stop when that estimate is <= tol ||x_c||.
 Breakdown (rho <= 64 eps ||S z||) ends the cycle early with an exact
 invariant subspace: f is applied to the leading j x j block and the solve ends.
 
@@ -250,7 +251,47 @@ def make_rule(fun, t: float = 1.0, n_quad: int | None = None, spec=None):
         N = n_quad or 128
         z, w = quadrature.invsqrt_rule(N, spec[0], spec[1])
         return z, w, False
+    if fun == "phi1":
+        N, P, mu, L = quadrature.EXP_MAIN
+        z, w = quadrature.phi1_rule(t, n_quad or N, P, mu, L)
+        z, w = quadrature.conjugate_half(z, w)
+        return z, w, True
+    if fun == "cos_sqrt":
+        z, w = quadrature.cos_sqrt_rule(t, n_quad or quadrature.COS_SQRT_N, spec[0], spec[1])
+        z, w = quadrature.conjugate_half(z, w)
+        return z, w, True
     raise ValueError(fun)
+
+
+# ----------------------------------------------------------------------------- stopping test
+def tail_estimate(ynorm: float, xnorm: float, history: list) -> float:
+    """Estimated remaining relative error after a cycle (the stopping test of the restart).
+
+    Section 4 estimates the error of the restarted iterate by the difference of two successive
+    cycles, ||y_c|| = ||x_c - x_{c-1}||.  Read as the first term of the remaining increments, which
+    a converging restart shrinks by a roughly constant ratio q = ||y_c|| / ||y_{c-1}||, the error
+    left after cycle c is the geometric tail ||y_c|| q / (1 - q) (exact when every increment is
+    the previous one times q).  q is the largest of the last TAIL_RATIOS ratios (fewer in the first
+    cycles), so small ratios between growing increments (a dip in a transient) do not end the loop;
+    with q >= 1, or after the first cycle (no ratio yet), the estimate is unbounded.  ``history``
+    holds the increment norms of the earlier cycles and is extended with this one.  Relative to
+    ||x_c||.
+    """
+    norms = history + [ynorm]
+    history.append(ynorm)
+    rel = ynorm / xnorm if xnorm > 0 else 0.0
+    if rel == 0.0:
+        return 0.0
+    if len(norms) < 2:
+        return np.inf
+    q = 0.0
+    for i in range(max(1, len(norms) - TAIL_RATIOS), len(norms)):
+        prev, cur = norms[i - 1], norms[i]
+        q = max(q, cur / prev if prev > 0 else (np.inf if cur > 0 else 0.0))
+    return rel * q / (1.0 - q) if q < 1.0 else np.inf
+
+
+TAIL_RATIOS = 3  # contraction ratios the stopping estimate takes the largest of
 
 
 # ----------------------------------------------------------------------------- driver
@@ -260,6 +301,7 @@ class SolveInfo:
     cycles: int = 0
     matvecs: int = 0
     est_rel_update: float = np.inf
+    err_est: float = np.inf  # tail_estimate of the last cycle (the stopping test)
     quad_rule_error: float = 0.0
     kappa_T: float = 1.0     # max over cycles of max_i T_ii / min_i T_ii (a lower bound on cond_2(S W))
     history: list = field(default_factory=list)
@@ -286,6 +328,7 @@ def restart_solve(A, b, fun, t: float = 1.0, m: int = 20, k: int | None = None, 
         ev = QuadratureRestart(*rule)
         info.quad_rule_error = quadrature.rule_error(fun, *rule, t=t, spec=spec)
     v = b
+    ynorms = []
     for c in range(max_cycles):
         if method == "sketched":
             cyc = sketched_cycle(A, S, v, m, k if k is not None else m, orth)
@@ -300,17 +343,18 @@ def restart_solve(A, b, fun, t: float = 1.0, m: int = 20, k: int | None = None, 
         info.matvecs += cyc.m
         dT = np.diag(cyc.T)
         info.kappa_T = max(info.kappa_T, float(dT.max() / dT.min()))
-        nx = np.linalg.norm(x)
-        info.est_rel_update = np.linalg.norm(y) / nx if nx > 0 else 0.0
+        nx, ny = np.linalg.norm(x), np.linalg.norm(y)
+        info.est_rel_update = ny / nx if nx > 0 else 0.0
+        info.err_est = tail_estimate(ny, nx, ynorms)
         rec = {"X": cyc.X, "h": cyc.h, "beta": cyc.beta, "alpha": cyc.alpha, "T": cyc.T,
-               "g": g, "est": info.est_rel_update, "m": cyc.m}
+               "g": g, "est": info.est_rel_update, "err_est": info.err_est, "m": cyc.m}
         if keep_cycles:
             rec["cycle"] = cyc
         info.history.append(rec)
         if cyc.breakdown:
             info.status = "breakdown"
             break
-        if info.est_rel_update <= tol:
+        if info.err_est <= tol:
             info.status = "ok"
             break
         v = cyc.vhat

@@ -9,6 +9,16 @@
   (scipy.linalg.sqrtm) followed by a linear solve; used where the paper's
   restart needs f of a non-normal matrix (reading: Schur-based evaluation,
   because an eigendecomposition is unstable on the growing restart matrix).
+* ``phi1``: phi_1(M) = (e^M - I) M^{-1} (the phi function of eq. conv_diff_sol3)
+  without inverting M, through the augmented exponential
+  exp([[M, I], [0, 0]]) = [[e^M, phi_1(M)], [0, I]] (the block of the
+  exponential of a block upper-triangular matrix: the integral
+  int_0^1 e^{sM} ds = phi_1(M)); the same Pade-13 scaling and squaring.
+* ``cos_sqrt``: cos(t sqrt(A)) (the membrane solution of eq. drum_sol) without
+  a square root, through the first-order form of u'' = -A u:
+  exp(t [[0, I], [-A, 0]]) = [[cos(t sqrt A), .], [., cos(t sqrt A)]]; the
+  series of cos(t sqrt z) has only integer powers of z, so any square root of
+  A gives the same matrix (as the paper notes for eq. drum_sol).
 * ``apply``: dispatch by function name.
 
 Pinned in ``tests/test_oracle_matfun.py`` against closed forms (rotation
@@ -54,23 +64,57 @@ def invsqrt(A: np.ndarray) -> np.ndarray:
     return Y
 
 
+def phi1(M: np.ndarray) -> np.ndarray:
+    """phi_1(M) = sum_k M^k / (k+1)!, the top-right block of exp([[M, I], [0, 0]])."""
+    M = np.asarray(M)
+    n = M.shape[0]
+    B = np.zeros((2 * n, 2 * n), dtype=M.dtype)
+    B[:n, :n] = M
+    B[:n, n:] = np.eye(n)
+    return expm(B)[:n, n:]
+
+
+def cos_sqrt(A: np.ndarray, t: float = 1.0) -> np.ndarray:
+    """cos(t sqrt(A)) = sum_k (-t^2 A)^k / (2k)!, the top-left block of exp(t [[0, I], [-A, 0]])."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    B = np.zeros((2 * n, 2 * n), dtype=A.dtype)
+    B[:n, n:] = t * np.eye(n)
+    B[n:, :n] = -t * A
+    return expm(B)[:n, :n]
+
+
 def apply(fun: str, A: np.ndarray, t: float = 1.0) -> np.ndarray:
-    """f(A) for fun in {"exp" (exp(-t A)), "invsqrt" (A^(-1/2))}; callables are applied as f(A)."""
+    """f(A) for fun in {"exp" (exp(-t A)), "invsqrt" (A^(-1/2)), "phi1" (phi_1(-t A)),
+    "cos_sqrt" (cos(t sqrt(A)))}; callables are applied as f(A)."""
     if callable(fun):
         return fun(A)
     if fun == "exp":
         return expm(-t * np.asarray(A))
     if fun == "invsqrt":
         return invsqrt(A)
+    if fun == "phi1":
+        return phi1(-t * np.asarray(A))
+    if fun == "cos_sqrt":
+        return cos_sqrt(A, t)
     raise ValueError(fun)
 
 
 def scalar(fun, z, t: float = 1.0):
-    """The same function on scalars (used by closed-form oracles)."""
+    """The same function on scalars (used by closed-form oracles and the rule checks)."""
     if callable(fun):
         return fun(z)
     if fun == "exp":
         return np.exp(-t * z)
     if fun == "invsqrt":
         return 1.0 / np.sqrt(z)
+    if fun == "phi1":  # phi_1(-t z) = (1 - e^{-t z}) / (t z), 1 at z = 0
+        s = -t * np.asarray(z)
+        small = np.abs(s) < 1e-8
+        safe = np.where(small, 1.0, s)
+        return np.where(small, 1.0 + s / 2.0, np.expm1(safe) / safe)
+    if fun == "cos_sqrt":  # cos(t sqrt(z)); for z < 0 this is cosh(t sqrt(-z))
+        z = np.asarray(z)
+        v = np.cos(t * np.sqrt(z.astype(complex)))
+        return v.real if not np.iscomplexobj(z) else v
     raise ValueError(fun)

@@ -26,6 +26,24 @@ z^(-1/2)  -- Stieltjes form z^(-1/2) = (2/pi) int_0^inf (z + s^2)^{-1} ds with
     zeta_l = -c^2 tan^2(theta_l),  w_l = -(c/N) sec^2(theta_l),
     c = (lambda_lo lambda_hi)^(1/4) from a spectral interval.
 
+phi_1(-t z)  -- the same Hankel contour: with phi_1(s) = (e^s - 1)/s,
+    (1/2 pi i) int e^s / (s (s - s0)) ds = phi_1(s0) for a contour enclosing
+    0 and s0 (the residues at 0 and s0; the part -1/s of phi_1 integrates to
+    zero, and e^s/s decays on the contour's tails like e^s itself), so the
+    nodes are exp_rule's and each weight is divided by its node's s = -t zeta.
+    The contour passes s = 0 at distance P, as it passes the spectrum's end.
+
+cos(t sqrt(z))  -- Cauchy integral on an ellipse around the spectral interval:
+    z(theta) = c + h (rho e^{i theta} + e^{-i theta}/rho)/2, c = (lo+hi)/2,
+    h = (hi-lo)/2, trapezoidal rule in theta_k = 2 pi (k + 1/2)/N:
+    zeta_k = z(theta_k), w_k = f(zeta_k) z'(theta_k) / (i N).  cos(t sqrt z)
+    is entire (its series has integer powers of z only), so any ellipse
+    around the interval works; its truncation error falls like rho^-N while
+    the rounding of the sum grows with max |f| on the ellipse, which grows
+    with rho.  Reading: rho = exp(37/N), the smallest with rho^-N below FP64
+    rounding (measured: rule error <= 6e-12 on [lo, hi] for t sqrt(hi) <= 100
+    at N = 256, the default).
+
 Nodes of the exp rule come in complex-conjugate pairs (u, -u); for real
 matrices ``conjugate_half`` keeps the Im zeta > 0 half, and the caller doubles
 the real part.
@@ -34,7 +52,8 @@ Rule error (``rule_error``): the restarted iteration with a fixed rule r
 converges to r(A) b, so the rule adds at most |r - f| over the spectral region
 to the error.  It is sampled at 256 points: exp at t z = 0 and t z geometric in
 [1e-4, 1e4] (absolute error; f <= 1), z^(-1/2) at z geometric in [lo, hi]
-(relative error).
+(relative error), phi_1(-t z) as exp (absolute error; 0 < f <= 1), cos(t sqrt z)
+at sqrt(z) uniform in [sqrt(lo), sqrt(hi)] (absolute error; |f| <= 1).
 """
 import numpy as np
 
@@ -64,6 +83,27 @@ def invsqrt_rule(N: int, lam_lo: float, lam_hi: float):
     return zeta.astype(complex), w.astype(complex)
 
 
+def phi1_rule(t: float, N: int = EXP_MAIN[0], P: float = EXP_MAIN[1], mu: float = EXP_MAIN[2],
+              L: float = EXP_MAIN[3]):
+    """(zeta, w) with sum_l w_l/(zeta_l - z) ~ phi_1(-t z): exp_rule's nodes, weights over s = -t zeta."""
+    zeta, w = exp_rule(t, N, P, mu, L)
+    return zeta, w / (-t * zeta)
+
+
+COS_SQRT_N = 256
+
+
+def cos_sqrt_rule(t: float, N: int, lam_lo: float, lam_hi: float):
+    """(zeta, w) with sum_l w_l/(zeta_l - z) ~ cos(t sqrt(z)) for z near [lam_lo, lam_hi]."""
+    rho = np.exp(37.0 / N)
+    c, h = 0.5 * (lam_lo + lam_hi), 0.5 * (lam_hi - lam_lo)
+    e = np.exp(2j * np.pi * (np.arange(N) + 0.5) / N)
+    zeta = c + h * (rho * e + 1.0 / (rho * e)) / 2.0
+    dz = 1j * h * (rho * e - 1.0 / (rho * e)) / 2.0
+    w = np.cos(t * np.sqrt(zeta)) * dz / (1j * N)
+    return zeta, w
+
+
 def conjugate_half(zeta, w):
     """Keep the Im(zeta) > 0 member of every conjugate pair (the rule must be conjugate-symmetric)."""
     keep = zeta.imag > 0
@@ -79,13 +119,18 @@ def rational_scalar(zeta, w, z):
 def rule_error(fun: str, zeta, w, half: bool, t: float = 1.0, spec=None) -> float:
     """Largest error of r(z) = sum_l w_l/(zeta_l - z) against f on the sample set described above."""
     J = RULE_SAMPLES
-    if fun == "exp":
+    if fun in ("exp", "phi1"):
         tz = np.concatenate([[0.0], 1e-4 * 1e8 ** (np.arange(J - 1) / (J - 2))])
-        z, f = tz / t, np.exp(-tz)
+        z = tz / t
+        f = np.exp(-tz) if fun == "exp" else np.where(tz > 0, -np.expm1(-tz) / np.where(tz > 0, tz, 1.0), 1.0)
+    elif fun == "cos_sqrt":
+        lo, hi = spec
+        sq = np.sqrt(lo) + (np.sqrt(hi) - np.sqrt(lo)) * np.arange(J) / (J - 1)
+        z, f = sq ** 2, np.cos(t * sq)
     else:
         lo, hi = spec
         z = lo * (hi / lo) ** (np.arange(J) / (J - 1))
         f = 1.0 / np.sqrt(z)
     r = rational_scalar(zeta, w, z)
     r = 2.0 * r.real if half else r.real
-    return float(np.max(np.abs(r - f)) if fun == "exp" else np.max(np.abs(r / f - 1.0)))
+    return float(np.max(np.abs(r / f - 1.0)) if fun == "invsqrt" else np.max(np.abs(r - f)))

@@ -97,7 +97,7 @@ def test_exp_action_grads_against_finite_differences():
     assert np.linalg.norm(gb - exact.kron_exp_fab(c, factors, t)) > 1e-3 * np.linalg.norm(gb)
 
 
-@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0)])
+@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0), ("phi1", 2e-3), ("cos_sqrt", 0.05)])
 def test_dense_fab_matches_sine_closed_form(fun, t):
     """O1c (dense f of the assembled matrix, for tiny operators of any structure) against the sine
     eigenbasis closed form on the 2-D Laplacian shifted by 1 (SPD, so z^(-1/2) is defined)."""
@@ -119,3 +119,31 @@ def test_dense_fab_matches_kronecker_exp_nonsymmetric():
     x1 = exact.dense_fab("exp", A, b, 3e-3)
     x2 = exact.kron_exp_fab(b, factors, 3e-3)
     assert np.linalg.norm(x1 - x2) <= 1e-13 * np.linalg.norm(x2)
+
+
+@pytest.mark.parametrize("N,t", [(7, 1e-3), (9, 3e-2)])
+def test_phi1_and_cos_sqrt_closed_forms_vs_scipy(N, t):
+    """The sine closed forms of phi_1(-t A) b and cos(t sqrt A) b against scipy's dense routes on the
+    assembled 2-D Laplacian (SPD): (t A)^(-1) (I - e^(-t A)) b and cosm(t sqrtm(A)) b."""
+    factors, shift = exact.problem_factors("laplacian_2d", N)
+    A = exact.assemble_dense(factors, shift)
+    b = wl.gaussian_vector(N * N, 11)
+    x1 = exact.sine_fab("phi1", b, N, [1, 1], 0.0, t)
+    x2 = np.linalg.solve(t * A, b - sla.expm(-t * A) @ b)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+    tc = 3.0 / np.sqrt(8 * (N + 1) ** 2)
+    y1 = exact.sine_fab("cos_sqrt", b, N, [1, 1], 0.0, tc)
+    y2 = sla.cosm(tc * sla.sqrtm(A).real) @ b
+    assert np.linalg.norm(y1 - y2) <= 1e-11 * np.linalg.norm(y2)
+
+
+def test_phi1_dense_nonsymmetric_vs_scipy():
+    """O1c's phi_1 (augmented exponential) on a non-symmetric convection-diffusion operator against
+    (t A)^(-1) (I - e^(-t A)) b with scipy's expm."""
+    N, t = 5, 4e-3
+    factors, _ = exact.problem_factors("convdiff_3d", N, peclet=30.0)
+    A = exact.assemble_dense(factors)
+    b = wl.gaussian_vector(N ** 3, 12)
+    x1 = exact.dense_fab("phi1", A, b, t)
+    x2 = np.linalg.solve(t * A, b - sla.expm(-t * A) @ b)
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)

@@ -89,10 +89,10 @@ def test_whitened_arnoldi_relation():
     assert np.linalg.norm(b - c.beta * V[:, 0]) < 1e-12 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0)])
+@pytest.mark.parametrize("fun,t", [("exp", 2e-3), ("invsqrt", 1.0), ("phi1", 2e-3), ("cos_sqrt", 0.1)])
 def test_quadrature_restart_equals_growing_matrix(fun, t):
     """The quadrature recursion reproduces block c of f(M_c) e_1 over many cycles."""
-    if fun == "exp":
+    if fun in ("exp", "phi1"):
         A = wl.convdiff_3d(12, 20.0).to_scipy()
         spec = None
     else:
@@ -302,3 +302,84 @@ def test_full_space_window_solve_meets_the_closed_form():
     x, info = krylov.restart_solve(A.to_scipy(), b, "exp", 1e-3, m=20, k=2, S=S, tol=1e-11, orth="full")
     assert info.status == "ok"
     assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------- stopping test (tail estimate)
+def test_tail_estimate_is_exact_for_geometric_increments():
+    """Increments y_c = q^(c-1) v add up to x* = v / (1 - q); after cycle c the remaining error is
+    q^c ||v|| / (1 - q), which the tail estimate returns exactly (relative to ||x_c||) from the
+    second cycle on; after the first cycle there is no ratio and the estimate is unbounded."""
+    v = np.random.default_rng(3).standard_normal(40)
+    for q in (0.05, 0.5, 0.93):
+        hist, x = [], np.zeros_like(v)
+        xstar = v / (1.0 - q)
+        for c in range(1, 14):
+            y = q ** (c - 1) * v
+            x = x + y
+            est = krylov.tail_estimate(np.linalg.norm(y), np.linalg.norm(x), hist)
+            true = np.linalg.norm(xstar - x) / np.linalg.norm(x)
+            if c == 1:
+                assert est == np.inf
+            else:
+                assert est == pytest.approx(true, rel=1e-10), (q, c)
+
+
+def test_tail_estimate_uses_the_largest_of_three_ratios():
+    """A small ratio right after growth (a dip inside a transient) gives no bound: the estimate takes
+    the largest of the last three ratios.  Hand-computed values; a zero increment gives 0."""
+    hist = []
+    ests = [krylov.tail_estimate(y, 1.0, hist) for y in (1.0, 0.1, 0.5, 1e-3, 5e-4, 4e-4, 2e-4)]
+    assert ests[0] == np.inf                                  # no ratio yet
+    assert ests[1] == pytest.approx(0.1 * 0.1 / 0.9)          # one ratio, 0.1
+    assert ests[2] == np.inf                                  # ratio 5
+    assert ests[3] == np.inf                                  # ratios 2e-3, 5, 0.1
+    assert ests[4] == np.inf                                  # ratios 0.5, 2e-3, 5
+    assert ests[5] == pytest.approx(4e-4 * 0.8 / 0.2)         # ratios 0.8, 0.5, 2e-3
+    assert ests[6] == pytest.approx(2e-4 * 0.8 / 0.2)         # ratios 0.5, 0.8, 0.5
+    assert krylov.tail_estimate(0.0, 1.0, [1.0, 0.5]) == 0.0
+
+
+def test_tail_estimate_stops_within_tol_where_the_raw_difference_does_not():
+    """z^(-1/2) of the 3-D Laplacian shifted to condition number 2.6e4, d = 4m: the increments of
+    the restart swing by two orders of magnitude from cycle to cycle.  Stopping at the first cycle
+    whose raw difference ||y_c|| / ||x_c|| is below tol leaves an error above tol (the sine closed
+    form decides); the tail estimate stops later with the error within tol."""
+    N, tol = 16, 1e-4
+    lmin0 = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2
+    lmax = 12 * (N + 1) ** 2
+    shift = lmax / 2.6e4 - lmin0
+    A = wl.shifted_laplacian_3d(N, shift)
+    b = wl.gaussian_vector(A.n, 0)
+    spec = (lmin0 + shift, lmax + shift)
+    S = sketch.sketch_matrix(A.n, 120, 8, seed=1)
+    ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], shift)
+    x, info = krylov.restart_solve(A.to_scipy(), b, "invsqrt", m=30, k=2, S=S, tol=tol, max_cycles=300,
+                                   spec=spec, keep_cycles=True)
+    assert info.status == "ok"
+    assert np.linalg.norm(x - ref) <= tol * np.linalg.norm(ref)
+    xs = np.zeros_like(b)
+    for c, h in enumerate(info.history):
+        xs = xs + h["cycle"].basis_apply(h["g"])
+        if h["est"] <= tol:  # where the raw successive difference would have stopped
+            assert c + 1 < info.cycles
+            assert np.linalg.norm(xs - ref) > tol * np.linalg.norm(ref)
+            break
+    else:
+        raise AssertionError("the raw difference never fell below tol")
+
+
+@pytest.mark.parametrize("fun,t", [("phi1", 1e-3), ("phi1", 2e-2), ("cos_sqrt", 0.02), ("cos_sqrt", 0.2)])
+def test_phi1_and_cos_sqrt_restarts_meet_the_closed_form(fun, t):
+    """phi_1(-t A) b (eq. conv_diff_sol3) and cos(t sqrt A) b (eq. drum_sol) by the sketched restart on
+    the 2-D Laplacian, N = 32, against the sine closed form."""
+    N = 32
+    A = wl.laplacian_2d(N)
+    b = wl.gaussian_vector(A.n, 13)
+    spec = (8 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2, 8 * (N + 1) ** 2)
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    x, info = krylov.restart_solve(A.to_scipy(), b, fun, t, m=20, k=2, S=S, tol=1e-11, max_cycles=200,
+                                   spec=spec if fun == "cos_sqrt" else None)
+    ref = exact.sine_fab(fun, b, N, [1, 1], 0.0, t)
+    assert info.status == "ok", info.cycles
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert info.quad_rule_error <= 1e-11

@@ -106,3 +106,75 @@ def test_rule_error_tracks_node_count(fun, N, lo):
         assert e < 1e-12
     else:
         assert e > 1e-6
+
+
+# --------------------------------------------------------- phi_1 (eq. conv_diff_sol3), cos(t sqrt)
+def test_phi1_closed_forms():
+    """phi_1 through the augmented exponential against its definition: (e^d - 1)/d on a diagonal,
+    the series I + N/2 + N^2/6 on a nilpotent N (N^3 = 0), and M phi_1(M) = e^M - I on a
+    non-normal M (scipy's expm on the right-hand side)."""
+    d = np.array([-40.0, -1.0, -1e-9, 0.0, 0.7, 3.0])
+    ph = np.diag(matfun.phi1(np.diag(d)))
+    ref = np.array([np.expm1(x) / x if x != 0 else 1.0 for x in d])
+    assert np.allclose(ph, ref, rtol=1e-14, atol=0)
+    N = np.triu(np.random.default_rng(5).standard_normal((3, 3)), 1)
+    assert np.allclose(matfun.phi1(N), np.eye(3) + N / 2 + N @ N / 6, atol=1e-14, rtol=0)
+    rng = np.random.default_rng(6)
+    M = rng.standard_normal((10, 10)) + np.triu(rng.standard_normal((10, 10)), 1) * 3 - 4 * np.eye(10)
+    assert np.linalg.norm(M @ matfun.phi1(M) - (sla.expm(M) - np.eye(10))) <= 1e-12 * np.linalg.norm(sla.expm(M))
+
+
+def test_cos_sqrt_closed_forms():
+    """cos(t sqrt A) through the first-order form: cos(t sqrt d) on a diagonal (cosh for d < 0), the
+    series I - t^2 A/2 + t^4 A^2/24 on a nilpotent A (A^3 = 0), the double-angle identity
+    C(2t) = 2 C(t)^2 - I on a non-normal A, and V cos(t sqrt L) V^T for a symmetric one."""
+    t = 0.7
+    d = np.array([-4.0, 0.0, 0.5, 9.0, 400.0])
+    c = np.diag(matfun.cos_sqrt(np.diag(d), t))
+    ref = np.array([np.cosh(t * np.sqrt(-x)) if x < 0 else np.cos(t * np.sqrt(x)) for x in d])
+    assert np.allclose(c, ref, rtol=0, atol=1e-13)
+    A = np.triu(np.random.default_rng(7).standard_normal((3, 3)), 1)
+    assert np.allclose(matfun.cos_sqrt(A, t), np.eye(3) - t ** 2 * A / 2 + t ** 4 * A @ A / 24, atol=1e-14, rtol=0)
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((8, 8)) + 5 * np.eye(8)
+    C1, C2 = matfun.cos_sqrt(B, t), matfun.cos_sqrt(B, 2 * t)
+    assert np.linalg.norm(C2 - (2 * C1 @ C1 - np.eye(8))) <= 1e-12 * max(1.0, np.linalg.norm(C2))
+    S = rng.standard_normal((8, 8))
+    S = S @ S.T + np.eye(8)
+    lam, V = np.linalg.eigh(S)
+    assert np.linalg.norm(matfun.cos_sqrt(S, t) - (V * np.cos(t * np.sqrt(lam))) @ V.T) <= 1e-12 * np.sqrt(8)
+
+
+@pytest.mark.parametrize("t", [1e-3, 1.0])
+def test_phi1_rule_scalar_accuracy(t):
+    """The Hankel contour with weights over s reproduces phi_1(-t z) on the region the exp rule
+    covers (sketched Ritz values included), and its conjugate half doubles to the full rule."""
+    s = _sector_points()
+    z = -s / t
+    zeta, w = quadrature.phi1_rule(t)
+    r = quadrature.rational_scalar(zeta, w, z)
+    ref = np.expm1(s) / s
+    assert np.max(np.abs(r - ref)) < 1e-12
+    zh, wh = quadrature.conjugate_half(zeta, w)
+    x = np.array([0.0, 30.0 / t, 3e3 / t])
+    assert np.allclose(2 * quadrature.rational_scalar(zh, wh, x).real, quadrature.rational_scalar(zeta, w, x).real,
+                       rtol=1e-13, atol=1e-16)
+    assert quadrature.rule_error("phi1", zh, wh, True, t=t) < 1e-12
+
+
+@pytest.mark.parametrize("kappa", [1.0, 20.0, 60.0])
+def test_cos_sqrt_rule_accuracy(kappa):
+    """The ellipse rule reproduces cos(t sqrt z) on [lo, hi] (t sqrt(hi) = kappa oscillations), on a
+    neighbourhood of the interval inside the ellipse, and a coarse rule is flagged by rule_error."""
+    lo, hi = 20.0, 3.4e4
+    t = kappa / np.sqrt(hi)
+    zeta, w = quadrature.cos_sqrt_rule(t, quadrature.COS_SQRT_N, lo, hi)
+    x = np.linspace(lo, hi, 500)
+    for zz in (x, x + 1j * 0.01 * (hi - lo) * np.sin(np.linspace(0, np.pi, 500))):
+        r = quadrature.rational_scalar(zeta, w, zz)
+        assert np.max(np.abs(r - np.cos(t * np.sqrt(zz)))) < 1e-11
+    zh, wh = quadrature.conjugate_half(zeta, w)
+    assert len(zh) == len(zeta) // 2
+    assert quadrature.rule_error("cos_sqrt", zh, wh, True, t=t, spec=(lo, hi)) < 1e-11
+    zc, wc = quadrature.conjugate_half(*quadrature.cos_sqrt_rule(max(t, 60 / np.sqrt(hi)), 24, lo, hi))
+    assert quadrature.rule_error("cos_sqrt", zc, wc, True, t=max(t, 60 / np.sqrt(hi)), spec=(lo, hi)) > 1e-6
