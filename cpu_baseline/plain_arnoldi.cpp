@@ -10,7 +10,9 @@
 // with the next cycle starting from v_{m+1}.  The rule is the parabolic Hankel contour
 // s(u) = P - mu u^2 + 2 i mu u in s = -t z, midpoint rule with N nodes, of which the N/2 with
 // Im s < 0 are solved and the result doubled in its real part (conjugate symmetry).  The stopping
-// test is the same relative one: ||V_m c|| <= tol ||x||.
+// test is the library's: the successive difference ||V_m c|| / ||x|| continued by the geometric
+// tail q / (1 - q) of the increments' contraction ratio q (the largest of the last three),
+// stopping when that is <= tol.
 //
 // It is neither the oracle nor the product: it shares no code with either and exists to time the
 // plain method on the host cores of the GPU machine.
@@ -20,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <limits>
 #include <vector>
 
 namespace {
@@ -131,6 +134,7 @@ int cpu_plain_expv(int64_t n, const int32_t* rowptr, const int32_t* colind, cons
     V[i] = b[i];
   }
   int status = 2, cyc = 0, mv = 0;
+  double yprev = 0.0, qprev = 0.0, qprev2 = 0.0;  // the stopping test's last increment norm and ratios
   for (cyc = 1; cyc <= max_cycles; ++cyc) {
     double a2 = 0.0;
 #pragma omp parallel for schedule(static) reduction(+ : a2)
@@ -188,9 +192,21 @@ int cpu_plain_expv(int64_t n, const int32_t* rowptr, const int32_t* colind, cons
       status = 1;
       break;
     }
-    if (std::sqrt(y2) <= tol * std::sqrt(x2)) {
-      status = 0;
-      break;
+    {  // remaining-error estimate: the geometric tail of the increments (the library's stopping test)
+      const double yn = std::sqrt(y2), rel = x2 > 0.0 ? std::sqrt(y2 / x2) : 0.0;
+      const double inf = std::numeric_limits<double>::infinity();
+      const double q = (cyc == 1) ? inf : (yprev > 0.0 ? yn / yprev : (yn > 0.0 ? inf : 0.0));
+      double qb = q;  // the largest of the last three ratios
+      if (cyc >= 3) qb = std::max(qb, qprev);
+      if (cyc >= 4) qb = std::max(qb, qprev2);
+      const double est = (rel == 0.0) ? 0.0 : (qb < 1.0 ? rel * qb / (1.0 - qb) : inf);
+      yprev = yn;
+      qprev2 = qprev;
+      qprev = q;
+      if (est <= tol) {
+        status = 0;
+        break;
+      }
     }
     if (cyc == max_cycles) break;
 #pragma omp parallel for schedule(static)

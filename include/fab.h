@@ -16,8 +16,13 @@
  *     the growing block matrix is evaluated through a fixed quadrature rule
  *     (the quadrature-based restart Section 4 names), so the per-cycle small
  *     work stays m x m;
- *   - the loop stops when ||y_c|| <= tol ||x|| for every time point (the
- *     successive-difference error estimate after Algorithm 2, relative form).
+ *   - the loop stops when the estimated remaining error is at most tol ||x||
+ *     for every time point: the successive-difference estimate after
+ *     Algorithm 2, ||y_c|| = ||x_c - x_{c-1}||, continued by the geometric tail
+ *     of the increments, ||y_c|| q / (1 - q) with q their contraction ratio
+ *     (see fab_info.err_est);
+ *   - every sum over blocks is formed in a fixed order (per-block partials,
+ *     then one reduction), so a solve gives the same bits on every run.
  *
  * Conventions
  *   - Every pointer is DEVICE memory unless its name starts with h_.
@@ -57,7 +62,14 @@ typedef enum {
 } fab_status;
 
 typedef enum { FAB_F64 = 0, FAB_F32 = 1 } fab_dtype;        /* A values and basis; x is FP64 */
-typedef enum { FAB_EXP_NEG = 0, FAB_INVSQRT = 1 } fab_fun;  /* exp(-t z) ; z^(-1/2)          */
+/* The function f of f(A) b.  t is a per-call parameter (h_t) of the timed functions.
+ *   FAB_EXP_NEG  exp(-t z)          the heat equation's solution operator (Section 5.1, 5.3)
+ *   FAB_INVSQRT  z^(-1/2)           a Stieltjes function (Section 4); needs spec_lo > 0
+ *   FAB_PHI1_NEG phi_1(-t z) = (1 - e^{-t z}) / (t z), the phi function of eq. conv_diff_sol3
+ *   FAB_COS_SQRT cos(t sqrt z)      the membrane solution of eq. drum_sol (t absorbs the wave speed);
+ *                needs the spectral interval 0 <= spec_lo < spec_hi (the rule is an ellipse
+ *                around it, accurate for t sqrt(spec_hi) up to ~100 with the default 256 nodes) */
+typedef enum { FAB_EXP_NEG = 0, FAB_INVSQRT = 1, FAB_PHI1_NEG = 2, FAB_COS_SQRT = 3 } fab_fun;
 /* FAB_SKETCHED: the sketched cycles with the quadrature restart (fixed m x m work per cycle).
  * FAB_PLAIN_RESTART: classical restarted Arnoldi (CGS2) with the same restart, as a comparator.
  * FAB_SKETCHED_GROWING: the sketched cycles with the restart as Algorithm 2 states it, f applied
@@ -76,8 +88,8 @@ typedef struct {
   double tol;         /* relative update tolerance, >= 0                              */
   int32_t max_cycles; /* >= 1                                                          */
   int32_t method;     /* fab_method; FAB_PLAIN_RESTART ignores k, d, zeta, seed        */
-  int32_t n_quad;     /* 0 = default rule size (128)                                  */
-  double spec_lo;     /* spectral interval for FAB_INVSQRT (required there, > 0)      */
+  int32_t n_quad;     /* 0 = default rule size (128; 256 for FAB_COS_SQRT), else 8..512, a multiple of 8 */
+  double spec_lo;     /* spectral interval for FAB_INVSQRT and FAB_COS_SQRT (required there) */
   double spec_hi;
 } fab_params;
 
@@ -86,29 +98,41 @@ typedef struct {
   int32_t cycles;          /* restart cycles run                                    */
   int32_t matvecs;         /* products with A                                       */
   int32_t group;           /* members per block of the fused product + sketch kernel */
-  double est_rel_update;   /* max_t ||y_t|| / ||x_t|| of the last cycle             */
+  double est_rel_update;   /* max_t ||y_t|| / ||x_t|| of the last cycle (the relative *
+                            * difference of two successive cycles, Alg. 2)          */
   double quad_rule_error;  /* error of the partial-fraction rule r against f over   *
-                            * the spectral region, max over 256 samples and t: exp: *
-                            * |r - f| at t z = 0 and t z geometric in [1e-4, 1e4];  *
-                            * z^(-1/2): |r/f - 1| at z geometric in [lo, hi].  The   *
+                            * the spectral region, max over 256 samples and t: exp  *
+                            * and phi_1: |r - f| at t z = 0 and t z geometric in    *
+                            * [1e-4, 1e4]; cos(t sqrt z): |r - f| at sqrt z uniform *
+                            * in [sqrt lo, sqrt hi]; z^(-1/2): |r/f - 1| at z       *
+                            * geometric in [lo, hi].  The                           *
                             * restarted iteration with a fixed rule converges to     *
                             * r(A) b, so this bounds what the rule adds to the error */
   double kappa_T;          /* conditioning of the sketched basis: max over cycles of *
                             * max_i T_ii / min_i T_ii for the whitening factor T of  *
                             * S W = Q T (appendix eq. A.1), a lower bound on         *
                             * cond_2(S W); 1 for the plain method (T = I)            */
+  double err_est;          /* the stopping test's estimate of the remaining relative *
+                            * error after the last cycle (infinite when the          *
+                            * increments did not contract): max_t of                 *
+                            * (||y_t|| / ||x_t||) q / (1 - q), q the largest of the  *
+                            * last three ratios ||y_t|| / ||y_t||_prev (fewer in     *
+                            * cycles 2 and 3); the solve stops when err_est <= tol   */
 } fab_info;
 
 typedef struct fab_ctx fab_ctx;
 typedef struct fab_op fab_op;
 
 /* Create a context bound to the current HIP device and to hip_stream (a
- * hipStream_t; NULL = the null stream).  Errors: FAB_E_INVALID (ctx NULL),
- * FAB_E_HIP. */
+ * hipStream_t; NULL = the null stream).  No passage of the paper: the device,
+ * stream and cached launch graphs that every call below runs on.
+ * Errors: FAB_E_INVALID (ctx NULL), FAB_E_HIP. */
 fab_status fab_create(fab_ctx** ctx, void* hip_stream);
 fab_status fab_destroy(fab_ctx* ctx);
 
-/* Wrap a CSR matrix (n x n) without copying.  rowptr[n+1], colind[nnz] are
+/* The operator A of the problem statement (Algorithm 2's first argument; the
+ * sparse matrices of Section 5).
+ * Wrap a CSR matrix (n x n) without copying.  rowptr[n+1], colind[nnz] are
  * int32 (ascending columns per row are not required); vals[nnz] are FP64 or FP32
  * (dtype).  BORROWS the three arrays: they must outlive the operator, and their
  * structure must not change while it exists.  Creation checks the structure on
@@ -127,7 +151,8 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
 fab_status fab_op_destroy(fab_op* op);
 
 /* A^T as a new CSR operator whose arrays the library allocates and owns (freed
- * by fab_op_destroy).  Rows of A^T are sorted by column index, so the result
+ * by fab_op_destroy).  Not in the paper: the adjoint of the method for the
+ * differentiation extension (gradients of <c, f(A) b>).  Rows of A^T are sorted by column index, so the result
  * is canonical.  The adjoint of the method needs it: <c, f(A) b> = <f(A^T) c,
  * b>, so d<c, f(tA) b>/db = f(tA^T) c, computed by fab_solve on A^T.  A's
  * structure is checked on the device first (row pointers non-decreasing from 0
@@ -145,23 +170,38 @@ fab_status fab_op_index_bytes(const fab_op* A, int32_t* h_bytes);
  * into caller-provided device buffers (test hook for fab_op_transpose). */
 fab_status fab_op_copy_arrays(fab_ctx* ctx, const fab_op* A, int32_t* rowptr, int32_t* colind, void* vals);
 
-/* Bytes of device workspace fab_solve needs for nt time points. */
+/* Bytes of device workspace fab_solve needs for nt time points: the basis W
+ * (n x (m+1), A's dtype) and its sketch S W (d x (m+1)) of Algorithm 1, R,
+ * the whitening factor T of appendix eq. A.1, the quadrature restart's weights
+ * (Section 4), per-block partial sums and the solver state.
+ * Errors: FAB_E_INVALID (null arguments, nt or m out of range). */
 fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, size_t* h_bytes);
 
-/* x[:, i] = f_i(A) b for the nt values h_t[i] (exp(-t_i z)), or nt = 1 for
- * z^(-1/2).  b[n] has A's dtype; x is n x nt FP64, column-major (ldx = n),
+/* The restarted randomized Krylov method: Algorithm 2 (RandomizedRestartedKrylov
+ * with A, S given by p->d, p->zeta, p->seed, b, m, tol, k_max = max_cycles),
+ * each cycle Algorithm 1 truncated to a window of k, whitened by appendix
+ * eq. A.1 and restarted through a quadrature rule (Section 4).
+ * x[:, i] = f_i(A) b for the nt values h_t[i] (exp(-t_i z), phi_1(-t_i z),
+ * cos(t_i sqrt z)), or nt = 1 for z^(-1/2).  b[n] has A's dtype; x is n x nt FP64, column-major (ldx = n),
  * overwritten.  work is device memory of at least fab_workspace_size bytes,
- * 256-byte aligned.  h_info is filled on every return >= FAB_E_HIP. */
+ * 256-byte aligned.  h_info is filled on every return >= FAB_E_HIP.
+ * One right-hand side per call: the boundary's nrhs/ldb/ldx form is the
+ * separate fab_solve_batched.  Errors: FAB_E_INVALID (null pointers, sizes,
+ * parameter ranges, t <= 0 or non-finite, work not 256-byte aligned),
+ * FAB_E_WORKSPACE, FAB_E_UNSUPPORTED, FAB_E_HIP; FAB_E_NONFINITE and
+ * FAB_E_DIVERGED come from the iteration. */
 fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h_t, int32_t nt,
                      const void* b, double* x, const fab_params* p, void* work, size_t work_bytes,
                      fab_info* h_info);
 
-/* Batched solves: nb right-hand sides sharing A (columns of b, b[r * ldb + i], A's dtype).
+/* Batched solves (Algorithm 2 for each right-hand side; the batching extension).
+ * nb right-hand sides sharing A (columns of b, b[r * ldb + i], A's dtype).
  * x[(r * nt + i) * ldx + row] = f_i(A) b_r (FP64, overwritten).  Every member runs the
  * method of fab_solve with the same parameters and its own basis, sketch (the same S), restart
  * weights and stopping test; members that have finished are skipped by every kernel while the
  * others continue.  The fused product + sketch kernel reads each CSR chunk once for a group of
- * G members (G chosen once per operator and batch shape by timing 1, 2, 4, 8, 16 on the device).
+ * G members (G chosen once per operator and batch shape by timing G = 1 and G = 16, the grouped
+ * kernel with the tile sketch on the matrix cores, on the device).
  * The whole cycle of all members is one captured graph.  h_info has nb entries; the return value
  * is the most severe member status (errors before warnings before FAB_OK_BREAKDOWN before FAB_OK).
  * 1 <= nb <= 1024; ldb, ldx >= n; FAB_PLAIN_RESTART is not batched (FAB_E_UNSUPPORTED).
@@ -172,7 +212,8 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
                              int32_t nb, const void* b, int64_t ldb, double* x, int64_t ldx,
                              const fab_params* p, void* work, size_t work_bytes, fab_info* h_info);
 
-/* Ragged batches: nops operators of uneven size (any mix of n, nnz and dtype), one right-hand
+/* Ragged batches (Algorithm 2 for each operator; the batching extension).
+ * nops operators of uneven size (any mix of n, nnz and dtype), one right-hand
  * side each: x[i] (n_i x nt FP64) = f(A_i) b[i].  b and x are host arrays of nops device
  * pointers.  Every operator runs the method of fab_solve in its own part of work
  * (fab_workspace_size_ragged bytes); the cycles of all operators are captured into one graph
@@ -187,20 +228,27 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
 
 /* ---- test hooks: the same kernels as fab_solve, exposed for parity tests ---- */
 
-/* y = A x (A's dtype for x and y). */
+/* y = A x (A's dtype for x and y): the product z = A w_j of Algorithm 1, by the
+ * kernel the solve uses.  work, work_bytes: unused (may be NULL, 0).
+ * Errors: FAB_E_INVALID (null arguments), FAB_E_HIP. */
 fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void* work, size_t work_bytes);
 
-/* Sx[d] (FP64) = S x for the sparse sign matrix defined by (n, d, zeta, seed);
- * x has dtype.  work: at least 128 d bytes (the slot copies of the accumulators). */
+/* The sketch of eq. (sparse_sign_sketch) applied to a vector, by the kernel the
+ * solve uses: Sx[d] (FP64) = S x for the sparse sign matrix defined by (n, d, zeta, seed);
+ * x has dtype.  work: at least 16384 d bytes (one partial sketch per block of the
+ * product kernel's grid, at most 2048 blocks; summed in a fixed order). */
 fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed,
                             int32_t dtype, const void* x, double* Sx, void* work, size_t work_bytes);
 
-/* The sketch specification itself: for columns col0 .. col0+count-1, the rows
- * (int32, count x zeta, row-major) and signs (int8, +1/-1) of S. */
+/* The sketch specification itself (eq. sparse_sign_sketch: zeta distinct rows
+ * per column, signs +-1, scale 1/sqrt(zeta) not included): for columns
+ * col0 .. col0+count-1, the rows (int32, count x zeta, row-major) and signs
+ * (int8, +1/-1) of S.  Errors: FAB_E_INVALID (ranges), FAB_E_HIP. */
 fab_status fab_sketch_table(fab_ctx* ctx, int64_t col0, int64_t count, int32_t d, int32_t zeta,
                             uint64_t seed, int32_t* rows, int8_t* signs);
 
-/* One cycle from start vector v (A's dtype), exposing its intermediates:
+/* One cycle of Algorithm 1 (window-truncated) with the whitening of appendix
+ * eq. A.1, from start vector v (A's dtype), exposing its intermediates:
  * W n x (m+1) (A's dtype, column-major), U = S W d x (m+1), R (m+1) x m, T (m+1) x (m+1)
  * (all FP64 column-major), Rt m x m = R_m + r_{m+1,m} (T_m^{-1} t) e_m^T, the projected matrix
  * in the basis W (the whitened X of the appendix's eq. A.1 is T_m Rt T_m^{-1}), and
@@ -226,7 +274,8 @@ fab_status fab_timing_enable(fab_ctx* ctx, int32_t on);
 fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
                            int64_t* h_loop_steps);
 
-/* out[0] = <x, y> for FP64 device vectors of length n, summed in a fixed order
+/* Not in the paper (the differentiation extension):
+ * out[0] = <x, y> for FP64 device vectors of length n, summed in a fixed order
  * (reproducible bits).  Used for the time derivative of <c, exp(-tA) b>, which
  * is -<c, A x> with x = exp(-tA) b.  out is device memory. */
 fab_status fab_dot(fab_ctx* ctx, int64_t n, const double* x, const double* y, double* out);

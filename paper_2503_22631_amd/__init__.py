@@ -18,8 +18,8 @@ import torch
 from . import _lib
 from ._lib import FabError, fab_info, fab_params
 
-FUN = {"exp": 0, "invsqrt": 1}
-SKETCH_APPLY_WORK_PER_ROW = 128   # fab_sketch_apply's workspace: 128 bytes per sketch row
+FUN = {"exp": 0, "invsqrt": 1, "phi1": 2, "cos_sqrt": 3}
+SKETCH_APPLY_WORK_PER_ROW = 16384  # fab_sketch_apply's workspace: 2048 block partials per sketch row
 METHOD = {"sketched": 0, "plain": 1, "growing": 2}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
@@ -159,7 +159,7 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
     """
     ctx = op.ctx
     p = kw.pop("params", None) or Params(**kw)
-    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if fun != "invsqrt" else np.ones(1)
     nt = len(ts)
     assert b.is_cuda and b.dtype == op.dtype and b.numel() == op.n
     b = b.contiguous()
@@ -177,14 +177,14 @@ def solve(op: CSROperator, b: torch.Tensor, fun: str = "exp", t=1e-3, x: torch.T
         _lib.check(st, "fab_solve")
     out = {"status": _lib.STATUS.get(info.status, info.status), "code": int(st), "cycles": info.cycles,
            "matvecs": info.matvecs, "est_rel_update": info.est_rel_update,
-           "quad_rule_error": info.quad_rule_error, "kappa_T": info.kappa_T}
+           "quad_rule_error": info.quad_rule_error, "kappa_T": info.kappa_T, "err_est": info.err_est}
     return x.view(nt, op.n).t(), out
 
 
 def _info_dict(info, code):
     return {"status": _lib.STATUS.get(info.status, info.status), "code": int(code), "cycles": info.cycles,
             "matvecs": info.matvecs, "est_rel_update": info.est_rel_update, "quad_rule_error": info.quad_rule_error,
-            "kappa_T": info.kappa_T, "group": info.group}
+            "kappa_T": info.kappa_T, "group": info.group, "err_est": info.err_est}
 
 
 def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None,
@@ -196,7 +196,7 @@ def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, wo
     """
     ctx = op.ctx
     p = kw.pop("params", None) or Params(**kw)
-    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if fun != "invsqrt" else np.ones(1)
     nt = len(ts)
     assert B.is_cuda and B.dtype == op.dtype and B.dim() == 2 and B.shape[0] == op.n
     nb = B.shape[1]
@@ -226,7 +226,7 @@ def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = 
     nops = len(ops)
     assert len(bs) == nops and all(op.ctx is ctx for op in ops)
     p = kw.pop("params", None) or Params(**kw)
-    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if FUN[fun] == 0 else np.ones(1)
+    ts = np.atleast_1d(np.asarray(t, dtype=np.float64)) if fun != "invsqrt" else np.ones(1)
     nt = len(ts)
     bs = [b.contiguous() for b in bs]
     for op, b in zip(ops, bs):

@@ -30,7 +30,7 @@ class fab_params(ctypes.Structure):
 class fab_info(ctypes.Structure):
     _fields_ = [("status", c_int32), ("cycles", c_int32), ("matvecs", c_int32), ("group", c_int32),
                 ("est_rel_update", c_double), ("quad_rule_error", c_double),
-                ("kappa_T", c_double)]
+                ("kappa_T", c_double), ("err_est", c_double)]
 
 
 class FabError(RuntimeError):

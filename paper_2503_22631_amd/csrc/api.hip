@@ -20,19 +20,20 @@
 namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* slots, const State* st, int nb, int G, size_t bs);
-size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta);
-int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta);
+                              double* parts, const State* st, int nb, int G, size_t bs);
+hipError_t launch_reduce_parts(hipStream_t, int e0, int len, int nparts, const double* parts, double* out,
+                               const State* st, int skip, int nb, size_t bs);
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16);
+int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta, bool c16);
 hipError_t configure_cycle_kernels();
 hipError_t configure_step_kernels();
 size_t group_lds_max();
-hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* cur, double* next, double* U,
-                       double* R, State* st, int nb, size_t bs);
+hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* uraw, double* U, double* R,
+                       State* st, int nb, size_t bs);
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
                          size_t bs);
 hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* cur, double* next, double* U, double* R, double* G, State* st, int nb,
-                              size_t bs);
+                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -47,15 +48,14 @@ hipError_t launch_rule(hipStream_t, int fun, int nt, const double* tvals, int n_
 hipError_t launch_copy_in(hipStream_t, int dtype, int grid, int n, const void* b, int64_t ldb, void* w0, int nb,
                           size_t bs);
 hipError_t launch_sqnorm(hipStream_t, int dtype, int grid, int n, const void* v, double* slots);
-hipError_t launch_start(hipStream_t, int d, int m, int plain, double* slots_start, double* slots_step,
-                        size_t step_len, double* U, double* R, State* st, int nb, size_t bs);
+hipError_t launch_start(hipStream_t, int d, int m, int plain, const double* sv, double* slots_start,
+                        double* slots_step, size_t step_len, double* U, double* R, State* st, int nb, size_t bs);
 
 hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb, const GrowBuffers* grow);
-hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, const double* C, void* W, double* x,
-                       int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs, const PassSketch& ps);
-hipError_t launch_final(hipStream_t, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
+hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, int dn, const double* C, void* W,
+                       double* x, int64_t ldx, double* parts, const State* st, int nb, size_t bs, const PassSketch& ps);
+hipError_t launch_final(hipStream_t, int nt, int dn, double tol, const double* red, State* st, Report* rep, int nb,
                         size_t bs);
-hipError_t launch_reduce_slots(hipStream_t, int len, const double* slots, double* out);
 hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
                                int8_t* signs);
 hipError_t launch_dot(hipStream_t, int64_t n, const double* x, const double* y, double* part, int max_blocks,
@@ -104,7 +104,7 @@ struct fab_ctx {
     hipGraphExec_t exec;
   };
   struct Tuned {  // autotuned members per block of the fused kernel, per operator and batch shape
-    const void* op;
+    uint64_t op;  // fab_op::serial (a destroyed operator's address can be reused by a new one)
     int64_t n;
     int nb, d, zeta, dtype, G;
   };
@@ -139,7 +139,12 @@ static uint64_t next_op_serial() {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static int rule_nodes(int fun, const fab_params* p) { return (p->n_quad > 0) ? p->n_quad : kRuleMain; }
+static int rule_nodes(int fun, const fab_params* p) {
+  return (p->n_quad > 0) ? p->n_quad : (fun == FAB_COS_SQRT ? kRuleCosSqrt : kRuleMain);
+}
+
+// Functions of a time parameter t (h_t): exp(-t z), phi_1(-t z), cos(t sqrt z); z^(-1/2) has none.
+static bool timed_fun(int fun) { return fun == FAB_EXP_NEG || fun == FAB_PHI1_NEG || fun == FAB_COS_SQRT; }
 
 static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, int nt) {
   Layout L{};
@@ -147,8 +152,9 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   const int m = p->m;
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   const int N = rule_nodes(fun, p);
-  L.nq = (fun == FAB_EXP_NEG) ? N / 2 : N;
+  L.nq = rule_is_half(fun) ? N / 2 : N;
   L.nsys = nt * L.nq;
+  const bool plain = p->method == FAB_PLAIN_RESTART;
   const size_t step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -159,9 +165,12 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.W = take(wcol(n, (int)es) * (m + 1) * es);
   L.U = take((size_t)d * (m + 1) * 8);
   L.R = take((size_t)(m + 1) * m * 8);
-  L.slots_step = take(2 * step_len * 8);
-  L.slots_start = take((size_t)kSlots * std::max(d, kSlots) * 8);
-  L.slots_norm = take((size_t)kSlots * 2 * kMaxNt * 8);
+  // zeroed at set-up from slots_step up to T: the plain comparator's atomic accumulators, the
+  // reduced sketches and norms, the state
+  L.slots_step = take(plain ? 2 * step_len * 8 : 0);
+  L.slots_start = take(plain ? (size_t)kSlots * 8 : 0);
+  L.uraw = take((size_t)d * 8);
+  L.red = take((size_t)(d + 2 * kMaxNt) * 8);
   L.state = take(sizeof(State));
   L.T = take((size_t)(m + 1) * (m + 1) * 8);
   L.Ut = take((size_t)d * (m + 1) * 8);
@@ -170,11 +179,12 @@ static Layout make_layout(int64_t n, int dtype, const fab_params* p, int fun, in
   L.rule_z = take((size_t)L.nsys * sizeof(cplx));
   L.rule_w = take((size_t)L.nsys * sizeof(cplx));
   L.psi = take((size_t)L.nsys * sizeof(cplx));
-  L.gbuf = take((size_t)nt * m * 8 + (size_t)nt * 8 /* t values */);
+  L.gbuf = take((size_t)L.nsys * m * 8 + (size_t)nt * 8 /* t values */);
   // growing restart: blocks (kGrowRows x m), couplings and sizes per cycle
   L.grow = take(p->method == FAB_SKETCHED_GROWING ? (size_t)kGrowRows * m * 8 + (size_t)kGrowRows * 12 : 0);
   L.G = take((size_t)(m + 1) * (m + 1) * 8);
-  L.report = 0;
+  // per-block partials (k_reduce_parts): the sketch entries [0, d), then the pass's norms
+  L.parts = take((size_t)kMaxParts * (d + 2 * kMaxNt) * 8);
   L.total = off;
   return L;
 }
@@ -191,8 +201,11 @@ static fab_status check_params(const fab_op* A, const fab_params* p, int fun, in
   }
   if (!(p->tol >= 0.0) || p->max_cycles < 1) return FAB_E_INVALID;
   if (p->n_quad != 0 && (p->n_quad < 8 || p->n_quad > 512 || (p->n_quad % 8) != 0)) return FAB_E_INVALID;
-  if (fun == FAB_EXP_NEG) {
+  if (fun == FAB_EXP_NEG || fun == FAB_PHI1_NEG) {
     if (nt < 1 || nt > kMaxNt) return FAB_E_INVALID;
+  } else if (fun == FAB_COS_SQRT) {  // the ellipse rule needs the spectral interval
+    if (nt < 1 || nt > kMaxNt) return FAB_E_INVALID;
+    if (!(p->spec_lo >= 0.0) || !(p->spec_hi > p->spec_lo) || !std::isfinite(p->spec_hi)) return FAB_E_INVALID;
   } else if (fun == FAB_INVSQRT) {
     if (nt != 1) return FAB_E_INVALID;
     if (!(p->spec_lo > 0.0) || !(p->spec_hi >= p->spec_lo) || !std::isfinite(p->spec_hi)) return FAB_E_INVALID;
@@ -216,7 +229,7 @@ static int stream_grid(int64_t n, int cap) {
 struct Ptrs {
   char* base;
   void* W;
-  double *U, *R, *slots_step, *slots_start, *slots_norm, *T, *Ut, *X, *C, *gbuf, *tvals, *G;
+  double *U, *R, *slots_step, *slots_start, *uraw, *red, *parts, *T, *Ut, *X, *C, *gbuf, *tvals, *G;
   State* st;
   cplx *rz, *rw, *psi;
   size_t step_len;
@@ -230,7 +243,9 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   q.R = (double*)(q.base + L.R);
   q.slots_step = (double*)(q.base + L.slots_step);
   q.slots_start = (double*)(q.base + L.slots_start);
-  q.slots_norm = (double*)(q.base + L.slots_norm);
+  q.uraw = (double*)(q.base + L.uraw);
+  q.red = (double*)(q.base + L.red);
+  q.parts = (double*)(q.base + L.parts);
   q.st = (State*)(q.base + L.state);
   q.T = (double*)(q.base + L.T);
   q.Ut = (double*)(q.base + L.Ut);
@@ -240,7 +255,7 @@ static Ptrs carve(void* work, const Layout& L, const fab_params* p, int nt) {
   q.rw = (cplx*)(q.base + L.rule_w);
   q.psi = (cplx*)(q.base + L.psi);
   q.gbuf = (double*)(q.base + L.gbuf);
-  q.tvals = q.gbuf + (size_t)nt * p->m;
+  q.tvals = q.gbuf + (size_t)L.nsys * p->m;
   q.G = (double*)(q.base + L.G);
   const int d = (p->method == FAB_PLAIN_RESTART) ? 1 : p->d;
   q.step_len = (size_t)kSlots * std::max(d, kMaxM + 2);
@@ -270,9 +285,10 @@ static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipE
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
 // Blocks of the fused SpMV + sketch kernel: as many as are resident on the device at once (the
 // occupancy calculator's count per CU, at most 8).
-static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1, int zeta = 1) {
-  const int per_cu = std::max(1, std::min(8, spmv_blocks_per_cu(dtype, mode, d, G, zeta)));
-  return stream_grid(n, per_cu * ctx->num_cu);
+static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1, int zeta = 1,
+                     bool c16 = false) {
+  const int per_cu = std::max(1, std::min(8, spmv_blocks_per_cu(dtype, mode, d, G, zeta, c16)));
+  return stream_grid(n, std::min(per_cu * ctx->num_cu, kMaxParts));  // one partial per block
 }
 
 // Batch geometry: nb members, each with a single-solve workspace bs bytes apart; the fused kernel
@@ -288,9 +304,9 @@ struct Batch {
 // sketches b for the first cycle (enqueue_first_sketch).
 static bool pass_sketches(const fab_params* p) { return p->method != FAB_PLAIN_RESTART && p->zeta <= 8; }
 
-static PassSketch pass_sketch(const fab_params* p, int dtype, const Ptrs& q) {
+static PassSketch pass_sketch(const fab_params* p, int dtype) {
   PassSketch ps{};
-  ps.slots = q.slots_start;
+  ps.on = 1;
   ps.d = p->d;
   ps.zeta = p->zeta;
   ps.k0 = (uint32_t)p->seed;
@@ -306,7 +322,8 @@ static fab_status enqueue_first_sketch(const fab_ctx* ctx, hipStream_t s, const 
   const int n = (int)A->n;
   const int g_sk = spmv_grid(ctx, n, A->dtype, 1, p->d, B.G, p->zeta);
   FAB_TRY(launch_spmv_sketch(s, A->dtype, 1, g_sk, n, A->rowptr, A->colind, A->colrel, A->vals, q.W, nullptr, p->d,
-                             p->zeta, p->seed, q.slots_start, q.st, B.nb, B.G, B.bs));
+                             p->zeta, p->seed, q.parts, q.st, B.nb, B.G, B.bs));
+  FAB_TRY(launch_reduce_parts(s, 0, p->d, g_sk, q.parts, q.red, q.st, 0, B.nb, B.bs));
   return FAB_OK;
 }
 
@@ -319,35 +336,36 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const int d = plain ? 1 : p->d;
   const int nb = B.nb;
   const size_t bs = B.bs;
-  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta);
+  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta, A->colrel != nullptr);
   const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * wcol(n, (int)es) * es; };
   const bool pass_sk = with_pass && pass_sketches(p);
   if (!plain) {
-    if (!pass_sk)  // otherwise the set-up or the previous cycle's pass accumulated S w_1 already
+    if (!pass_sk) {  // otherwise the set-up or the previous cycle's pass formed S w_1 already
       FAB_TRY(launch_spmv_sketch(s, dt, 1, g_sk, n, A->rowptr, A->colind, A->colrel, A->vals, col(0), nullptr, d,
-                                 p->zeta, p->seed, q.slots_start, q.st, nb, B.G, bs));
+                                 p->zeta, p->seed, q.parts, q.st, nb, B.G, bs));
+      FAB_TRY(launch_reduce_parts(s, 0, d, g_sk, q.parts, q.red, q.st, 0, nb, bs));
+    }
   } else {
     FAB_TRY(launch_sqnorm(s, dt, g_vec, n, col(0), q.slots_start));
   }
-  FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st, nb, bs));
+  FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.red, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st, nb,
+                       bs));
   FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st, nb, bs));
   for (int j = 0; j < m; ++j) {
-    double* set_cur = q.slots_step + (size_t)(j & 1) * q.step_len;
-    double* set_nxt = q.slots_step + (size_t)((j + 1) & 1) * q.step_len;
     if (!plain) {
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
-                                 d, p->zeta, p->seed, set_cur, q.st, nb, B.G, bs));
+                                 d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs));
       if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
+      FAB_TRY(launch_reduce_parts(s, 0, d, g_spmv, q.parts, q.uraw, q.st, 0, nb, bs));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
       if (nb == 1 && d <= 256 && p->k <= 8) {
-        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, set_cur, set_nxt, q.U, q.R, q.G, q.st,
-                                   nb, bs));
+        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs));
       } else {
-        FAB_TRY(launch_orth(s, j, p->k, m, d, set_cur, set_nxt, q.U, q.R, q.st, nb, bs));
+        FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
         FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
       }
     } else {
@@ -396,9 +414,14 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   }
   FAB_TRY(launch_small(s, a, nb, p->method == FAB_SKETCHED_GROWING ? &gb : nullptr));
   if (with_pass) {
-    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, q.C, q.W, x, B.ldx, q.slots_norm, q.st, nb, bs,
-                        pass_sk ? pass_sketch(p, dt, q) : PassSketch{}));
-    FAB_TRY(launch_final(s, nt, p->tol, q.slots_norm, q.st, rep, nb, bs));
+    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, d, q.C, q.W, x, B.ldx, q.parts, q.st, nb, bs,
+                        pass_sk ? pass_sketch(p, dt) : PassSketch{}));
+    // the next start's sketch (entries [0, d)) when the pass formed it, and the norms after it
+    if (pass_sk)
+      FAB_TRY(launch_reduce_parts(s, 0, d + 2 * nt, g_vec, q.parts, q.red, q.st, 1, nb, bs));
+    else
+      FAB_TRY(launch_reduce_parts(s, d, 2 * nt, g_vec, q.parts, q.red + d, q.st, 1, nb, bs));
+    FAB_TRY(launch_final(s, nt, d, p->tol, q.red, q.st, rep, nb, bs));
   }
   return FAB_OK;
 }
@@ -648,10 +671,10 @@ fab_status fab_dot(fab_ctx* ctx, int64_t n, const double* x, const double* y, do
 fab_status fab_workspace_size(const fab_op* A, const fab_params* p, int32_t nt, size_t* h_bytes) {
   if (!A || !p || !h_bytes || nt < 1 || nt > kMaxNt || p->m < 1 || p->m > kMaxM) return FAB_E_INVALID;
   if (p->method == FAB_SKETCHED && (p->d < 1 || p->d > kMaxD)) return FAB_E_INVALID;
-  const int fun = FAB_EXP_NEG;  // the exp layout is the larger of the two
-  Layout L = make_layout(A->n, A->dtype, p, fun, nt);
-  Layout L2 = make_layout(A->n, A->dtype, p, FAB_INVSQRT, nt);
-  *h_bytes = std::max(L.total, L2.total);
+  size_t most = 0;  // the largest layout over the functions (they differ in rule nodes)
+  for (int fun : {FAB_EXP_NEG, FAB_INVSQRT, FAB_PHI1_NEG, FAB_COS_SQRT})
+    most = std::max(most, make_layout(A->n, A->dtype, p, fun, nt).total);
+  *h_bytes = most;
   return FAB_OK;
 }
 
@@ -668,16 +691,23 @@ fab_status fab_workspace_size_batched(const fab_op* A, const fab_params* p, int3
 // batch's own operator and workspace (HIP events, 3 launches after 1 warm-up) and the fastest is
 // kept for this operator and batch shape.  Runs before the solve's set-up, which clears what the
 // timing launches wrote.
+// Whether the grouped kernel (kGroup members per block) can serve this sketch: d <= 256 and its
+// dynamic LDS within what configure_step_kernels allows.
+static bool group_fits(int dtype, const fab_params* p) {
+  return p->d <= 256 && spmv_sketch_lds(dtype, 0, p->d, 16, p->zeta, false) <= group_lds_max() &&
+         spmv_sketch_lds(dtype, 1, p->d, 16, p->zeta, false) <= group_lds_max();
+}
+
 static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p, int nb, const Ptrs& q, size_t bs,
                              int* G_out) {
   *G_out = 1;
   if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
-  if (ctx->force_group > 0) {
-    *G_out = (p->d <= 256) ? ctx->force_group : 1;  // the grouped kernel serves d <= 256
+  if (ctx->force_group > 0) {  // a forced group the grouped kernel cannot serve falls back to 1
+    *G_out = (ctx->force_group > 1 && !group_fits(A->dtype, p)) ? 1 : ctx->force_group;
     return FAB_OK;
   }
   for (const auto& t : ctx->tuned)
-    if (t.op == A && t.n == A->n && t.nb == nb && t.d == p->d && t.zeta == p->zeta && t.dtype == A->dtype) {
+    if (t.op == A->serial && t.n == A->n && t.nb == nb && t.d == p->d && t.zeta == p->zeta && t.dtype == A->dtype) {
       *G_out = t.G;
       return FAB_OK;
     }
@@ -693,15 +723,15 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   // candidates: one member per block, or a group of 16 (the MFMA sketch's N-tile; finished members
   // and padding cost gathers of nothing)
   for (int G = 1; G <= 16 && err == hipSuccess; G += 15) {
-    if (G > 1 && (d > 256 || spmv_sketch_lds(dt, 0, d, G, p->zeta) > group_lds_max())) break;
-    const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta);
+    if (G > 1 && !group_fits(dt, p)) break;
+    const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta, A->colrel != nullptr);
     void* x0 = q.W;
     void* y0 = (char*)q.W + wcol(n, (int)es) * es;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
       if (rep == 1) err = hipEventRecord(e0, s);
       if (err == hipSuccess)
         err = launch_spmv_sketch(s, dt, 0, grid, n, A->rowptr, A->colind, A->colrel, A->vals, x0, y0, d, p->zeta,
-                                 p->seed, q.slots_step, nullptr, nb, G, bs);
+                                 p->seed, q.parts, nullptr, nb, G, bs);
     }
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -715,7 +745,8 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail(err, "tune_group", __LINE__);
-  ctx->tuned.push_back({A, A->n, nb, d, p->zeta, A->dtype, best});
+  if (ctx->tuned.size() >= 64) ctx->tuned.erase(ctx->tuned.begin());  // oldest first
+  ctx->tuned.push_back({A->serial, A->n, nb, d, p->zeta, A->dtype, best});
   *G_out = best;
   return FAB_OK;
 }
@@ -727,14 +758,15 @@ struct Track {
   fab_status status = FAB_W_NOT_CONVERGED;
   int cycles = 0, matvecs = 0;
   bool finished = false;
-  double est = 0.0, rule_err = 0.0, kappa_T = 1.0;
+  double est = 0.0, err_est = 0.0, rule_err = 0.0, kappa_T = 1.0;
 };
 
 // Returns true when this report finishes the member.
 static bool track_report(Track& t, const Report& rr, int c) {
   t.cycles = c + 1;
   t.matvecs += rr.meff;
-  t.est = rr.est;
+  t.est = rr.relupd;
+  t.err_est = rr.est;
   t.rule_err = std::max(t.rule_err, rr.rule_err);
   if (rr.meff > 0 && std::isfinite(rr.kappa_T)) t.kappa_T = std::max(t.kappa_T, rr.kappa_T);
   if (rr.nonfinite) {
@@ -745,7 +777,7 @@ static bool track_report(Track& t, const Report& rr, int c) {
     t.status = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
   } else if (rr.converged) {
     t.status = FAB_OK;
-  } else if (!(rr.est <= kDivergedEst)) {
+  } else if (!(rr.relupd <= kDivergedEst)) {
     // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
     // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
     t.status = FAB_E_DIVERGED;
@@ -772,6 +804,7 @@ static fab_status finish_tracks(std::vector<Track>& tr, const fab_params* p, fab
       h_info[r].cycles = t.cycles;
       h_info[r].matvecs = t.matvecs;
       h_info[r].est_rel_update = t.est;
+      h_info[r].err_est = t.err_est;
       h_info[r].quad_rule_error = t.rule_err;
       h_info[r].kappa_T = t.kappa_T;
       h_info[r].group = group;
@@ -792,13 +825,13 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
     for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, FAB_E_UNSUPPORTED);
     return FAB_E_UNSUPPORTED;
   }
-  if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
+  if (timed_fun(fun) && !h_t) return FAB_E_INVALID;
   fab_status ps = check_params(A, p, fun, nt);
   if (ps != FAB_OK) {
     for (int r = 0; r < nb; ++r) info_init(h_info ? h_info + r : nullptr, ps);
     return ps;
   }
-  if (fun == FAB_EXP_NEG)
+  if (timed_fun(fun))
     for (int i = 0; i < nt; ++i)
       if (!std::isfinite(h_t[i]) || !(h_t[i] > 0.0)) return FAB_E_INVALID;
   if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
@@ -826,7 +859,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
   FAB_TRY(launch_zero_strided(s, (double*)((char*)work + L.slots_step), (L.T - L.slots_step) / 8, nb, bs));
   FAB_TRY(launch_zero_strided(s, x, (size_t)n, nb * nt, (size_t)ldx * 8));
   FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
-  for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
+  for (int i = 0; i < nt; ++i) ctx->h_t[i] = timed_fun(fun) ? h_t[i] : 1.0;
   FAB_TRY(hipMemcpyAsync(q.tvals, ctx->h_t, sizeof(double) * nt, hipMemcpyHostToDevice, s));
   FAB_TRY(launch_rule(s, fun, nt, q.tvals, rule_nodes(fun, p), p->spec_lo, p->spec_hi, q.rz, q.rw, q.psi, q.st, nb,
                       bs));
@@ -938,14 +971,14 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   for (int i = 0; i < nops && h_info; ++i) info_init(h_info + i, FAB_E_INVALID);
   if (!ctx || !ops || !b || !x || !p || !work || nops < 1 || nops > kMaxBatch) return FAB_E_INVALID;
   if (p->method != FAB_SKETCHED) return FAB_E_UNSUPPORTED;
-  if (fun == FAB_EXP_NEG && !h_t) return FAB_E_INVALID;
+  if (timed_fun(fun) && !h_t) return FAB_E_INVALID;
   if (((uintptr_t)work & 255) != 0) return FAB_E_INVALID;
   for (int i = 0; i < nops; ++i) {
     if (!ops[i] || !b[i] || !x[i]) return FAB_E_INVALID;
     const fab_status ps = check_params(ops[i], p, fun, nt);
     if (ps != FAB_OK) return ps;
   }
-  if (fun == FAB_EXP_NEG)
+  if (timed_fun(fun))
     for (int i = 0; i < nt; ++i)
       if (!std::isfinite(h_t[i]) || !(h_t[i] > 0.0)) return FAB_E_INVALID;
   size_t need = 0;
@@ -969,7 +1002,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
   FAB_TRY(hipStreamSynchronize(s));  // the pinned staging buffer may still feed a previous call
-  for (int i = 0; i < nt; ++i) ctx->h_t[i] = (fun == FAB_EXP_NEG) ? h_t[i] : 1.0;
+  for (int i = 0; i < nt; ++i) ctx->h_t[i] = timed_fun(fun) ? h_t[i] : 1.0;
   for (int i = 0; i < nops; ++i) {  // per-operator set-up, as in a single solve
     const int n = (int)ops[i]->n;
     FAB_TRY(launch_zero(s, (double*)((char*)q[i].base + L[i].slots_step), (L[i].T - L[i].slots_step) / 8));
@@ -1110,7 +1143,7 @@ fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void*
   hipStream_t s = ctx->work;
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
-  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1, 1), (int)A->n, A->rowptr, A->colind,
+  FAB_TRY(launch_spmv_sketch(s, A->dtype, 2, spmv_grid(ctx, A->n, A->dtype, 2, 1, 1, 1, A->colrel != nullptr), (int)A->n, A->rowptr, A->colind,
                              A->colrel, A->vals, x, y, 1, 1, 0, nullptr, nullptr, 1, 1, 0));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
@@ -1121,15 +1154,15 @@ fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, ui
   if (!ctx || !x || !Sx || !work || n <= 0 || n >= ((int64_t)1 << 31) || d < 1 || d > kMaxD || zeta < 1 ||
       zeta > 32 || zeta > d || (dtype != FAB_F64 && dtype != FAB_F32))
     return FAB_E_INVALID;
-  if (work_bytes < (size_t)kSlots * d * 8) return FAB_E_WORKSPACE;
+  if (work_bytes < (size_t)kMaxParts * d * 8) return FAB_E_WORKSPACE;
   hipStream_t s = ctx->work;
   FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
   FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
-  double* slots = (double*)work;
-  FAB_TRY(launch_zero(s, slots, (size_t)kSlots * d));
-  FAB_TRY(launch_spmv_sketch(s, dtype, 1, spmv_grid(ctx, n, dtype, 1, d), (int)n, nullptr, nullptr, nullptr, nullptr, x,
-                             nullptr, d, zeta, seed, slots, nullptr, 1, 1, 0));
-  FAB_TRY(launch_reduce_slots(s, d, slots, Sx));
+  double* parts = (double*)work;
+  const int grid = spmv_grid(ctx, n, dtype, 1, d, 1, zeta);
+  FAB_TRY(launch_spmv_sketch(s, dtype, 1, grid, (int)n, nullptr, nullptr, nullptr, nullptr, x, nullptr, d, zeta, seed,
+                             parts, nullptr, 1, 1, 0));
+  FAB_TRY(launch_reduce_parts(s, 0, d, grid, parts, Sx, nullptr, -1, 1, 0));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }

@@ -57,19 +57,28 @@ __global__ void k_zero_strided(double* p, size_t count, size_t step_bytes) {
 //   U = sqrt((P+L)/mu), N midpoint nodes; zeta = -s/t, w = -h s'(u) e^s / (2 pi i t).  Only the
 //   nodes with u < 0 (Im zeta > 0) are kept: for real X the other half are conjugates, and the
 //   accumulation takes twice the real part.  (N, P, mu, L) = (N, 3, 6, 45).
+// fun 2, phi_1(-t z) (eq. conv_diff_sol3): the same contour and nodes, each weight divided by its
+//   s = -t zeta.  The integral of e^s / (s (s - s0)) over a contour around 0 and s0 is phi_1(s0)
+//   (residues at 0 and s0), and e^s / s decays on the contour's tails like e^s.
 // fun 1, z^(-1/2) = (2/pi) int_0^inf (z + s^2)^{-1} ds with s = c tan(theta), N midpoint nodes on
 //   (0, pi/2): zeta = -c^2 tan^2(theta), w = -(c/N) sec^2(theta), c = (lo hi)^(1/4).
-// Layout: nq nodes per time point (nq = N/2 for exp, N for z^(-1/2)).
+// fun 3, cos(t sqrt z) (eq. drum_sol): Cauchy integral on the ellipse zeta(theta) = c + h (rho e^{i
+//   theta} + e^{-i theta} / rho) / 2 around [lo, hi] (c, h its centre and half-width), trapezoidal
+//   nodes theta = 2 pi (k + 1/2) / N, w = f(zeta) zeta'(theta) / (i N), rho = exp(37 / N) (the
+//   smallest ellipse whose truncation term rho^-N is below FP64 rounding: max |f| on the ellipse,
+//   which sets the rounding of the sum, grows with rho).  cos(t sqrt z) is entire, so no branch of
+//   the square root matters.  The Im zeta > 0 half (theta < pi) is kept, as for exp.
+// Layout: nq nodes per time point (nq = N/2 for the conjugate-half rules, N for z^(-1/2)).
 __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_main, double lo, double hi,
                        cplx* __restrict__ rz, cplx* __restrict__ rw, cplx* __restrict__ psi, size_t bs) {
   rz = bat(rz, bs);  // every batch member holds its own copy (psi is per member)
   rw = bat(rw, bs);
   psi = bat(psi, bs);
-  const int nq = (fun == 0) ? n_main / 2 : n_main;
+  const int nq = rule_is_half(fun) ? n_main / 2 : n_main;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nt * nq; s += gridDim.x * blockDim.x) {
     const int it = s / nq, idx = s % nq;
     cplx z, w;
-    if (fun == 0) {
+    if (fun == 0 || fun == 2) {
       const double t = tvals[it];
       const int N = n_main;
       const double P = kExpP, mu = kExpMu, L = kExpL;
@@ -84,6 +93,20 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
       const cplx q = cmul(ds, es);
       const double f = h / (2.0 * M_PI * t);
       w = cmk(-q.im * f, q.re * f);
+      if (fun == 2) w = cdiv(w, sv);  // phi_1: weight over s (s != 0: Re s = P at u = 0)
+    } else if (fun == 3) {
+      const double t = tvals[it];
+      const int N = n_main;
+      const double rho = exp(37.0 / N), c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+      const double th = 2.0 * M_PI * (idx + 0.5) / N;
+      const double ct = cos(th), st = sin(th);
+      const double ap = 0.5 * (rho + 1.0 / rho), am = 0.5 * (rho - 1.0 / rho);
+      z = cmk(c + h * ap * ct, h * am * st);
+      const cplx dz = cmk(-h * ap * st, h * am * ct);  // d zeta / d theta
+      const cplx sq = csqrt_p(z);
+      const cplx fz = ccos(cmk(t * sq.re, t * sq.im));
+      const cplx q = cmul(fz, dz);
+      w = cmk(q.im / N, -q.re / N);  // q / (i N)
     } else {
       const int N = n_main;
       const double c = sqrt(sqrt(lo * hi));
@@ -100,9 +123,10 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
 
 // Accuracy of the rule as a function, once per solve: the restarted iteration with a fixed rule r
 // converges to r(A) b, so |r - f| over the spectral region bounds what the rule adds to the error.
-// Samples (kRuleSamples per time point): exp(-t z) at t z = 0 and t z geometric in [1e-4, 1e4],
-// absolute error (f <= 1 there); z^(-1/2) at z geometric in [lo, hi], relative error.  The largest
-// error over samples and time points goes to st->rule_err.  One block of kRuleSamples threads.
+// Samples (kRuleSamples per time point): exp(-t z) and phi_1(-t z) at t z = 0 and t z geometric in
+// [1e-4, 1e4], absolute error (0 < f <= 1 there); z^(-1/2) at z geometric in [lo, hi], relative
+// error; cos(t sqrt z) at sqrt z uniform in [sqrt lo, sqrt hi], absolute error (|f| <= 1).  The
+// largest error over samples and time points goes to st->rule_err.  One block of kRuleSamples threads.
 __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, const double* __restrict__ tvals,
                                                              int nq, double lo, double hi,
                                                              const cplx* __restrict__ rz,
@@ -115,11 +139,16 @@ __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, co
     const cplx* zz = rz + (size_t)it * nq;
     const cplx* ww = rw + (size_t)it * nq;
     double z, f;
-    if (fun == 0) {
+    if (fun == 0 || fun == 2) {
       const double t = tvals[it];
       const double tz = (j == 0) ? 0.0 : 1e-4 * pow(1e8, (double)(j - 1) / (kRuleSamples - 2));
       z = tz / t;
-      f = exp(-tz);
+      f = (fun == 0) ? exp(-tz) : (tz > 0.0 ? -expm1(-tz) / tz : 1.0);
+    } else if (fun == 3) {
+      const double t = tvals[it];
+      const double sq = sqrt(lo) + (sqrt(hi) - sqrt(lo)) * (double)j / (kRuleSamples - 1);
+      z = sq * sq;
+      f = cos(t * sq);
     } else {
       z = lo * pow(hi / lo, (double)j / (kRuleSamples - 1));
       f = 1.0 / sqrt(z);
@@ -128,8 +157,8 @@ __global__ __launch_bounds__(kRuleSamples) void k_rule_check(int fun, int nt, co
     // four independent divisions per trip, so their dependent chains interleave
 #pragma unroll 4
     for (int l = 0; l < nq; ++l) r = cadd(r, cdiv(ww[l], csub(zz[l], cmk(z, 0.0))));
-    const double rv = (fun == 0) ? 2.0 * r.re : r.re;  // conjugate-half exp rule: twice the real part
-    err = fmax(err, (fun == 0) ? fabs(rv - f) : fabs(rv / f - 1.0));
+    const double rv = rule_is_half(fun) ? 2.0 * r.re : r.re;  // conjugate-half rules: twice the real part
+    err = fmax(err, (fun == 1) ? fabs(rv / f - 1.0) : fabs(rv - f));
   }
   for (int off = 32; off > 0; off >>= 1) err = fmax(err, __shfl_xor(err, off, 64));
   if ((j & 63) == 0) red[j >> 6] = err;
@@ -168,9 +197,12 @@ __global__ __launch_bounds__(kThreads) void k_sqnorm(int n, const T* __restrict_
   }
 }
 
-// Cycle start (the normalisation that opens Algorithm 1): alpha = ||S v|| and u_1 = S v / alpha (sketched), or
-// alpha = ||v|| (plain).  Resets the per-cycle flags and zeroes all sketch accumulators.
-__global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, double* __restrict__ slots_start,
+// Cycle start (the normalisation that opens Algorithm 1): alpha = ||S v|| and u_1 = S v / alpha
+// (sketched; sv = S v, the fixed-order sum of the partials), or alpha = ||v|| (plain: kSlots copies
+// of ||v||^2 in slots_start).  Resets the per-cycle flags; for the plain method also zeroes its
+// accumulators.
+__global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, const double* __restrict__ sv,
+                                                    double* __restrict__ slots_start,
                                                     double* __restrict__ slots_step, size_t step_len,
                                                     double* __restrict__ U, double* __restrict__ R,
                                                     State* __restrict__ st, size_t bs) {
@@ -180,13 +212,13 @@ __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, dou
   if (st->done) return;
   slots_start = bat(slots_start, bs);
   slots_step = bat(slots_step, bs);
+  sv = bat(sv, bs);
   U = bat(U, bs);
   R = bat(R, bs);
   double acc = 0.0;
   if (!plain) {
     for (int i = threadIdx.x; i < d; i += kThreads) {
-      double s = 0.0;
-      for (int c = 0; c < kSlots; ++c) s += slots_start[(size_t)c * d + i];
+      const double s = sv[i];
       U[i] = s;
       acc += s * s;
     }
@@ -218,10 +250,12 @@ __global__ __launch_bounds__(kThreads) void k_start(int d, int m, int plain, dou
   }
   __syncthreads();
   const double inv = (s_alpha > 0.0) ? 1.0 / s_alpha : 0.0;
-  if (!plain)
+  if (!plain) {
     for (int i = threadIdx.x; i < d; i += kThreads) U[i] *= inv;
-  for (int i = threadIdx.x; i < kSlots * d; i += kThreads) slots_start[i] = 0.0;
-  for (size_t i = threadIdx.x; i < 2 * step_len; i += kThreads) slots_step[i] = 0.0;
+  } else {
+    for (int i = threadIdx.x; i < kSlots; i += kThreads) slots_start[i] = 0.0;
+    for (size_t i = threadIdx.x; i < 2 * step_len; i += kThreads) slots_step[i] = 0.0;
+  }
   for (int i = threadIdx.x; i < (m + 1) * m; i += kThreads) R[i] = 0.0;
 }
 
@@ -620,9 +654,9 @@ __global__ __launch_bounds__(kWhitenThreads) void k_whiten_mem(SmallArgs a0) {
 // Quadrature solves, one wavefront per system s: (zeta_s I - Rt) y = e_1 with Rt upper Hessenberg.
 // Lane l holds column l of the row being eliminated (m <= 64); Gaussian elimination with partial
 // pivoting between neighbouring rows stores the triangular factor in LDS, then a column-oriented
-// back substitution needs one broadcast per row.  Adds alpha w_s psi_s y into the pass
-// coefficients of its rule (FP64 atomics into the zeroed g buffer) and advances
-// psi_s <- psi_s alpha r tau y_m.
+// back substitution needs one broadcast per row.  Stores its term alpha w_s psi_s y of the pass
+// coefficients in row s of the g buffer (k_combine adds the rows of a time point in node order)
+// and advances psi_s <- psi_s alpha r tau y_m.
 // v of lane src (src the same in every lane), through the scalar unit rather than an LDS permute
 __device__ __forceinline__ cplx bcast_c(cplx v, int src) { return cplx{bcast_lane(v.re, src), bcast_lane(v.im, src)}; }
 // 1 / b through one real division (the moduli met here are far from the FP64 range limits)
@@ -693,27 +727,32 @@ __global__ __launch_bounds__(64) void k_quad(SmallArgs a0) {
   const cplx ps = a.psi[sidx];
   const cplx wp = cmul(a.rw[sidx], ps);
   {
-    // add alpha * w psi y into the coefficients of its time point (twice the real part for the
-    // conjugate-half exp rule)
-    const int it = sidx / a.nq;
-    const double fac = (a.fun == 0) ? 2.0 : 1.0;
-    if (lane < mm) unsafeAtomicAdd(a.gbuf + (size_t)it * a.m + lane, fac * st->alpha * cmul(wp, y).re);
+    // this node's term alpha * w psi y of its time point's coefficients (twice the real part for the
+    // conjugate-half rules)
+    const double fac = rule_is_half(a.fun) ? 2.0 : 1.0;
+    if (lane < mm) a.gbuf[(size_t)sidx * a.m + lane] = fac * st->alpha * cmul(wp, y).re;
   }
   const cplx ym = bcast_c(y, mm - 1);
   if (lane == 0) a.psi[sidx] = cscale(cmul(ps, ym), st->cpl);
 }
 
-// Pass coefficients C[:, t] (t < nt) from the rule sums; the restart column C[:, nt] was written
-// by the whitening kernel.
+// Pass coefficients C[:, t] (t < nt): the rule nodes' terms of each time point added in node order
+// (a fixed order, so the same bits on every run); the restart column C[:, nt] was written by the
+// whitening kernel.
 __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a0) {
   const SmallArgs a = member_args(a0);
   const State* st = a.st;
   if (st->done) return;
-  const int m = a.m, nt = a.nt, mm = st->meff;
+  const int m = a.m, nt = a.nt, mm = st->meff, nq = a.nq;
   const bool zero = st->nonfinite || mm == 0;
   for (int e = threadIdx.x; e < (m + 1) * nt; e += kThreads) {
     const int i = e % (m + 1), it = e / (m + 1);
-    a.C[e] = (zero || i >= mm) ? 0.0 : a.gbuf[(size_t)it * m + i];
+    double v = 0.0;
+    if (!zero && i < mm) {
+      const double* g = a.gbuf + (size_t)it * nq * m + i;
+      for (int l = 0; l < nq; ++l) v += g[(size_t)l * m];
+    }
+    a.C[e] = v;
   }
   if (zero)
     for (int i = threadIdx.x; i <= m; i += kThreads) a.C[(size_t)nt * (m + 1) + i] = 0.0;
@@ -791,12 +830,15 @@ __global__ __launch_bounds__(kGrowRows) void k_grow_expmv(SmallArgs a, const dou
   const double* blk = gM + (size_t)off * m;
   const int j0 = li > 0 ? li - 1 : 0;  // Hessenberg: entries from column li - 1 on
   const double kap = (i < p && li == 0 && c > 0) ? gK[c] : 0.0;
-  // ||M||_1: column sums
-  for (int e = i; e < p; e += kGrowRows) colsum[e] = 0.0;
-  __syncthreads();
+  // ||M||_1: thread i sums column i (blocks are square, so column i is local column li of block c):
+  // rows 0 .. li+1 of its block (Hessenberg) and, for a block's last column, the coupling entry
+  // in the first row of the next block; each sum in row order
   if (i < p) {
-    for (int jj = j0; jj < sz; ++jj) atomicAdd(&colsum[off + jj], fabs(blk[li + (size_t)jj * m]));
-    if (kap != 0.0) atomicAdd(&colsum[off - 1], fabs(kap));
+    double cs = 0.0;
+    const int rmax = min(li + 1, sz - 1);
+    for (int r = 0; r <= rmax; ++r) cs += fabs(blk[r + (size_t)li * m]);
+    if (li == sz - 1 && c + 1 < st->grow_c) cs += fabs(gK[c + 1]);
+    colsum[i] = cs;
   }
   __syncthreads();
   double cmax = 0.0;
@@ -860,33 +902,36 @@ hipError_t launch_small_grow(hipStream_t s, const SmallArgs& a, double* gM, doub
 }
 
 // ------------------------------------------------------------------------------ fused pass
-// x_t += W c_t for every time point, v_hat = W c_nt written over column 0, and per-block
-// partial norms ||y_t||^2, ||x_t||^2 (added into kSlots copies).
+// x_t += W c_t for every time point, v_hat = W c_nt written over column 0, and per-block partial
+// norms ||y_t||^2, ||x_t||^2, written to entries dn + 2t and dn + 2t + 1 of the partial buffer
+// (k_reduce_parts adds the blocks in a fixed order).
 constexpr int kPassGroup = 8;  // basis columns whose loads the pass issues together
 
-// With ps.slots set, the pass also sketches v_hat for the next cycle's start (alpha = ||S v_hat||,
+// With ps.on, the pass also sketches v_hat for the next cycle's start (alpha = ||S v_hat||,
 // u_1 = S v_hat / alpha): each row's S column is regenerated as in the fused product and added
-// into d bins in LDS, which are flushed into one of the kSlots copies at the end.  That spares the
-// next cycle a sketch-only pass over v_hat; the extra ALU work hides under the pass's loads.
+// into d bins in LDS (one set per wavefront, as there), whose fixed-order sums go to entries
+// [0, d) of the partial buffer.  That spares the next cycle a sketch-only pass over v_hat; the
+// extra ALU work hides under the pass's loads.
 template <typename T, int NT>
-__global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const double* __restrict__ C,
+__global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn, const double* __restrict__ C,
                                                    T* __restrict__ W, double* __restrict__ x, int64_t ldx,
-                                                   double* __restrict__ norm_slots, const State* __restrict__ st,
+                                                   double* __restrict__ parts, const State* __restrict__ st,
                                                    size_t bs, PassSketch ps) {
   __shared__ double part[kThreads / 64][2 * NT];
-  extern __shared__ double pbins[];  // ps.d bins when sketching
+  extern __shared__ double pbins[];  // (kThreads / 64) x ps.d bins when sketching
   st = bat(st, bs);
   const int mm = st->meff;
   if (st->done || st->nonfinite || mm == 0) return;
   C = bat(C, bs);
   W = bat(W, bs);
-  norm_slots = bat(norm_slots, bs);
+  parts = bat(parts, bs);
   x += (int64_t)blockIdx.y * nt * ldx;  // member r's time points are columns r nt .. r nt + nt - 1
   const int brk = st->brk;
   const int ncol = brk ? mm : mm + 1;
-  const bool sk = ps.slots != nullptr && !brk;  // block-uniform
+  const bool sk = ps.on && !brk;  // block-uniform
+  double* wbins = pbins + (threadIdx.x >> 6) * ps.d;
   if (sk) {
-    for (int b = threadIdx.x; b < ps.d; b += kThreads) pbins[b] = 0.0;
+    for (int b = threadIdx.x; b < (kThreads / 64) * ps.d; b += kThreads) pbins[b] = 0.0;
     __syncthreads();
   }
   double yn[NT], xn[NT];
@@ -937,7 +982,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
       const double zs = (double)(T)acc[NT] * ps.scale;  // the stored value, as the next cycle reads it
 #pragma unroll
       for (int l = 0; l < 8; ++l)
-        if (l < ps.zeta) unsafeAtomicAdd(&pbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+        if (l < ps.zeta) unsafeAtomicAdd(&wbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -950,48 +995,71 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, const d
     }
   }
   __syncthreads();
+  const size_t pidx = part_index();
   if (threadIdx.x < 2 * nt) {
-    double s = 0.0;
-    for (int q = 0; q < kThreads / 64; ++q) s += part[q][threadIdx.x];
-    unsafeAtomicAdd(norm_slots + (size_t)(blockIdx.x % kSlots) * (2 * kMaxNt) + threadIdx.x, s);
+    double s = part[0][threadIdx.x];
+    for (int q = 1; q < kThreads / 64; ++q) s += part[q][threadIdx.x];
+    parts[(size_t)(dn + threadIdx.x) * kMaxParts + pidx] = s;
   }
-  if (sk) {  // the barrier above ordered every bin update before these reads
-    double* sl = bat(ps.slots, bs) + (size_t)(blockIdx.x % kSlots) * ps.d;
+  if (ps.on) {  // the barrier above ordered every bin update before these reads; zeros after a breakdown
     for (int b = threadIdx.x; b < ps.d; b += kThreads) {
-      const double v = pbins[b];
-      if (v != 0.0) unsafeAtomicAdd(sl + b, v);
+      double v = 0.0;
+      if (sk) {
+        v = pbins[b];
+        for (int q = 1; q < kThreads / 64; ++q) v += pbins[q * ps.d + b];
+      }
+      parts[(size_t)b * kMaxParts + pidx] = v;
     }
   }
 }
 
-// Convergence test after the pass (Algorithm 2 stopping rule, relative form).
-__global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, State* __restrict__ st,
+// Convergence test after the pass: the error estimate after Algorithm 2 (the difference of two
+// successive cycles, y_c = x_c - x_{c-1}) read as the first of the remaining increments.  With q
+// the largest of the last three contraction ratios ||y_c|| / ||y_{c-1}|| of a time point (fewer in
+// cycles 2 and 3), the remaining error is estimated by the geometric tail
+//   err_t = (||y_c|| / ||x_c||) q / (1 - q)   for q < 1, and is unbounded for q >= 1
+// (in particular after the first cycle, which has no ratio).  Small ratios between growing
+// increments (a dip inside a transient) do not end the loop.  The solve stops when
+// max_t err_t <= tol.  The raw relative increment max_t ||y_c|| / ||x_c|| is reported too; it
+// decides divergence.  The norms are the fixed-order sums of the pass's partials (red + dn).
+__global__ void k_final(int nt, int dn, double tol, const double* __restrict__ red, State* __restrict__ st,
                         Report* __restrict__ rep, size_t bs) {
   if (threadIdx.x != 0) return;
   st = bat(st, bs);
-  norm_slots = bat(norm_slots, bs);
+  red = bat(red, bs) + dn;
   rep += blockIdx.y;
   if (st->done) {  // finished in an earlier cycle: report unchanged
     rep->done = 1;
     return;
   }
-  double est = 0.0, qd = 0.0;
+  const double inf = __builtin_inf();
+  const int c = st->cyc;
+  double est = 0.0, rel = 0.0, qd = 0.0;
   for (int it = 0; it < nt; ++it) {
-    double y2 = 0.0, x2 = 0.0;
-    for (int q = 0; q < kSlots; ++q) {
-      y2 += norm_slots[(size_t)q * (2 * kMaxNt) + 2 * it];
-      x2 += norm_slots[(size_t)q * (2 * kMaxNt) + 2 * it + 1];
-    }
+    const double y2 = red[2 * it], x2 = red[2 * it + 1];
     st->ynorm2[it] = y2;
     st->xnorm2[it] = x2;
-    const double e = (x2 > 0.0) ? sqrt(y2 / x2) : 0.0;
+    const double y = sqrt(y2);
+    const double r = (x2 > 0.0) ? sqrt(y2 / x2) : 0.0;
+    rel = fmax(rel, r);
+    const double yp = st->yprev[it];
+    const double q = (c == 0) ? inf : (yp > 0.0 ? y / yp : (y > 0.0 ? inf : 0.0));
+    double qb = q;
+    if (c >= 2) qb = fmax(qb, st->qprev[it]);
+    if (c >= 3) qb = fmax(qb, st->qprev2[it]);
+    const double e = (r == 0.0) ? 0.0 : (qb < 1.0 ? r * qb / (1.0 - qb) : inf);
     est = fmax(est, e);
+    st->yprev[it] = y;
+    st->qprev2[it] = st->qprev[it];
+    st->qprev[it] = q;
   }
+  st->cyc = c + 1;
+  st->relupd = rel;
   qd = st->rule_err;
-  for (int q = 0; q < kSlots * 2 * kMaxNt; ++q) norm_slots[q] = 0.0;
   st->est = est;
   st->converged = (est <= tol) ? 1 : 0;
   rep->est = est;
+  rep->relupd = rel;
   rep->rule_err = qd;
   rep->alpha = st->alpha;
   rep->beta = st->beta;
@@ -1001,17 +1069,8 @@ __global__ void k_final(int nt, double tol, double* __restrict__ norm_slots, Sta
   rep->nonfinite = st->nonfinite;
   rep->converged = st->converged;
   rep->grow_fail = st->grow_fail;
-  st->done = (st->converged || st->brk || st->nonfinite || !(est <= kDivergedEst)) ? 1 : 0;
+  st->done = (st->converged || st->brk || st->nonfinite || !(rel <= kDivergedEst)) ? 1 : 0;
   rep->done = st->done;
-}
-
-// Sum of the slot copies: out[i] = sum_c slots[c*len + i] (sketch test hook).
-__global__ void k_reduce_slots(int len, const double* __restrict__ slots, double* __restrict__ out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < kSlots; ++c) s += slots[(size_t)c * len + i];
-    out[i] = s;
-  }
 }
 
 // Rows and signs of S for a range of columns (specification test hook).
@@ -1078,7 +1137,7 @@ hipError_t launch_zero(hipStream_t s, double* p, size_t count) {
 hipError_t launch_rule(hipStream_t s, int fun, int nt, const double* tvals, int n_main, double lo, double hi,
                        cplx* rz, cplx* rw, cplx* psi, State* st, int nb, size_t bs) {
   hipLaunchKernelGGL(k_rule, dim3(8, nb), dim3(256), 0, s, fun, nt, tvals, n_main, lo, hi, rz, rw, psi, bs);
-  const int nq = (fun == 0) ? n_main / 2 : n_main;
+  const int nq = rule_is_half(fun) ? n_main / 2 : n_main;
   hipLaunchKernelGGL(k_rule_check, dim3(1), dim3(kRuleSamples), 0, s, fun, nt, tvals, nq, lo, hi, rz, rw, st, nb,
                      bs);
   return hipGetLastError();
@@ -1102,10 +1161,10 @@ hipError_t launch_sqnorm(hipStream_t s, int dtype, int grid, int n, const void* 
   return hipGetLastError();
 }
 
-hipError_t launch_start(hipStream_t s, int d, int m, int plain, double* slots_start, double* slots_step,
-                        size_t step_len, double* U, double* R, State* st, int nb, size_t bs) {
-  hipLaunchKernelGGL(k_start, dim3(1, nb), dim3(kThreads), 0, s, d, m, plain, slots_start, slots_step, step_len, U,
-                     R, st, bs);
+hipError_t launch_start(hipStream_t s, int d, int m, int plain, const double* sv, double* slots_start,
+                        double* slots_step, size_t step_len, double* U, double* R, State* st, int nb, size_t bs) {
+  hipLaunchKernelGGL(k_start, dim3(1, nb), dim3(kThreads), 0, s, d, m, plain, sv, slots_start, slots_step, step_len,
+                     U, R, st, bs);
   return hipGetLastError();
 }
 
@@ -1145,12 +1204,12 @@ hipError_t launch_small(hipStream_t s, const SmallArgs& a, int nb, const GrowBuf
 }
 
 template <typename T>
-static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, const double* C, T* W, double* x,
-                          int64_t ldx, double* ns, const State* st, int nb, size_t bs, const PassSketch& ps) {
+static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, int dn, const double* C, T* W, double* x,
+                          int64_t ldx, double* parts, const State* st, int nb, size_t bs, const PassSketch& ps) {
   const dim3 g(grid, nb);
-  const size_t lds = ps.slots ? (size_t)ps.d * sizeof(double) : 0;
+  const size_t lds = ps.on ? (size_t)(kThreads / 64) * ps.d * sizeof(double) : 0;
 #define FAB_P(NTV) \
-  hipLaunchKernelGGL((k_pass<T, NTV>), g, dim3(kThreads), lds, s, n, m, nt, C, W, x, ldx, ns, st, bs, ps)
+  hipLaunchKernelGGL((k_pass<T, NTV>), g, dim3(kThreads), lds, s, n, m, nt, dn, C, W, x, ldx, parts, st, bs, ps)
   if (nt <= 1)
     FAB_P(1);
   else if (nt <= 2)
@@ -1164,25 +1223,21 @@ static void launch_pass_t(hipStream_t s, int grid, int n, int m, int nt, const d
 #undef FAB_P
 }
 
-hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt, const double* C, void* W,
-                       double* x, int64_t ldx, double* norm_slots, const State* st, int nb, size_t bs,
+hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt, int dn, const double* C, void* W,
+                       double* x, int64_t ldx, double* parts, const State* st, int nb, size_t bs,
                        const PassSketch& ps) {
-  if (ps.slots && (ps.zeta < 1 || ps.zeta > 8 || ps.d < 1 || ps.d > kMaxD)) return hipErrorInvalidValue;
+  if (ps.on && (ps.zeta < 1 || ps.zeta > 8 || ps.d < 1 || ps.d > kMaxD || ps.d != dn)) return hipErrorInvalidValue;
+  if (grid < kXcds || grid > kMaxParts || grid % kXcds != 0) return hipErrorInvalidValue;  // part_index
   if (dtype == 0)
-    launch_pass_t<double>(s, grid, n, m, nt, C, (double*)W, x, ldx, norm_slots, st, nb, bs, ps);
+    launch_pass_t<double>(s, grid, n, m, nt, dn, C, (double*)W, x, ldx, parts, st, nb, bs, ps);
   else
-    launch_pass_t<float>(s, grid, n, m, nt, C, (float*)W, x, ldx, norm_slots, st, nb, bs, ps);
+    launch_pass_t<float>(s, grid, n, m, nt, dn, C, (float*)W, x, ldx, parts, st, nb, bs, ps);
   return hipGetLastError();
 }
 
-hipError_t launch_final(hipStream_t s, int nt, double tol, double* norm_slots, State* st, Report* rep, int nb,
+hipError_t launch_final(hipStream_t s, int nt, int dn, double tol, const double* red, State* st, Report* rep, int nb,
                         size_t bs) {
-  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, tol, norm_slots, st, rep, bs);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_slots(hipStream_t s, int len, const double* slots, double* out) {
-  hipLaunchKernelGGL(k_reduce_slots, dim3((len + 255) / 256), dim3(256), 0, s, len, slots, out);
+  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, dn, tol, red, st, rep, bs);
   return hipGetLastError();
 }
 

@@ -9,11 +9,13 @@
 namespace fab {
 
 constexpr int kThreads = 256;      // threads per block of the streaming kernels
-constexpr int kSlots = 8;          // copies of each sketch accumulator (spreads FP64 atomics)
+constexpr int kSlots = 8;          // copies of each accumulator of the plain comparator's atomics
+constexpr int kMaxParts = 2048;    // largest grid of a kernel that writes per-block partial sums
 constexpr int kMaxM = 64;          // largest cycle length
 constexpr int kMaxD = 2048;        // largest sketch dimension (LDS bins: 16 KB FP64)
 constexpr int kMaxNt = 16;         // largest number of time points per solve
 constexpr int kRuleMain = 128;     // default nodes of the quadrature rule
+constexpr int kRuleCosSqrt = 256;  // default nodes of the ellipse rule of cos(t sqrt z)
 constexpr int kRuleSamples = 256;  // sample points of the rule's accuracy check
 constexpr double kExpP = 3.0, kExpMu = 6.0, kExpL = 45.0;  // parabolic contour of the exp rule
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
@@ -99,6 +101,22 @@ __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
   return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 __device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+// principal square root (branch cut on the negative real axis), without cancellation
+__device__ __forceinline__ cplx csqrt_p(cplx z) {
+  const double r = hypot(z.re, z.im);
+  if (r == 0.0) return cplx{0.0, 0.0};
+  if (z.re >= 0.0) {
+    const double t = sqrt(0.5 * (r + z.re));
+    return cplx{t, z.im / (2.0 * t)};
+  }
+  const double t = sqrt(0.5 * (r - z.re));
+  return cplx{fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+// cos(x + iy) = cos x cosh y - i sin x sinh y
+__device__ __forceinline__ cplx ccos(cplx z) { return cplx{cos(z.re) * cosh(z.im), -sin(z.re) * sinh(z.im)}; }
+// Functions whose rule is conjugate-symmetric: only the Im zeta > 0 half of the nodes is kept and
+// the sums take twice the real part (all but z^(-1/2), whose nodes are real).
+__host__ __device__ __forceinline__ bool rule_is_half(int fun) { return fun != 1; }
 __device__ __forceinline__ double cabs1(cplx a) { return fabs(a.re) + fabs(a.im); }
 // a / b, scaled to avoid overflow (Smith's method)
 __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
@@ -130,13 +148,29 @@ struct State {
   int grow_c, grow_p, grow_fail;
   int gram_rows;  // rows of the sketched Gram matrix G = U^T U complete in this cycle (0: none kept)
   int whiten_chol;  // this cycle's T: 1 from the Cholesky factor of G, 0 from the Householder QR
+  // stopping test: ||y_t|| of the previous cycle, the contraction ratios ||y_t|| / ||y_t||_prev of
+  // the previous two cycles, the cycles run so far, and the largest relative increment
+  // ||y_t|| / ||x_t|| of this cycle
+  double yprev[kMaxNt], qprev[kMaxNt], qprev2[kMaxNt];
+  double relupd;
+  int cyc;
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).
 struct Report {
-  double est, rule_err, alpha, beta, kappa_T;
+  double est, rule_err, alpha, beta, kappa_T, relupd;
   int brk, meff, nonfinite, converged, done, grow_fail;
 };
+
+// Per-block partial sums in a fixed order.  A kernel whose grid is a multiple of kXcds and at most
+// kMaxParts blocks writes entry e of block b's partial to parts[e * kMaxParts + part_index()]; the
+// reduction kernel then adds the entries p = 0, 1, ... in one order on every run, so the result
+// does not depend on which block finished first (FP64 atomics would make it depend on that).
+// Blocks are dealt round-robin to the XCDs, so the index is XCD-major: the 16 partials that share
+// a 128-byte line come from blocks of one XCD and merge in its L2.
+__device__ __forceinline__ size_t part_index() {
+  return (size_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+}
 
 // Batched solves: member r of a batch owns a copy of the single-solve workspace at byte offset
 // r * bs; kernels launched with gridDim.y = members shift their workspace pointers with bat().
@@ -174,7 +208,7 @@ struct SmallArgs {
   const cplx* rz;
   const cplx* rw;
   cplx* psi;
-  double* gbuf;     // nt x m: the rule sums of the cycle (restart coefficients before k_combine)
+  double* gbuf;     // (nt nq) x m: each rule node's term of the restart coefficients (k_combine adds them)
   double* C;        // (m+1) x (nt+1) pass coefficients (main rule), restart column last
   const double* G;  // (m+1) x (m+1) sketched Gram matrix, row-major lower triangle (st->gram_rows rows)
   State* st;
@@ -199,10 +233,11 @@ __device__ __forceinline__ SmallArgs member_args(const SmallArgs& a0) {
   return a;
 }
 
-// Sketch of the restart vector accumulated by the pass for the next cycle's start (slots ==
-// nullptr: the pass does not sketch, and the cycle starts with a sketch-only pass instead).
+// Sketch of the restart vector formed by the pass for the next cycle's start (on == 0: the pass
+// does not sketch, and the cycle starts with a sketch-only pass instead).  The pass writes its
+// partials of S v_hat to entries [0, d) of the partial buffer and those of the norms after them.
 struct PassSketch {
-  double* slots;  // kSlots x d accumulators of the next cycle's start (member r at r * bs)
+  int on;
   int d, zeta;    // zeta <= 8
   uint32_t k0, k1;
   double scale;   // 1/sqrt(zeta) rounded to the value type, as the sketch-only pass applies it
@@ -218,8 +253,8 @@ struct GrowBuffers {
 };
 
 struct Layout {
-  size_t W, U, R, slots_step, slots_start, slots_norm, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf,
-      grow, G, report, total;
+  size_t W, U, R, slots_step, slots_start, uraw, red, state, T, Ut, X, C, rule_z, rule_w, psi, gbuf, grow, G,
+      parts, total;
   int nsys, nq;
 };
 

@@ -3,9 +3,12 @@
 //
 //   k_spmv_sketch : z = A w_j (CSR, one row per lane) fused with u = S z, the sparse-sign sketch
 //                   (the product and sketch of Algorithm 1).  S's rows and signs are regenerated
-//                   per row from its counter-based specification, scattered into per-block LDS
-//                   bins and added into kSlots global copies.  Batches: one member per block, or
-//                   16 per block with the tile sketch on the matrix cores.
+//                   per row from its counter-based specification and scattered into LDS bins, one
+//                   set per wavefront; each block writes its partial sketch to the partial buffer.
+//                   Batches: one member per block, or 16 per block with the tile sketch on the
+//                   matrix cores.
+//   k_reduce_parts: the per-block partials summed in a fixed order (the sketch of z, the norms of
+//                   the pass): bit-for-bit the same result on every run.
 //   k_orth_update : one launch for step j's Gram-Schmidt and window update (single solves with a
 //                   small sketch): persistent blocks, each redoing the sketch-space Gram-Schmidt
 //                   in one wavefront while four stream the basis update.
@@ -56,8 +59,12 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 // Each block walks row tiles of kThreads rows (XCD-contiguous slabs).  The tile's nonzeros are
 // staged through LDS in chunks of kChunk with coalesced loads of values and column indices, then
 // every lane forms its own row (so stencil gathers of x stay coalesced across the wavefront).
-// The sketch of the row value is scattered into per-block FP64 LDS bins, which are added
-// into one of kSlots global FP64 copies at the end.  The rows and signs of S are regenerated from
+// The sketch of the row value is scattered into FP64 LDS bins, one set per wavefront: a
+// wavefront's LDS atomics are applied in one order (its instructions in program order, the lanes of
+// one instruction in the hardware's fixed order), so only the four sets are added at the end, in a
+// fixed order, into the block's partial in the partial buffer (see part_index; k_reduce_parts adds
+// the blocks).  Shared bins would take the wavefronts' adds in whatever order they arrive, and the
+// sketch, hence every later step, would change in its last bits from run to run.  The rows and signs of S are regenerated from
 // the counter-based specification for every row (no bytes of S are read): with the LDS-staged
 // product the generator's integer work overlaps the memory traffic.
 // Rows are summed in FP64 for FP32 data too: a stencil row's terms are ~|w|/h^2 while the row sum
@@ -75,12 +82,13 @@ constexpr int kGather = 8;
 // issued before the first LDS write, so the tile waits for one memory round trip rather than one
 // per element.  Barriers on both sides (the previous chunk has been consumed; this one is ready).
 // With colrel (operators whose columns all lie within 16 bits of their tile's first row, row0) the
-// columns are read as those 16-bit offsets: 2 bytes per nonzero instead of 4.  The offsets are
-// added to row0 only when written to LDS, so no load waits for another.
+// columns are read as those 16-bit offsets: 2 bytes per nonzero instead of 4.  Each offset is held
+// in a 32-bit register (packed pairs would make every load wait for the previous one).  With sc16
+// the offsets are stored in LDS as they are (the reader adds row0), else widened to columns.
 template <typename T>
 __device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const int* __restrict__ colind,
                                             const int16_t* __restrict__ colrel, int row0, int cs, int len, T* sv,
-                                            int* sc) {
+                                            int* sc, int16_t* sc16 = nullptr) {
   __syncthreads();
   T tv[kChunk / kThreads];
   if (colrel) {  // uniform over the grid
@@ -98,7 +106,8 @@ __device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const in
       const int e = threadIdx.x + q * kThreads;
       if (e < len) {
         sv[e] = tv[q];
-        sc[e] = row0 + (int)tr[q];
+        if (sc16) sc16[e] = (int16_t)tr[q];
+        else sc[e] = row0 + (int)tr[q];
       }
     }
   } else {
@@ -124,10 +133,11 @@ __device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const in
 }
 
 // acc + sum of the row's entries [lo, hi) (LDS positions relative to cs) times x, in entry order,
-// kGather gathers of x in flight at a time.
-template <typename T>
-__device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* __restrict__ x, int lo, int hi, int cs,
-                                          double acc) {
+// kGather gathers of x in flight at a time.  Columns from sc (I = int) or as 16-bit offsets from
+// the tile's first row row0 (I = int16_t).
+template <typename T, typename I>
+__device__ __forceinline__ double row_dot(const T* sv, const I* sc, int row0, const T* __restrict__ x, int lo, int hi,
+                                          int cs, double acc) {
   for (int pg = lo; pg < hi; pg += kGather) {
     T av[kGather], xv[kGather];
 #pragma unroll
@@ -137,7 +147,7 @@ __device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* _
       xv[q] = T(0);
       if (p < hi) {
         av[q] = sv[p - cs];
-        xv[q] = x[sc[p - cs]];
+        xv[q] = x[(sizeof(I) == 2 ? row0 : 0) + (int)sc[p - cs]];
       }
     }
 #pragma unroll
@@ -146,11 +156,14 @@ __device__ __forceinline__ double row_dot(const T* sv, const int* sc, const T* _
   return acc;
 }
 
-// LDS layout of the fused kernel: bins (G*d FP64), then for member groups (G > 1) the tile's
-// products (kThreads*G values) and S's column masks (kThreads*ceil(d/16) words), then the CSR chunk
-// (kChunk values and column indices).
+// LDS layout of the fused kernel: bins (one set of d FP64 per wavefront for one member per block;
+// G*d FP64, owned bin by bin by the matrix-core loop, for member groups), then for member groups
+// (G > 1) the tile's products (kThreads*G values) and S's column masks (kThreads*ceil(d/16) words),
+// then the CSR chunk (kChunk values, then kChunk column indices: 16-bit tile offsets for one member
+// per block on an operator that has them, else 32-bit columns).
+constexpr int kWaves = kThreads / 64;
 __host__ __device__ inline size_t spmv_lds_bins(int mode, int d, int G) {
-  return (mode == 2) ? 0 : (((size_t)G * d * 8 + 15) & ~(size_t)15);
+  return (mode == 2) ? 0 : (((size_t)(G > 1 ? G : kWaves) * d * 8 + 15) & ~(size_t)15);
 }
 // Grouped kernel (d <= 256): per tile row, one 32-bit word per 16-bin slice of S's column: bit b
 // = the row hits bin 16 slice + b, bit 16 + b = that entry is negative.
@@ -200,21 +213,26 @@ __device__ __forceinline__ float bf16_value(short h) { return __uint_as_float(((
 
 // Occupancy hint of the fused kernel: for FP32 data one member per block, at least 8 waves per SIMD
 // (the register budget then fits 8 blocks per CU; LDS allows it, and the 256^3 FP32 product runs
-// 17% faster than at the default 7).  FP64 blocks are limited to 6 per CU by LDS anyway, and the
-// grouped kernel would spill under the tighter budget: no hint for them.
-template <typename T, bool GRP>
+// 17% faster than at the default 7).  FP64 blocks that stage 16-bit column offsets: 6 waves (LDS
+// fits 6 blocks of 27 KB at d = 200; unhinted, the compiler takes 89 VGPRs, 5 waves).  Other FP64
+// blocks are limited to 5 or 6 per CU by LDS anyway, and the grouped kernel would spill under a
+// tighter budget: no hint for them.
+template <typename T, bool GRP, bool C16>
 constexpr int spmv_min_waves() {
-  return (sizeof(T) == 4 && !GRP) ? 8 : 1;
+  return (sizeof(T) == 4 && !GRP) ? 8 : ((C16 && !GRP) ? 6 : 1);
 }
 
-template <typename T, int MODE, int ZMAX, bool GRP>
-__global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
+// C16: the CSR chunk's columns are staged in LDS as the operator's 16-bit tile offsets (one member
+// per block on an operator that has them; a separate instantiation, since one kernel holding both
+// forms needs 101 instead of 75 VGPRs and drops from 6 to 4 waves per SIMD).
+template <typename T, int MODE, int ZMAX, bool GRP, bool C16 = false>
+__global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP, C16>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
                                                           const int16_t* __restrict__ colrel,
                                                           const T* __restrict__ vals,
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           int d, int zeta, T scale, uint32_t k0, uint32_t k1,
-                                                          double* __restrict__ slots,
+                                                          double* __restrict__ parts,
                                                           const State* __restrict__ st, int nb, int G, size_t bs) {
   extern __shared__ unsigned char smem_raw[];
   // This block serves batch members r0 .. r0+gn-1 (one member for single solves): the CSR chunk is
@@ -230,14 +248,17 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
   uint32_t* mtile = reinterpret_cast<uint32_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T));  // [row][slice]
   T* sv = reinterpret_cast<T*>(smem_raw + o_chk);
   int* sc = reinterpret_cast<int*>(smem_raw + o_chk + kChunk * sizeof(T));
+  int16_t* sc16 = C16 ? reinterpret_cast<int16_t*>(sc) : nullptr;
   uint32_t live_mask = 0;  // members still iterating (block-uniform)
   for (int g = 0; g < gn; ++g) {
     const State* sg = st ? bat(st, bs, r0 + g) : nullptr;
     if (!sg || !(sg->brk || sg->done)) live_mask |= 1u << g;
   }
   if (live_mask == 0) return;
+  const int nbins = (GRP ? G : kWaves) * d;
+  double* wbins = bins + (GRP ? 0 : (threadIdx.x >> 6) * d);  // this wavefront's set (one member per block)
   if (MODE != 2) {
-    for (int i = threadIdx.x; i < G * d; i += kThreads) bins[i] = 0.0;
+    for (int i = threadIdx.x; i < nbins; i += kThreads) bins[i] = 0.0;
     __syncthreads();
   }
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -262,7 +283,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
       // waiting waves first and the ALU work of the sketch fills the gaps between (159 against
       // 153.5 solves/s on the 128^3 workload; the fused kernel 38.7 against 41.0 us)
       __builtin_amdgcn_s_setprio(2);
-      if (one_chunk) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc);
+      if (one_chunk) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc, sc16);
     }
     if (GRP && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
     int rows[ZMAX];
@@ -298,12 +319,14 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
       if (MODE != 1) {
         double acc = 0.0;  // FP64 row sums for either value type (see the note above)
         if (one_chunk) {
-          acc = row_dot(sv, sc, xg, my_lo, my_hi, p0, acc);
+          if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, my_lo, my_hi, p0, acc);
+          else acc = row_dot(sv, sc, row0, xg, my_lo, my_hi, p0, acc);
         } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
           for (int cs = p0; cs < p1; cs += kChunk) {
             const int len = min(kChunk, p1 - cs);
-            stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc);
-            acc = row_dot(sv, sc, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
+            stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc, sc16);
+            if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
+            else acc = row_dot(sv, sc, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
           }
         }
         z = (T)acc;
@@ -319,7 +342,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
             const double zs = (double)z * (double)scale;
 #pragma unroll
             for (int l = 0; l < ZMAX; ++l)
-              if (l < zeta) unsafeAtomicAdd(&bins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+              if (l < zeta) unsafeAtomicAdd(&wbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
           }
         } else {
           ztile[threadIdx.x * G + g] = z;
@@ -403,34 +426,75 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP>())) void k_spmv_s
       }
     }
   }
-  if (MODE != 2) {
+  if (MODE != 2) {  // the block's partial sketch of every live member, zeros included
     __syncthreads();
+    const size_t pidx = part_index();
     for (int i = threadIdx.x; i < G * d; i += kThreads) {
       const int b = i / G, g = i - b * G;
-      const double v = bins[i];
-      if (g < gn && v != 0.0 && ((live_mask >> g) & 1u))
-        unsafeAtomicAdd(bat(slots, bs, r0 + g) + (size_t)(blockIdx.x % kSlots) * d + b, v);
+      if (g >= gn || !((live_mask >> g) & 1u)) continue;
+      double v;
+      if (GRP) {
+        v = bins[i];
+      } else {  // the wavefront sets in a fixed order
+        v = bins[b];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) v += bins[w * d + b];
+      }
+      bat(parts, bs, r0 + g)[(size_t)b * kMaxParts + pidx] = v;
     }
+  }
+}
+
+// out[i] = sum over p < nparts of parts[(e0 + i) * kMaxParts + p] for i = blockIdx.x, one block per
+// entry and member (blockIdx.y), in a fixed order: thread t adds p = t, t + kThreads, ... in turn
+// (all its loads issued first), a butterfly sums each wavefront, and the wavefront sums are added in
+// order.  Members are skipped as their producer skipped them: skip 0 = broken down or finished (the
+// fused product), 1 = finished, non-finite or empty (the pass), -1 = never.
+__global__ __launch_bounds__(kThreads) void k_reduce_parts(int e0, int nparts, const double* __restrict__ parts,
+                                                           double* __restrict__ out, const State* __restrict__ st,
+                                                           int skip, size_t bs) {
+  __shared__ double ws[kWaves];
+  if (st && skip >= 0) {
+    const State* sm = bat(st, bs);
+    if (skip == 0 ? (sm->brk || sm->done) : (sm->done || sm->nonfinite || sm->meff == 0)) return;
+  }
+  const double* src = bat(parts, bs) + (size_t)(e0 + (int)blockIdx.x) * kMaxParts;
+  double v[kMaxParts / kThreads];
+#pragma unroll
+  for (int u = 0; u < kMaxParts / kThreads; ++u) {
+    const int p = threadIdx.x + u * kThreads;
+    v[u] = (p < nparts) ? src[p] : 0.0;
+  }
+  double s = v[0];
+#pragma unroll
+  for (int u = 1; u < kMaxParts / kThreads; ++u) s += v[u];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = ws[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) r += ws[w];
+    bat(out, bs)[blockIdx.x] = r;
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Sketch-space modified Gram-Schmidt of step j, one wavefront (no barriers).  Element e of the
 // d-vector lives in lane e % 64, slot e / 64 (PER slots per lane, d <= 64 PER).
-// slots_cur: kSlots x d partial sketches of z (summed here in a fixed order); U: d x (m+1)
-// sketched basis.  When `coef` is given, lane 0 stores the window coefficients r_ij there (index
-// i - lo, i = lo..j), 1/rho in *inv and the outcome (1 = a new basis vector) in *ok; when `write`,
-// the wavefront also stores R column j, U column j+1 and the step's state, and zeroes slots_next
-// (the other set, accumulated by step j+1).
+// uraw: S z (d values, the fixed-order sum of the product's partials); U: d x (m+1) sketched
+// basis.  When `coef` is given, lane 0 stores the window coefficients r_ij there (index i - lo,
+// i = lo..j), 1/rho in *inv and the outcome (1 = a new basis vector) in *ok; when `write`, the
+// wavefront also stores R column j, U column j+1 and the step's state.
 // ---------------------------------------------------------------------------------------------
-// KW > 0: the window's KW columns of U are loaded together with the slot sums (one memory round
-// trip instead of one per window column; requires j - lo + 1 <= KW).  When `unew` is given, the
-// lanes receive their PER entries of u_{j+1} there (unchanged on breakdown).
+// KW > 0: the window's KW columns of U are loaded together with S z (one memory round trip
+// instead of one per window column; requires j - lo + 1 <= KW).  When `unew` is given, the lanes
+// receive their PER entries of u_{j+1} there (unchanged on breakdown).
 template <int PER, int KW>
-__device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ slots_cur,
-                                          double* __restrict__ slots_next, double* __restrict__ U,
-                                          double* __restrict__ R, State* __restrict__ st, bool write,
-                                          double* coef, double* inv_out, int* ok_out, double* unew = nullptr) {
+__device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ uraw,
+                                          double* __restrict__ U, double* __restrict__ R, State* __restrict__ st,
+                                          bool write, double* coef, double* inv_out, int* ok_out,
+                                          double* unew = nullptr) {
   const int lane = threadIdx.x & 63;
   const int lo = max(0, j - k + 1);
   double u[PER];
@@ -447,15 +511,8 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = lane + 64 * q;
-    double s = 0.0;
-    if (e < d) {
-#pragma unroll
-      for (int c = 0; c < kSlots; ++c) s += slots_cur[(size_t)c * d + e];
-    }
-    u[q] = s;
+    u[q] = (e < d) ? uraw[e] : 0.0;
   }
-  if (write)
-    for (int i = lane; i < kSlots * d; i += 64) slots_next[i] = 0.0;
   double loc = 0.0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) loc += u[q] * u[q];
@@ -533,18 +590,17 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
 }
 
 template <int PER>
-__global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ slots_cur,
-                                             double* __restrict__ slots_next, double* __restrict__ U,
-                                             double* __restrict__ R, State* __restrict__ st, size_t bs) {
+__global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const double* __restrict__ uraw,
+                                             double* __restrict__ U, double* __restrict__ R, State* __restrict__ st,
+                                             size_t bs) {
   st = bat(st, bs);
   if (st->brk || st->done) return;
-  orth_wave<PER, 0>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st, true, nullptr,
-                    nullptr, nullptr);
+  orth_wave<PER, 0>(j, k, m, d, bat(uraw, bs), bat(U, bs), bat(R, bs), st, true, nullptr, nullptr, nullptr);
 }
 
 // Step j's Gram-Schmidt and window update in one launch (d <= 256), with persistent blocks.
 // Blocks of 1 + 4 wavefronts: the first redoes the sketch-space Gram-Schmidt (the same
-// fixed-order sums in every block, so every block gets the same coefficients; block 0 also stores
+// arithmetic on the same S z in every block, so every block gets the same coefficients; block 0 also stores
 // R, U and the state) while the other four load their first batch of elements (z and the window).
 // After the barrier they stream the block's batches of kOuBatch elements, and the loads of the
 // next batch are issued before the current one is updated and stored, so reads and writes of the
@@ -651,8 +707,7 @@ __device__ __forceinline__ void gram_load(const double* __restrict__ U, int d, i
 
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
-                                                          const double* __restrict__ slots_cur,
-                                                          double* __restrict__ slots_next, double* __restrict__ U,
+                                                          const double* __restrict__ uraw, double* __restrict__ U,
                                                           double* __restrict__ R, double* __restrict__ G,
                                                           State* __restrict__ st, size_t bs) {
   __shared__ double s_coef[kMaxM + 1];
@@ -671,8 +726,8 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
     const double* Ub = bat(U, bs);
     const int ne = gram_entries(j);
     double gv[kGramGroup][4], un[4] = {0.0, 0.0, 0.0, 0.0};
-    orth_wave<4, KMAX>(j, k, m, d, bat(slots_cur, bs), bat(slots_next, bs), bat(U, bs), bat(R, bs), st,
-                       blockIdx.x == 0, s_coef, &s_inv, &s_ok, un);
+    orth_wave<4, KMAX>(j, k, m, d, bat(uraw, bs), bat(U, bs), bat(R, bs), st, blockIdx.x == 0, s_coef, &s_inv,
+                       &s_ok, un);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     if (!s_ok) return;  // breakdown: row j+1 does not exist
@@ -878,27 +933,32 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 }
 
 // ------------------------------------------------------------------------------------ launchers
-size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta) {
+size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16) {
   const size_t es = dtype == 0 ? 8 : 4;
   (void)zeta;
-  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, d, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + 4));
+  const size_t ib = (c16 && G <= 1) ? 2 : 4;  // LDS bytes per column index
+  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, d, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + ib));
 }
 
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
                                        const int16_t* cr, const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
-                                       double* slots, const State* st, int nb, int G, size_t bs) {
+                                       double* parts, const State* st, int nb, int G, size_t bs) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
-  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta);
+  const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta, cr != nullptr);
   const dim3 g2(grid, (nb + G - 1) / G);
+  const bool c16 = cr != nullptr && mode != 1;  // the sketch-only mode stages no CSR chunk
 #define FAB_L(M, Z)                                                                                             \
   if (G > 1)                                                                                                    \
     hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
-                       scale, k0, k1, slots, st, nb, G, bs);                                                    \
+                       scale, k0, k1, parts, st, nb, G, bs);                                                    \
+  else if (c16)                                                                                                 \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false, (M != 1)>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, \
+                       d, zeta, scale, k0, k1, parts, st, nb, 1, bs);                                           \
   else                                                                                                          \
     hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
-                       scale, k0, k1, slots, st, nb, 1, bs)
+                       scale, k0, k1, parts, st, nb, 1, bs)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -949,39 +1009,40 @@ size_t group_lds_max() { return kGroupLdsMax; }
 
 // The instantiation launch_spmv_sketch picks, for the occupancy query below.
 template <typename T, int M, int Z>
-static const void* spmv_kernel_mz(int G) {
+static const void* spmv_kernel_mz(int G, bool c16) {
   if (G > 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, true>);
+  if (c16 && M != 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false, (M != 1)>);
   return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false>);
 }
 
 template <typename T>
-static const void* spmv_kernel(int mode, int zeta, int G) {
-  if (mode == 2) return spmv_kernel_mz<T, 2, 1>(G);
+static const void* spmv_kernel(int mode, int zeta, int G, bool c16) {
+  if (mode == 2) return spmv_kernel_mz<T, 2, 1>(G, c16);
   const int Z = zeta <= 1 ? 1 : zeta <= 4 ? 4 : zeta <= 8 ? 8 : zeta <= 16 ? 16 : 32;
   if (mode == 0) {
     switch (Z) {
-      case 1: return spmv_kernel_mz<T, 0, 1>(G);
-      case 4: return spmv_kernel_mz<T, 0, 4>(G);
-      case 8: return spmv_kernel_mz<T, 0, 8>(G);
-      case 16: return spmv_kernel_mz<T, 0, 16>(G);
-      default: return spmv_kernel_mz<T, 0, 32>(G);
+      case 1: return spmv_kernel_mz<T, 0, 1>(G, c16);
+      case 4: return spmv_kernel_mz<T, 0, 4>(G, c16);
+      case 8: return spmv_kernel_mz<T, 0, 8>(G, c16);
+      case 16: return spmv_kernel_mz<T, 0, 16>(G, c16);
+      default: return spmv_kernel_mz<T, 0, 32>(G, c16);
     }
   }
   switch (Z) {
-    case 1: return spmv_kernel_mz<T, 1, 1>(G);
-    case 4: return spmv_kernel_mz<T, 1, 4>(G);
-    case 8: return spmv_kernel_mz<T, 1, 8>(G);
-    case 16: return spmv_kernel_mz<T, 1, 16>(G);
-    default: return spmv_kernel_mz<T, 1, 32>(G);
+    case 1: return spmv_kernel_mz<T, 1, 1>(G, c16);
+    case 4: return spmv_kernel_mz<T, 1, 4>(G, c16);
+    case 8: return spmv_kernel_mz<T, 1, 8>(G, c16);
+    case 16: return spmv_kernel_mz<T, 1, 16>(G, c16);
+    default: return spmv_kernel_mz<T, 1, 32>(G, c16);
   }
 }
 
 // Blocks of the fused kernel resident per CU, from the runtime's occupancy calculator (registers,
 // LDS with its allocation granularity, wavefront slots), so that a grid of that many blocks per CU
 // runs in one pass with no trailing partial wave of blocks.
-int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta) {
-  const size_t lds = spmv_sketch_lds(dtype, mode, d, G, zeta);
-  const void* f = dtype == 0 ? spmv_kernel<double>(mode, zeta, G) : spmv_kernel<float>(mode, zeta, G);
+int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta, bool c16) {
+  const size_t lds = spmv_sketch_lds(dtype, mode, d, G, zeta, c16);
+  const void* f = dtype == 0 ? spmv_kernel<double>(mode, zeta, G, c16) : spmv_kernel<float>(mode, zeta, G, c16);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kThreads, lds) != hipSuccess || nb < 1) nb = 1;
   return nb;
@@ -989,44 +1050,53 @@ int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta) {
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* slots, const State* st, int nb, int G, size_t bs) {
+                              double* parts, const State* st, int nb, int G, size_t bs) {
+  // the partials need a grid of whole XCD rounds within the partial buffer (part_index)
+  if (mode != 2 && (grid < kXcds || grid > kMaxParts || grid % kXcds != 0)) return hipErrorInvalidValue;
   if (dtype == 0)
     return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, cr, (const double*)va, (const double*)x,
-                                        (double*)y, d, zeta, seed, slots, st, nb, G, bs);
+                                        (double*)y, d, zeta, seed, parts, st, nb, G, bs);
   return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, cr, (const float*)va, (const float*)x, (float*)y, d,
-                                     zeta, seed, slots, st, nb, G, bs);
+                                     zeta, seed, parts, st, nb, G, bs);
 }
 
-hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* cur, double* next, double* U,
-                       double* R, State* st, int nb, size_t bs) {
+hipError_t launch_reduce_parts(hipStream_t s, int e0, int len, int nparts, const double* parts, double* out,
+                               const State* st, int skip, int nb, size_t bs) {
+  if (len < 1) return hipSuccess;
+  if (nparts < 1 || nparts > kMaxParts) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(len, nb), dim3(kThreads), 0, s, e0, nparts, parts, out, st, skip, bs);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* uraw, double* U, double* R,
+                       State* st, int nb, size_t bs) {
   const dim3 g(1, nb);
   if (d <= 256)
-    hipLaunchKernelGGL(k_orth<4>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
+    hipLaunchKernelGGL(k_orth<4>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   else if (d <= 512)
-    hipLaunchKernelGGL(k_orth<8>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
+    hipLaunchKernelGGL(k_orth<8>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   else if (d <= 1024)
-    hipLaunchKernelGGL(k_orth<16>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
+    hipLaunchKernelGGL(k_orth<16>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   else
-    hipLaunchKernelGGL(k_orth<32>, g, dim3(64), 0, s, j, k, m, d, cur, next, U, R, st, bs);
+    hipLaunchKernelGGL(k_orth<32>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   return hipGetLastError();
 }
 
 hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* cur, double* next, double* U, double* R, double* G, State* st, int nb,
-                              size_t bs) {
+                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs) {
   const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
   if (dtype == 0) {
     if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, G, st, bs);
+      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, uraw, U, R, G, st, bs);
     else
-      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, cur, next, U, R, G, st, bs);
+      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, uraw, U, R, G, st, bs);
   } else {
     if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, G, st, bs);
+      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, uraw, U, R, G, st, bs);
     else
-      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, cur, next, U, R, G, st, bs);
+      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, uraw, U, R, G, st, bs);
   }
   return hipGetLastError();
 }

@@ -449,6 +449,31 @@ def test_repeated_solves_are_consistent(fab, ctx):
         assert _rel(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-13
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_solves_are_bitwise_reproducible(fab, ctx, dtype):
+    """Every sum over blocks is formed in a fixed order, so a solve repeated on fresh buffers gives
+    the same bits and the same cycle count.  The case is the one most sensitive to rounding order:
+    z^(-1/2) at condition number 2.6e4 with d = 4m, whose increments swing by orders of magnitude
+    from cycle to cycle (a last-bit change early on would change the path and the cycle count)."""
+    N = 16
+    lmin0 = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2
+    lmax = 12 * (N + 1) ** 2
+    shift = lmax / 2.6e4 - lmin0
+    A = wl.shifted_laplacian_3d(N, shift)
+    op = _op(fab, ctx, A, dtype)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 0), dtype=dtype, device="cuda")
+    kw = dict(m=30, k=2, d=120, zeta=8, seed=1, tol=1e-8, spec=(lmin0 + shift, lmax + shift), max_cycles=300)
+    runs = []
+    for _ in range(3):
+        work = torch.empty(fab.workspace_size(op, fab.Params(**kw)), dtype=torch.uint8, device="cuda")
+        x, info = fab.solve(op, b, "invsqrt", work=work, **kw)
+        runs.append((x.clone(), info))
+    for x, info in runs[1:]:
+        assert info["cycles"] == runs[0][1]["cycles"] and info["status"] == runs[0][1]["status"]
+        assert torch.equal(x, runs[0][0])
+    assert runs[0][1]["cycles"] > 30, runs[0][1]  # the sensitive regime was exercised
+
+
 # --------------------------------------------------------------- full-size workload (bench shape)
 def test_convdiff_128_full_size(fab, ctx):
     """3-D convection-diffusion, 128^3 (n = 2.1M), Pe 50, exp(-1e-4 A) b, m=50, k=4, d=200, zeta=8:
@@ -512,15 +537,6 @@ def _laplacian_3d_interval(N, shift):
 
 
 FP32_TOL = 2e-6   # FP32 values and basis (FP64 row sums, bins and cycle end; x in FP64), small grids
-# 256^3, condition number 2.6e4, d = 120, tol 1e-6: the stopping test reads successive increments,
-# which trail the error by the contraction factor of the slow modes (FP64 at these settings:
-# 3.0-3.6e-6).  In FP32 the rounding of the basis seeds the transients that the sketch's distortion
-# causes at this sketch size, and the run-to-run order of the FP64 atomic sums decides the path:
-# 30 to 105 cycles and 8e-7 .. 3.0e-5 over twelve runs, and one run that stopped inside a dip after
-# 24 cycles at 1.5e-4.  Bar: the scale of FP32 rounding carried through the operator's
-# conditioning, cond(A) eps_32 = 2.6e4 * 6e-8 = 1.6e-3 (tol sits at the FP32 floor here, so the
-# stopping test meets it only by chance).
-FP32_FULL_TOL = 1.6e-3
 # Batched anisotropic FP32 workload (1024^2, t up to 1e-3, t lambda_max ~ 4e3, ~30 cycles): FP32
 # rounding of each cycle's basis sets a floor that a tighter tol does not move (measured, worst of
 # sampled members: 3e-7 at t = 1e-5 rising to 2.5e-5 at t = 1e-3, at tol 1e-6 and 1e-7 alike; FP64
@@ -557,20 +573,37 @@ def test_fp32_invsqrt_shifted_laplacian(fab, ctx):
     assert _rel(x[:, 0].cpu().numpy(), ref) <= FP32_TOL
 
 
-def test_fp32_invsqrt_256_full_size(fab, ctx):
-    """(A + I)^(-1/2) b on the 256^3 Laplacian (n = 16.8M, 1 GB of CSR), FP32 loop with m=30, k=2,
-    d=120, zeta=8, tol 1e-6: the whole vector against the sine-basis closed form."""
+# The 256^3 z^(-1/2) workload (n = 16.8M, 1 GB of CSR, condition number 2.6e4), m = 30, k = 2.
+# With the sketch size of the workload, d = 120 = 4m, the sketch's distortion makes the restart's
+# increments swing by 10x from cycle to cycle while the error falls by ~5% a cycle (the convergence
+# spikes the paper reports for small sketches), so no estimate built from the increments tracks the
+# error there: at tol 1e-6 the tail estimate stops after 34 cycles (FP64) and 36 (FP32) with errors
+# 3.05e-6 and 1.1e-5 (the plain successive difference stops at the same cycles).  Every sum is formed
+# in a fixed order, so these numbers repeat bit for bit; the bars are them plus 30%.  With d = 480 =
+# 16m (the paper's stable regime) the increments contract steadily and the estimate meets tol: the
+# bars there are 2 tol.  The reference is the closed form of b rounded to the value type.
+@pytest.mark.parametrize("dtype,d,tol,bar", [(torch.float64, 120, 1e-6, 4e-6), (torch.float32, 120, 1e-6, 1.5e-5),
+                                             (torch.float64, 480, 1e-8, 2e-8), (torch.float32, 480, 1e-6, 2e-6)])
+def test_invsqrt_256_full_size(fab, ctx, dtype, d, tol, bar):
+    """(A + I)^(-1/2) b on the 256^3 Laplacian (FP64, or FP32 values and basis), m=30, k=2, zeta=8:
+    the whole vector against the sine-basis closed form; the solve repeated gives the same bits."""
     N = 256
     A = wl.shifted_laplacian_3d(N, 1.0)
-    op = _op(fab, ctx, A, torch.float32)
+    op = _op(fab, ctx, A, dtype)
     b = wl.gaussian_vector(A.n, 0)
-    x, info = fab.solve(op, torch.as_tensor(b, dtype=torch.float32, device="cuda"), "invsqrt", m=30, k=2, d=120,
-                        zeta=8, seed=1, tol=1e-6, spec=_laplacian_3d_interval(N, 1.0), max_cycles=300)
-    ref = exact.sine_fab("invsqrt", b, N, [1, 1, 1], 1.0)
-    err = _rel(x[:, 0].cpu().numpy(), ref)
-    print(f"fp32 invsqrt 256^3: {info} rel err {err:.3e}", flush=True)
+    bt = torch.as_tensor(b, dtype=dtype, device="cuda")
+    kw = dict(m=30, k=2, d=d, zeta=8, seed=1, tol=tol, spec=_laplacian_3d_interval(N, 1.0), max_cycles=300)
+    x, info = fab.solve(op, bt, "invsqrt", **kw)
+    x = x[:, 0].clone()
+    ref = exact.sine_fab("invsqrt", bt.double().cpu().numpy(), N, [1, 1, 1], 1.0)
+    err = _rel(x.cpu().numpy(), ref)
+    print(f"invsqrt 256^3 {dtype} d={d} tol={tol:.0e}: cycles {info['cycles']} err_est {info['err_est']:.2e} "
+          f"rel err {err:.3e}", flush=True)
     assert info["status"] == "FAB_OK", info
-    assert err <= FP32_FULL_TOL
+    assert err <= bar
+    if d == 120:
+        x2, info2 = fab.solve(op, bt, "invsqrt", **kw)
+        assert info2["cycles"] == info["cycles"] and torch.equal(x2[:, 0], x)
 
 
 # ---------------------------------------------------- adjoint and differentiation (A^T, autograd)
@@ -972,7 +1005,7 @@ def test_full_window_with_quadrature_restart(fab, ctx):
     A = wl.convdiff_3d(N, 20.0)
     op = _op(fab, ctx, A)
     b = wl.gaussian_vector(A.n, 8)
-    t = 3e-3
+    t = 1e-2
     x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, m=16, k=16, d=64, zeta=4, seed=3,
                         tol=1e-10, max_cycles=40)
     S = sketch.sketch_matrix(A.n, 64, 4, seed=3)
@@ -980,3 +1013,77 @@ def test_full_window_with_quadrature_restart(fab, ctx):
     assert info["status"] == "FAB_OK" and info["cycles"] == io.cycles >= 3
     assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-10
     assert info["kappa_T"] == pytest.approx(1.0, abs=1e-9)
+
+
+# ------------------------------------------------ phi_1 (eq. conv_diff_sol3) and cos(t sqrt) (eq. drum_sol)
+def _laplacian_2d_interval(N):
+    return 8 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2, 8 * (N + 1) ** 2
+
+
+@pytest.mark.parametrize("fun,ts", [("phi1", [1e-3]), ("phi1", [1e-4, 1e-3, 2e-2]), ("cos_sqrt", [0.02]),
+                                    ("cos_sqrt", [0.005, 0.02, 0.2])])
+def test_phi1_and_cos_sqrt_closed_form_and_twin(fab, ctx, fun, ts):
+    """phi_1(-t A) b and cos(t sqrt A) b on the 2-D Laplacian, N = 48 (n = 2304: nine tiles and a
+    ragged tail), several time points in one solve: each column against the sine closed form at
+    1e-10, and against the oracle twin with the same S (the same cycle count, results to 1e-10)."""
+    N = 48
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 13)
+    spec = _laplacian_2d_interval(N)
+    kw = dict(m=20, k=2, tol=1e-11, max_cycles=200)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), fun, t=ts, d=80, zeta=8, seed=1, spec=spec, **kw)
+    assert info["status"] == "FAB_OK", info
+    assert info["quad_rule_error"] <= 1e-11
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    for i, t in enumerate(ts):
+        ref = exact.sine_fab(fun, b, N, [1, 1], 0.0, t)
+        assert _rel(x[:, i].cpu().numpy(), ref) <= 1e-10, t
+    if len(ts) == 1:
+        xo, io = krylov.restart_solve(A.to_scipy(), b, fun, ts[0], S=S, spec=spec, **kw)
+        assert info["cycles"] == io.cycles
+        assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-10
+
+
+def test_phi1_nonsymmetric_vs_dense(fab, ctx):
+    """phi_1(-t A) b on the non-symmetric 3-D convection-diffusion operator (Pe 20, N = 12): against
+    the oracle's dense phi_1 of the assembled matrix (augmented exponential)."""
+    N, t = 12, 2e-3
+    A = wl.convdiff_3d(N, 20.0)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 14)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "phi1", t=t, m=24, k=4, d=96, zeta=8, seed=2,
+                        tol=1e-11, max_cycles=100)
+    ref = exact.dense_fab("phi1", A.to_scipy().toarray(), b, t)
+    assert info["status"] == "FAB_OK", info
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-10
+
+
+def test_cos_sqrt_coarse_rule_is_flagged_and_bad_interval_rejected(fab, ctx):
+    """A 16-node ellipse for 60 oscillations over the interval cannot represent cos(t sqrt z): the
+    solve warns (FAB_W_QUADRATURE) instead of claiming the tolerance; an empty interval is invalid."""
+    N = 24
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 15), device="cuda")
+    lo, hi = _laplacian_2d_interval(N)
+    x, info = fab.solve(op, b, "cos_sqrt", t=60 / np.sqrt(hi), spec=(lo, hi), n_quad=16, tol=1e-8, check=False)
+    assert info["status"] == "FAB_W_QUADRATURE", info
+    assert info["quad_rule_error"] > 1e-6
+    _, bad = fab.solve(op, b, "cos_sqrt", t=0.1, spec=(hi, hi), check=False)
+    assert bad["code"] == -1
+
+
+def test_phi1_fp32_loop(fab, ctx):
+    """FP32 values and basis with phi_1 on the anisotropic 2-D operator, N = 96: FP32-level error."""
+    N = 96
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A, torch.float32)
+    b = wl.gaussian_vector(A.n, 16)
+    ts = [1e-4, 1e-3]
+    x, info = fab.solve(op, torch.as_tensor(b, dtype=torch.float32, device="cuda"), "phi1", t=ts, m=20, k=2,
+                        d=80, zeta=8, seed=1, tol=1e-6, max_cycles=100)
+    assert info["status"] == "FAB_OK", info
+    bb = b.astype(np.float32).astype(np.float64)
+    for i, t in enumerate(ts):
+        assert _rel(x[:, i].cpu().numpy(), exact.sine_fab("phi1", bb, N, [1.0, 0.01], 0.0, t=t)) <= FP32_TOL, t
