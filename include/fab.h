@@ -240,6 +240,20 @@ fab_status fab_spmv(fab_ctx* ctx, const fab_op* A, const void* x, void* y, void*
 fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed,
                             int32_t dtype, const void* x, double* Sx, void* work, size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fab_sketch_apply without
+ * a workspace argument.  Sx[d] (FP64) = S x, with the same kernels, grid and
+ * bits as fab_sketch_apply; the per-block partial sketches live in a static
+ * device array of the library (4 MiB per GPU, held until the process ends), so
+ * the call allocates nothing.  x (n, dtype) and Sx are the caller's device
+ * buffers.  Limit: d <= 256 (FAB_E_UNSUPPORTED above it).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (several contexts or
+ * host threads on the same device) race and must be serialised by the caller.
+ * Errors: FAB_E_INVALID (null pointers, n, zeta or dtype out of range),
+ * FAB_E_UNSUPPORTED (d > 256), FAB_E_HIP. */
+fab_status fab_sketch_apply_noalloc(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed,
+                                    int32_t dtype, const void* x, double* Sx);
+
 /* The sketch specification itself (eq. sparse_sign_sketch: zeta distinct rows
  * per column, signs +-1, scale 1/sqrt(zeta) not included): for columns
  * col0 .. col0+count-1, the rows (int32, count x zeta, row-major) and signs

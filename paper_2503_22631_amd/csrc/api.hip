@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -87,6 +88,7 @@ struct GraphKey {
 
 struct fab_ctx {
   int device = 0;
+  double* scratch = nullptr;  // this device's copy of `scratch` (fab_sketch_apply_noalloc)
   hipStream_t user = nullptr;
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
@@ -276,6 +278,33 @@ static fab_status hip_fail(hipError_t e, const char* expr, int line) {
     hipError_t e_ = (expr);                                        \
     if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__);    \
   } while (0)
+
+// ---------------------------------------------------------- allocation-free sketch application
+// For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+// harnesses that forbid hipMalloc): fab_sketch_apply_noalloc keeps the product kernel's per-block
+// partial sketches in `scratch`, a file-scope device array of kMaxParts x kScratchMaxD FP64 (4 MiB),
+// instead of a caller's workspace.  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names only a stand-in for the symbol: its device address on
+// a device comes from hipGetSymbolAddress, taken once per device, with that device current, when
+// the first context on it is created (scratch_address), and kept in every context of the device.
+constexpr int kScratchMaxD = 256;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[(size_t)kMaxParts * kScratchMaxD];
+
+static hipError_t scratch_address(int device, double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 // Timing events are recorded only on cycles enqueued directly on the stream (timing mode does
 // not capture a graph: an event recorded during capture becomes a graph dependency and never
@@ -469,6 +498,13 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
   if (configure_cycle_kernels() != hipSuccess || configure_step_kernels() != hipSuccess) {
     delete c;
     return FAB_E_HIP;
+  }
+  {
+    const hipError_t e = scratch_address(c->device, &c->scratch);  // the device is current here
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+    }
   }
   if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
@@ -1163,6 +1199,26 @@ fab_status fab_sketch_apply(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, ui
   FAB_TRY(launch_spmv_sketch(s, dtype, 1, grid, (int)n, nullptr, nullptr, nullptr, nullptr, x, nullptr, d, zeta, seed,
                              parts, nullptr, 1, 1, 0));
   FAB_TRY(launch_reduce_parts(s, 0, d, grid, parts, Sx, nullptr, -1, 1, 0));
+  FAB_TRY(hipStreamSynchronize(s));
+  return FAB_OK;
+}
+
+fab_status fab_sketch_apply_noalloc(fab_ctx* ctx, int64_t n, int32_t d, int32_t zeta, uint64_t seed, int32_t dtype,
+                                    const void* x, double* Sx) {
+  if (!ctx || !x || !Sx || n <= 0 || n >= ((int64_t)1 << 31) || d < 1 || zeta < 1 || zeta > 32 || zeta > d ||
+      (dtype != FAB_F64 && dtype != FAB_F32))
+    return FAB_E_INVALID;
+  if (d > kScratchMaxD) return FAB_E_UNSUPPORTED;  // beyond the static scratch
+  if (!ctx->scratch) return FAB_E_HIP;
+  hipStream_t s = ctx->work;
+  FAB_TRY(hipEventRecord(ctx->ev, ctx->user));
+  FAB_TRY(hipStreamWaitEvent(s, ctx->ev, 0));
+  // the same kernels and grid as fab_sketch_apply; every block overwrites its partial (rows
+  // [0, d) x the grid), so nothing in scratch needs clearing
+  const int grid = spmv_grid(ctx, n, dtype, 1, d, 1, zeta);
+  FAB_TRY(launch_spmv_sketch(s, dtype, 1, grid, (int)n, nullptr, nullptr, nullptr, nullptr, x, nullptr, d, zeta, seed,
+                             ctx->scratch, nullptr, 1, 1, 0));
+  FAB_TRY(launch_reduce_parts(s, 0, d, grid, ctx->scratch, Sx, nullptr, -1, 1, 0));
   FAB_TRY(hipStreamSynchronize(s));
   return FAB_OK;
 }
