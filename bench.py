@@ -51,6 +51,12 @@ def algorithmic_bytes(n: int, nnz: int, k: int, es: int = 8, ib: int = 4):
     return spmv, step
 
 
+def update_bytes(n: int, m: int, k: int, es: int = 8) -> float:
+    """Average bytes per window update of a full cycle: step j reads z and its min(k, j+1) window
+    columns and writes w_{j+1}."""
+    return sum((2 + min(k, j + 1)) * es * n for j in range(m)) / m
+
+
 def kernel_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SRC:
@@ -137,7 +143,8 @@ def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=(), x_cpu_plain=None):
              "cpu_plain_rel_err": rel(x_cpu_plain) if x_cpu_plain is not None else None})
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str):
+def summarize_pmc(fetch_dir: str, write_dir: str, out_json: str = TRAFFIC_FILE, workload: str = None,
+                  kernel_label: str = "k_spmv_sketch<double, SpMV+sketch, zeta<=8>"):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel, scaled by what the
     same counters read for a device copy of known size; writes the traffic record under profiles/."""
     def load(d, counter):
@@ -167,22 +174,23 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
     f_scale = (COPY_BYTES / kib) / f_c if f_c else 1.0
     w_scale = (COPY_BYTES / kib) / w_c if w_c else 1.0
     traffic = (f_k * f_scale + w_k * w_scale) * kib if (f_k is not None and w_k is not None) else None
-    rec = {"kernel": "k_spmv_sketch<double, SpMV+sketch, zeta<=8>", "workload": WORKLOAD["workload"],
+    rec = {"kernel": kernel_label, "workload": workload or WORKLOAD["workload"],
            "kernel_source_sha": kernel_sha(), "dispatches": [nf, nw],
            "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
            "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": COPY_BYTES,
            "fetch_scale": f_scale, "write_scale": w_scale, "traffic_bytes_per_launch": traffic,
            "unscaled_bytes_per_launch": (f_k + w_k) * kib if (f_k is not None and w_k is not None) else None}
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    os.makedirs(os.path.dirname(out_json), exist_ok=True)
+    json.dump(rec, open(out_json, "w"), indent=1)
     print(json.dumps(rec))
 
 
-def summarize_trace(trace_dir: str, out_md: str, command: str):
+def summarize_trace(trace_dir: str, out_md: str, command: str, workload: str = None):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = list(csv.DictReader(open(f)))
-    lines = [f"# rocprofv3 kernel statistics: {WORKLOAD['workload']}", "", "Command (from the repository root, on the MI355X machine):",
+    lines = [f"# rocprofv3 kernel statistics: {workload or WORKLOAD['workload']}", "",
+             "Command (from the repository root, on the MI355X machine):",
              "", "```", command, "```", "",
              "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in rows:
@@ -206,6 +214,39 @@ def _timed(fn, reps=1):
     return (time.perf_counter() - t0) / reps, r
 
 
+def profile_256(dtype_name: str):
+    """A short run for rocprofv3: z^(-1/2) of the shifted 3-D Laplacian at 256^3 (n = 16.8M), m = 30,
+    k = 2, d = 120, zeta = 8, FP32 or FP64 values and basis, two solves of three cycles each (90
+    launches of the fused product + sketch), then a device copy of COPY_BYTES for counter
+    calibration."""
+    import numpy as np
+    import torch
+
+    import paper_2503_22631_amd as fab
+    import workloads as wl
+
+    N = 256
+    dt = torch.float32 if dtype_name == "f32" else torch.float64
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    b = wl.gaussian_vector(A.n, 0)
+    lo = 3 * 4 * (N + 1) ** 2 * np.sin(np.pi / (2 * (N + 1))) ** 2 + 1.0
+    ctx = fab.Context()
+    op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=dt)
+    bt = torch.as_tensor(b, dtype=dt, device="cuda")
+    for _ in range(2):
+        fab.solve(op, bt, "invsqrt", m=30, k=2, d=120, zeta=8, seed=1, tol=1e-6, spec=(lo, 12 * (N + 1) ** 2 + 1.0),
+                  max_cycles=3, check=False)
+    torch.cuda.synchronize()
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_256": dtype_name, "n": A.n, "nnz": A.nnz,
+                      "spmv_bytes_per_launch": algorithmic_bytes(A.n, A.nnz, 2, es=4 if dtype_name == "f32" else 8,
+                                                                 ib=op.index_bytes())[0]}))
+    return 0
+
+
 def extra_legs(fab, ctx):
     """The other workloads of the method on the same GPU: the paper's restart-rand (k = m, growing
     restart) on the headline workload; z^(-1/2) with FP32 against FP64 values
@@ -221,6 +262,21 @@ def extra_legs(fab, ctx):
 
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     out, checks = {}, []
+    # --- the small workload: 2-D Laplacian 64^2 (n = 4096), exp(-1e-3 A) b, m=20, k=2, d=80, tol 1e-10;
+    # the whole working set (~0.7 MB) stays in the caches, so this is the latency of a solve
+    Nl = 64
+    A = wl.laplacian_2d(Nl)
+    b = wl.gaussian_vector(A.n, 0)
+    op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals)
+    bt = torch.as_tensor(b, device="cuda")
+    sec, (x, info) = _timed(lambda: fab.solve(op, bt, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10),
+                            reps=50)
+    leg = {"workload": "laplacian_2d_N64, exp(-1e-3 A) b, m=20, k=2, d=80, zeta=8, tol 1e-10, f64",
+           "solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "cycles": info["cycles"], "status": info["status"]}
+    xh = x[:, 0].cpu().numpy()
+    checks.append((leg, "rel_err", lambda ex, xh=xh, b=b: rel(xh, ex.sine_fab("exp", b, 64, [1, 1], 0.0, t=1e-3))))
+    out["laplacian_64"] = leg
+    del op, bt, x, A
     # --- the paper's restart-rand on the headline workload: full sketched Gram-Schmidt (k = m) and the
     # restart as Algorithm 2 states it (exp of the growing block matrix), against the default (k = 4,
     # quadrature restart) timed above
@@ -239,6 +295,29 @@ def extra_legs(fab, ctx):
     checks.append((leg, "rel_err", lambda ex, xh=xh, b=b, w=w: rel(
         xh, ex.kron_exp_fab(b, ex.problem_factors("convdiff_3d", w["N"], peclet=w["peclet"])[0], w["t"]))))
     out["restart_rand_128"] = leg
+    # --- the paper's unrestarted randomized Arnoldi at its sketch sizes: one cycle, k = m = 60 (the
+    # whole basis in the Gram-Schmidt and the update), d = 1200 and 3600, on the same operator; the
+    # update reads up to 61 basis columns per step (the tall-skinny product of Section 2.2)
+    for d_un in (1200, 3600):
+        kw = dict(m=60, k=60, d=d_un, zeta=w["zeta"], seed=w["sketch_seed"], tol=1e-12, max_cycles=1)
+        sec, (x, info) = _timed(lambda kw=kw: fab.solve(op, bt, "exp", t=w["t"], check=False, **kw), reps=3)
+        fab.timing_enable(ctx, True)
+        fab.solve(op, bt, "exp", t=w["t"], check=False, **kw)
+        tm = fab.timing_read(ctx)
+        fab.timing_enable(ctx, False)
+        ub = update_bytes(A.n, 60, 60)
+        us = tm["update_ms"] / max(tm["update_launches"], 1) / 1e3
+        sb, _ = algorithmic_bytes(A.n, A.nnz, 60, ib=op.index_bytes())
+        ss = tm["spmv_ms"] / max(tm["spmv_launches"], 1) / 1e3
+        leg = {"workload": f"convdiff_3d_N128_Pe50, one cycle (no restart), m = k = 60, d = {d_un}",
+               "solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "status": info["status"],
+               "update": {"kernel": "k_update<double, 64>", "avg_us": us * 1e6, "bytes_per_launch_avg": ub,
+                          "GB/s": ub / us / 1e9, "frac": ub / us / 1e9 / HBM_PEAK_GBS},
+               "spmv_sketch": {"avg_us": ss * 1e6, "GB/s": sb / ss / 1e9, "frac": sb / ss / 1e9 / HBM_PEAK_GBS}}
+        xh = x[:, 0].cpu().numpy()
+        checks.append((leg, "rel_err", lambda ex, xh=xh, b=b, w=w: rel(
+            xh, ex.kron_exp_fab(b, ex.problem_factors("convdiff_3d", w["N"], peclet=w["peclet"])[0], w["t"]))))
+        out[f"unrestarted_rand_128_d{d_un}"] = leg
     del op, bt, x, A
     torch.cuda.empty_cache()
     # --- z^(-1/2) of the shifted 3-D Laplacian, 256^3 (n = 16.8M), FP32 vs FP64
@@ -291,10 +370,22 @@ def extra_legs(fab, ctx):
     b64 = torch.as_tensor(Bm[:, 0].astype(np.float64), device="cuda")
     sec1, (x1, info1) = _timed(lambda: fab.solve(op64, b64, "exp", t=T, **kw))
     single = [x1[:, i].cpu().numpy() for i in range(len(T))]
+    # the same FP64 single solves at looser tolerances, so the batched FP32 rate can be set against
+    # the FP64 rate at the accuracy the FP32 batch reaches (its error is in rel_err_sampled_max)
+    by_tol = {}
+    for tl in (1e-5, 1e-4):
+        kwl = dict(kw, tol=tl)
+        sec2, (x2, info2) = _timed(lambda kwl=kwl: fab.solve(op64, b64, "exp", t=T, **kwl))
+        s2 = [x2[:, i].cpu().numpy() for i in range(len(T))]
+        by_tol[f"{tl:.0e}"] = {"results_per_s": len(T) / sec2, "cycles": info2["cycles"]}
+        checks.append((by_tol[f"{tl:.0e}"], "rel_err_max", lambda ex, N=N, T=T, Bm=Bm, s2=s2: max(
+            rel(s2[i], ex.sine_fab("exp", Bm[:, 0].astype(np.float64), N, [1.0, 0.01], 0.0, t=t))
+            for i, t in enumerate(T))))
     leg = {"workload": "anisotropic_2d_N1024 (1, 0.01), exp, 64 rhs x 8 t in [1e-5, 1e-3]", "n": A.n,
            "results": nb * len(T), "results_per_s": nb * len(T) / sec, "seconds": sec,
            "cycles_max": max(i["cycles"] for i in infos), "group": infos[0]["group"], "values": "f32",
-           "single_f64": {"results_per_s": len(T) / sec1, "cycles": info1["cycles"]},
+           "single_f64": {"results_per_s": len(T) / sec1, "cycles": info1["cycles"], "tol": kw["tol"]},
+           "single_f64_looser_tol": by_tol,
            "speedup_vs_single_f64": (nb * len(T) / sec) / (len(T) / sec1)}
     checks.append((leg, "rel_err_sampled_max", lambda ex, N=N, T=T, Bm=Bm, samples=samples: max(
         rel(v, ex.sine_fab("exp", Bm[:, r].astype(np.float64), N, [1.0, 0.01], 0.0, t=T[i])) for (r, i), v in samples.items())))
@@ -362,8 +453,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (FP32, batched, ragged, adjoint)")
     ap.add_argument("--profile", action="store_true",
                     help="few solves, no CPU leg, plus a device copy of known size for counter calibration")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_MD", "COMMAND"))
+    ap.add_argument("--profile-256", choices=("f32", "f64"),
+                    help="a short 256^3 z^(-1/2) run (FP32 or FP64 values and basis) for rocprofv3")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="FETCH_DIR WRITE_DIR [OUT_JSON WORKLOAD KERNEL_LABEL]")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="ARG", help="TRACE_DIR OUT_MD COMMAND [WORKLOAD]")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -371,6 +465,8 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return 0
+    if args.profile_256:
+        return profile_256(args.profile_256)
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is documented, not built).", file=sys.stderr)
@@ -424,6 +520,8 @@ def main():
     spmv_avg_s = tm["spmv_ms"] / max(tm["spmv_launches"], 1) / 1e3
     achieved = spmv_bytes / spmv_avg_s / 1e9
     loop_gbs = step_bytes * tm["loop_steps"] / (tm["loop_ms"] / 1e3) / 1e9 if tm["loop_ms"] > 0 else None
+    upd_b = update_bytes(A.n, w["m"], w["k"])
+    upd_s = tm["update_ms"] / max(tm["update_launches"], 1) / 1e3
 
     comparison, x_plain = None, None
     if not args.no_compare:
@@ -464,7 +562,12 @@ def main():
                                   f"region ({args.steps} solves, {1e3 * (i1 - i0) / args.steps:.2f} ms/solve)"},
            "loop": {"GB/s": loop_gbs, "frac": (loop_gbs / HBM_PEAK_GBS) if loop_gbs else None,
                     "bytes_per_step": step_bytes, "steps_timed": tm["loop_steps"],
-                    "avg_step_us": 1e3 * tm["loop_ms"] / max(tm["loop_steps"], 1)},
+                    "avg_step_us": 1e3 * tm["loop_ms"] / max(tm["loop_steps"], 1),
+                    "update": {"kernel": "k_orth_update (sketch-space Gram-Schmidt + window update)",
+                               "avg_us": upd_s * 1e6, "bytes_per_launch_avg": upd_b,
+                               "GB/s": upd_b / upd_s / 1e9 if upd_s > 0 else None,
+                               "frac": upd_b / upd_s / 1e9 / HBM_PEAK_GBS if upd_s > 0 else None,
+                               "launches_timed": tm["update_launches"]}},
            "comparison": comparison}
     checks = []
     if not args.no_extra:

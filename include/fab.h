@@ -57,7 +57,7 @@ typedef enum {
   FAB_E_UNSUPPORTED = -2,   /* valid but not supported by this build          */
   FAB_E_HIP = -3,           /* a HIP runtime call failed                      */
   FAB_E_NONFINITE = -4,     /* NaN/Inf met in the iteration (A or b)          */
-  FAB_E_DIVERGED = -5,      /* an increment exceeded 1e8 ||x||                */
+  FAB_E_DIVERGED = -5,      /* an increment exceeded 1e8 ||x|| (see fab_divergence_limit) */
   FAB_E_WORKSPACE = -6      /* work_bytes smaller than fab_workspace_size     */
 } fab_status;
 
@@ -82,7 +82,7 @@ typedef enum { FAB_SKETCHED = 0, FAB_PLAIN_RESTART = 1, FAB_SKETCHED_GROWING = 2
 typedef struct {
   int32_t m;          /* cycle length (basis size per cycle), 1 <= m <= 64            */
   int32_t k;          /* truncation window of the Gram-Schmidt, 1 <= k <= m          */
-  int32_t d;          /* sketch rows, m+1 <= d <= 2048                                */
+  int32_t d;          /* sketch rows, m+1 <= d <= 4096                                */
   int32_t zeta;       /* nonzeros per sketch column, 1 <= zeta <= min(32, d)          */
   uint64_t seed;      /* defines S (Philox4x32-10 counter-based spec, see fab_sketch_table) */
   double tol;         /* relative update tolerance, >= 0                              */
@@ -272,6 +272,12 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
                            void* W, double* U, double* R, double* T, double* Rt, double* h_scal,
                            void* work, size_t work_bytes);
 
+/* Test hook for the divergence status: a solve is abandoned with FAB_E_DIVERGED when a cycle's
+ * relative increment max_t ||y_t|| / ||x_t|| exceeds limit (default 1e8).  A small limit forces the
+ * status on any problem (the first cycle's increment is x itself, relative increment 1).  The limit
+ * applies to later calls on ctx.  Errors: FAB_E_INVALID (ctx NULL, limit not > 0). */
+fab_status fab_divergence_limit(fab_ctx* ctx, double limit);
+
 /* Members per block of the batched product + sketch kernel: 1, or 16 (the MFMA sketch
  * path); 0 (the default) times both on the first batched solve of each operator and batch shape
  * and keeps the faster.  Test hook: pins either path.  Errors: FAB_E_INVALID. */
@@ -280,13 +286,14 @@ fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
 /* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on
  * the context's stream (instead of replaying the cycle graph: the same kernels with the same
  * launch configuration) and records HIP events around each launch of the fused SpMV + sketch
- * kernel (the product and sketch of Algorithm 1) and around each cycle's m-step loop,
- * accumulating their durations.
+ * kernel (the product and sketch of Algorithm 1), around each window update (Algorithm 1's basis
+ * update: the fused Gram-Schmidt + update kernel, or the update kernel alone), and around each
+ * cycle's m-step loop, accumulating their durations.
  * fab_timing_read returns the totals since the last read and clears them.  Counts only steps
  * that ran (steps after a breakdown are excluded).  Errors: FAB_E_INVALID, FAB_E_HIP. */
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on);
 fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
-                           int64_t* h_loop_steps);
+                           int64_t* h_loop_steps, double* h_update_ms, int64_t* h_update_launches);
 
 /* Not in the paper (the differentiation extension):
  * out[0] = <x, y> for FP64 device vectors of length n, summed in a fixed order

@@ -24,7 +24,7 @@ METHOD = {"sketched": 0, "plain": 1, "growing": 2}
 DTYPE = {torch.float64: 0, torch.float32: 1}
 
 __all__ = ["Context", "CSROperator", "Params", "solve", "solve_batched", "solve_ragged", "workspace_size", "spmv", "sketch_apply",
-           "sketch_table", "cycle_debug", "dot", "batch_group", "ExpAction", "exp_action", "timing_enable", "timing_read",
+           "sketch_table", "cycle_debug", "dot", "batch_group", "divergence_limit", "ExpAction", "exp_action", "timing_enable", "timing_read",
            "FabError", "lib_path"]
 
 
@@ -249,6 +249,11 @@ def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = 
     return [x.t() for x in xs], [_info_dict(infos[i], st) for i in range(nops)]
 
 
+def divergence_limit(ctx: Context, limit: float = 1e8):
+    """Relative increment above which a solve is abandoned with FAB_E_DIVERGED (test hook; default 1e8)."""
+    _lib.check(ctx.lib.fab_divergence_limit(ctx.handle, float(limit)), "fab_divergence_limit", ok=(0,))
+
+
 def batch_group(ctx: Context, G: int = 0):
     """Pin the members per block of the batched kernel (1 or 16); 0 = autotune (default)."""
     _lib.check(ctx.lib.fab_batch_group(ctx.handle, int(G)), "fab_batch_group", ok=(0,))
@@ -259,11 +264,13 @@ def timing_enable(ctx: Context, on: bool = True):
 
 
 def timing_read(ctx: Context) -> dict:
-    """Accumulated HIP-event durations of the SpMV+sketch kernel and of the step loops (ms)."""
+    """Accumulated HIP-event durations of the SpMV+sketch kernel, the window updates and the step loops (ms)."""
     a, b_, c, d = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    e, f = ctypes.c_double(), ctypes.c_int64()
     _lib.check(ctx.lib.fab_timing_read(ctx.handle, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c),
-                                       ctypes.byref(d)), "fab_timing_read", ok=(0,))
-    return {"spmv_ms": a.value, "spmv_launches": b_.value, "loop_ms": c.value, "loop_steps": d.value}
+                                       ctypes.byref(d), ctypes.byref(e), ctypes.byref(f)), "fab_timing_read", ok=(0,))
+    return {"spmv_ms": a.value, "spmv_launches": b_.value, "loop_ms": c.value, "loop_steps": d.value,
+            "update_ms": e.value, "update_launches": f.value}
 
 
 def spmv(op: CSROperator, xv: torch.Tensor) -> torch.Tensor:

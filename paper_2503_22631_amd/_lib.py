@@ -17,7 +17,7 @@ STATUS = {
 EXPORTS = ["fab_create", "fab_destroy", "fab_csr_create", "fab_op_destroy", "fab_op_transpose",
            "fab_op_index_bytes", "fab_op_copy_arrays", "fab_workspace_size", "fab_workspace_size_batched", "fab_solve",
            "fab_solve_batched", "fab_workspace_size_ragged", "fab_solve_ragged", "fab_spmv", "fab_sketch_apply", "fab_sketch_apply_noalloc",
-           "fab_sketch_table", "fab_cycle_debug", "fab_dot", "fab_batch_group", "fab_timing_enable", "fab_timing_read",
+           "fab_sketch_table", "fab_cycle_debug", "fab_dot", "fab_batch_group", "fab_divergence_limit", "fab_timing_enable", "fab_timing_read",
            "fab_status_string", "fab_last_error"]
 
 
@@ -84,8 +84,10 @@ def load():
         "fab_cycle_debug": ([c_void_p, c_void_p, c_void_p, P(fab_params), c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p, P(c_double), c_void_p, c_size_t], c_int32),
         "fab_batch_group": ([c_void_p, c_int32], c_int32),
+        "fab_divergence_limit": ([c_void_p, c_double], c_int32),
         "fab_timing_enable": ([c_void_p, c_int32], c_int32),
-        "fab_timing_read": ([c_void_p, P(c_double), P(c_int64), P(c_double), P(c_int64)], c_int32),
+        "fab_timing_read": ([c_void_p, P(c_double), P(c_int64), P(c_double), P(c_int64), P(c_double), P(c_int64)],
+                            c_int32),
         "fab_status_string": ([c_int32], ctypes.c_char_p),
         "fab_last_error": ([], ctypes.c_char_p),
     }

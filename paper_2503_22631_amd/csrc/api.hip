@@ -55,8 +55,8 @@ hipError_t launch_start(hipStream_t, int d, int m, int plain, const double* sv, 
 hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb, const GrowBuffers* grow);
 hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, int dn, const double* C, void* W,
                        double* x, int64_t ldx, double* parts, const State* st, int nb, size_t bs, const PassSketch& ps);
-hipError_t launch_final(hipStream_t, int nt, int dn, double tol, const double* red, State* st, Report* rep, int nb,
-                        size_t bs);
+hipError_t launch_final(hipStream_t, int nt, int dn, double tol, double div_limit, const double* red, State* st,
+                        Report* rep, int nb, size_t bs);
 hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
                                int8_t* signs);
 hipError_t launch_dot(hipStream_t, int64_t n, const double* x, const double* y, double* part, int max_blocks,
@@ -72,6 +72,10 @@ constexpr int kDotBlocks = 1024;  // partial sums of fab_dot (fixed grid: reprod
 
 using namespace fab;
 
+// Timing events: [2j, 2j+1] around step j's product + sketch, [kTevUpdate + 2j, +1] around its window
+// update (the fused Gram-Schmidt + update, or the update alone), kTevEnd at the end of the step loop.
+constexpr int kTevUpdate = 2 * kMaxM, kTevEnd = 4 * kMaxM;
+
 struct GraphKey {
   uint64_t op;  // fab_op::serial
   const void* work;
@@ -83,6 +87,7 @@ struct GraphKey {
   int timing, nb, G, pad;
   int64_t ldx;
   size_t bs;
+  double div_limit;
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -96,11 +101,12 @@ struct fab_ctx {
   double* d_part = nullptr;  // kDotBlocks partial sums of fab_dot (device)
   double* h_t = nullptr;  // pinned staging for the time points
   int num_cu = 256;
-  // benchmark timing: events around each SpMV+sketch launch (2 per step) and the loop end
+  // benchmark timing: events around each SpMV+sketch launch and each window-update launch (2 each
+  // per step; see kTevUpdate) and at the loop end (kTevEnd)
   bool timing = false;
   std::vector<hipEvent_t> tev;
-  double t_spmv_ms = 0.0, t_loop_ms = 0.0;
-  int64_t t_spmv_n = 0, t_loop_n = 0;
+  double t_spmv_ms = 0.0, t_loop_ms = 0.0, t_upd_ms = 0.0;
+  int64_t t_spmv_n = 0, t_loop_n = 0, t_upd_n = 0;
   struct Cached {
     GraphKey key;
     hipGraphExec_t exec;
@@ -112,6 +118,7 @@ struct fab_ctx {
   };
   std::vector<Tuned> tuned;
   int force_group = 0;  // fab_batch_group: 0 = autotune
+  double div_limit = kDivergedEst;  // fab_divergence_limit: relative increment that abandons a solve
   // ragged solves: branch streams and fork/join events of the captured graph, and its cache
   std::vector<hipStream_t> branch;
   std::vector<hipEvent_t> join;
@@ -392,11 +399,14 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
       if (nb == 1 && d <= 256 && p->k <= 8) {
+        if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
+        if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
       }
+      if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j + 1], s));
     } else {
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
@@ -412,7 +422,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(j + 1), &q.st->inv_rho, q.st, 1, 0));
     }
   }
-  if (tev) FAB_TRY(record_timing_event((*tev)[2 * kMaxM], s));
+  if (tev) FAB_TRY(record_timing_event((*tev)[kTevEnd], s));
   SmallArgs a{};
   a.d = d;
   a.m = m;
@@ -450,7 +460,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       FAB_TRY(launch_reduce_parts(s, 0, d + 2 * nt, g_vec, q.parts, q.red, q.st, 1, nb, bs));
     else
       FAB_TRY(launch_reduce_parts(s, d, 2 * nt, g_vec, q.parts, q.red + d, q.st, 1, nb, bs));
-    FAB_TRY(launch_final(s, nt, d, p->tol, q.red, q.st, rep, nb, bs));
+    FAB_TRY(launch_final(s, nt, d, p->tol, ctx->div_limit, q.red, q.st, rep, nb, bs));
   }
   return FAB_OK;
 }
@@ -798,7 +808,7 @@ struct Track {
 };
 
 // Returns true when this report finishes the member.
-static bool track_report(Track& t, const Report& rr, int c) {
+static bool track_report(Track& t, const Report& rr, int c, double div_limit) {
   t.cycles = c + 1;
   t.matvecs += rr.meff;
   t.est = rr.relupd;
@@ -813,7 +823,7 @@ static bool track_report(Track& t, const Report& rr, int c) {
     t.status = (rr.meff == 0 && c == 0) ? FAB_OK : FAB_OK_BREAKDOWN;  // b = 0: x = 0 exactly
   } else if (rr.converged) {
     t.status = FAB_OK;
-  } else if (!(rr.relupd <= kDivergedEst)) {
+  } else if (!(rr.relupd <= div_limit)) {
     // Transient growth of the increments (est ~ 1) is normal on wide spectra: the restarted
     // iteration of a fixed rule still converges.  Only increments that dwarf the iterate stop it.
     t.status = FAB_E_DIVERGED;
@@ -926,6 +936,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
   key.G = B.G;
   key.ldx = ldx;
   key.bs = bs;
+  key.div_limit = ctx->div_limit;
   hipGraphExec_t exec = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) exec = g.exec;
@@ -960,18 +971,27 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
       if (tr[r].finished) continue;
       const Report rr = ctx->h_rep[r];
       if (!rr.nonfinite) steps = std::max(steps, rr.meff);
-      if (track_report(tr[r], rr, c)) --remaining;
+      if (track_report(tr[r], rr, c, ctx->div_limit)) --remaining;
     }
     if (ctx->timing) {
+      // the update of a step runs when the step does not break down: the steps before the last
+      // always, the last one only for a full cycle (the sketched path; the plain comparator records none)
+      const int upd = (p->method == FAB_PLAIN_RESTART) ? 0 : (steps == p->m ? steps : std::max(steps - 1, 0));
       for (int j = 0; j < steps; ++j) {
         float ms = 0.f;
         FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[2 * j], ctx->tev[2 * j + 1]));
         ctx->t_spmv_ms += ms;
       }
+      for (int j = 0; j < upd; ++j) {
+        float ms = 0.f;
+        FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[kTevUpdate + 2 * j], ctx->tev[kTevUpdate + 2 * j + 1]));
+        ctx->t_upd_ms += ms;
+      }
       ctx->t_spmv_n += steps;
+      ctx->t_upd_n += upd;
       if (steps == p->m) {
         float ms = 0.f;
-        FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[2 * kMaxM]));
+        FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[kTevEnd]));
         ctx->t_loop_ms += ms;
         ctx->t_loop_n += steps;
       }
@@ -1063,9 +1083,11 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   std::vector<uintptr_t> key = {(uintptr_t)nops, (uintptr_t)fun, (uintptr_t)nt, (uintptr_t)work,
                                 (uintptr_t)p->m, (uintptr_t)p->k, (uintptr_t)p->d, (uintptr_t)p->zeta,
                                 (uintptr_t)p->seed, (uintptr_t)rule_nodes(fun, p)};
-  uint64_t tolbits;
+  uint64_t tolbits, divbits;
   std::memcpy(&tolbits, &p->tol, 8);
+  std::memcpy(&divbits, &ctx->div_limit, 8);
   key.push_back((uintptr_t)tolbits);
+  key.push_back((uintptr_t)divbits);
   for (int i = 0; i < nops; ++i) {  // operators by serial: a destroyed operator's address can be reused
     key.push_back((uintptr_t)ops[i]->serial);
     key.push_back((uintptr_t)x[i]);
@@ -1121,7 +1143,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
     }
     FAB_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < nops; ++i)
-      if (!tr[i].finished && track_report(tr[i], ctx->h_rep[i], c)) --remaining;
+      if (!tr[i].finished && track_report(tr[i], ctx->h_rep[i], c, ctx->div_limit)) --remaining;
   }
   return finish_tracks(tr, p, h_info, 1);
 }
@@ -1141,6 +1163,12 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
   return solve_batch(ctx, A, fun, h_t, nt, nb, b, ldb, x, ldx, p, work, work_bytes, h_info);
 }
 
+fab_status fab_divergence_limit(fab_ctx* ctx, double limit) {
+  if (!ctx || !(limit > 0.0)) return FAB_E_INVALID;
+  ctx->div_limit = limit;
+  return FAB_OK;
+}
+
 fab_status fab_batch_group(fab_ctx* ctx, int32_t G) {
   if (!ctx || (G != 0 && G != 1 && G != 16)) return FAB_E_INVALID;
   ctx->force_group = G;
@@ -1150,25 +1178,28 @@ fab_status fab_batch_group(fab_ctx* ctx, int32_t G) {
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on) {
   if (!ctx) return FAB_E_INVALID;
   if (on && ctx->tev.empty()) {
-    ctx->tev.resize(2 * kMaxM + 1, nullptr);
+    ctx->tev.resize(kTevEnd + 1, nullptr);
     for (auto& e : ctx->tev)
       if (hipEventCreate(&e) != hipSuccess) return FAB_E_HIP;
   }
   ctx->timing = on != 0;
-  ctx->t_spmv_ms = ctx->t_loop_ms = 0.0;
-  ctx->t_spmv_n = ctx->t_loop_n = 0;
+  ctx->t_spmv_ms = ctx->t_loop_ms = ctx->t_upd_ms = 0.0;
+  ctx->t_spmv_n = ctx->t_loop_n = ctx->t_upd_n = 0;
   return FAB_OK;
 }
 
 fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
-                           int64_t* h_loop_steps) {
-  if (!ctx || !h_spmv_ms || !h_spmv_launches || !h_loop_ms || !h_loop_steps) return FAB_E_INVALID;
+                           int64_t* h_loop_steps, double* h_update_ms, int64_t* h_update_launches) {
+  if (!ctx || !h_spmv_ms || !h_spmv_launches || !h_loop_ms || !h_loop_steps || !h_update_ms || !h_update_launches)
+    return FAB_E_INVALID;
   *h_spmv_ms = ctx->t_spmv_ms;
   *h_spmv_launches = ctx->t_spmv_n;
   *h_loop_ms = ctx->t_loop_ms;
   *h_loop_steps = ctx->t_loop_n;
-  ctx->t_spmv_ms = ctx->t_loop_ms = 0.0;
-  ctx->t_spmv_n = ctx->t_loop_n = 0;
+  *h_update_ms = ctx->t_upd_ms;
+  *h_update_launches = ctx->t_upd_n;
+  ctx->t_spmv_ms = ctx->t_loop_ms = ctx->t_upd_ms = 0.0;
+  ctx->t_spmv_n = ctx->t_loop_n = ctx->t_upd_n = 0;
   return FAB_OK;
 }
 

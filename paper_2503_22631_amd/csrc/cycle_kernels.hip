@@ -1022,8 +1022,8 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn,
 // increments (a dip inside a transient) do not end the loop.  The solve stops when
 // max_t err_t <= tol.  The raw relative increment max_t ||y_c|| / ||x_c|| is reported too; it
 // decides divergence.  The norms are the fixed-order sums of the pass's partials (red + dn).
-__global__ void k_final(int nt, int dn, double tol, const double* __restrict__ red, State* __restrict__ st,
-                        Report* __restrict__ rep, size_t bs) {
+__global__ void k_final(int nt, int dn, double tol, double div_limit, const double* __restrict__ red,
+                        State* __restrict__ st, Report* __restrict__ rep, size_t bs) {
   if (threadIdx.x != 0) return;
   st = bat(st, bs);
   red = bat(red, bs) + dn;
@@ -1069,7 +1069,7 @@ __global__ void k_final(int nt, int dn, double tol, const double* __restrict__ r
   rep->nonfinite = st->nonfinite;
   rep->converged = st->converged;
   rep->grow_fail = st->grow_fail;
-  st->done = (st->converged || st->brk || st->nonfinite || !(rel <= kDivergedEst)) ? 1 : 0;
+  st->done = (st->converged || st->brk || st->nonfinite || !(rel <= div_limit)) ? 1 : 0;
   rep->done = st->done;
 }
 
@@ -1170,9 +1170,26 @@ hipError_t launch_start(hipStream_t s, int d, int m, int plain, const double* sv
 
 size_t quad_lds(int m) { return (size_t)m * (m + 1) * 8 + 16 + (size_t)m * (m + 1) * sizeof(cplx); }
 
+// The pass's bins (one set of d FP64 per wavefront) reach 128 KB at d = kMaxD.
+template <typename T>
+static hipError_t configure_pass_t() {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_pass<T, 1>), reinterpret_cast<const void*>(&k_pass<T, 2>),
+                       reinterpret_cast<const void*>(&k_pass<T, 4>), reinterpret_cast<const void*>(&k_pass<T, 8>),
+                       reinterpret_cast<const void*>(&k_pass<T, 16>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (kThreads / 64) * kMaxD * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t configure_cycle_kernels() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_quad), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)quad_lds(kMaxM));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_quad),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)quad_lds(kMaxM));
+  if (e == hipSuccess) e = configure_pass_t<double>();
+  if (e == hipSuccess) e = configure_pass_t<float>();
+  return e;
 }
 
 hipError_t launch_small_grow(hipStream_t s, const SmallArgs& a, double* gM, double* gK, int* gSz,
@@ -1235,9 +1252,9 @@ hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt,
   return hipGetLastError();
 }
 
-hipError_t launch_final(hipStream_t s, int nt, int dn, double tol, const double* red, State* st, Report* rep, int nb,
-                        size_t bs) {
-  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, dn, tol, red, st, rep, bs);
+hipError_t launch_final(hipStream_t s, int nt, int dn, double tol, double div_limit, const double* red, State* st,
+                        Report* rep, int nb, size_t bs) {
+  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, dn, tol, div_limit, red, st, rep, bs);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ constexpr int kThreads = 256;      // threads per block of the streaming kernels
 constexpr int kSlots = 8;          // copies of each accumulator of the plain comparator's atomics
 constexpr int kMaxParts = 2048;    // largest grid of a kernel that writes per-block partial sums
 constexpr int kMaxM = 64;          // largest cycle length
-constexpr int kMaxD = 2048;        // largest sketch dimension (LDS bins: 16 KB FP64)
+constexpr int kMaxD = 4096;        // largest sketch dimension (LDS bins: 4 x 32 KB FP64 per block)
 constexpr int kMaxNt = 16;         // largest number of time points per solve
 constexpr int kRuleMain = 128;     // default nodes of the quadrature rule
 constexpr int kRuleCosSqrt = 256;  // default nodes of the ellipse rule of cos(t sqrt z)

@@ -983,26 +983,39 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
   return hipGetLastError();
 }
 
-constexpr int kGroupLdsMax = 96 * 1024;  // dynamic LDS the grouped kernel may use (2 blocks per CU)
+constexpr int kGroupLdsMax = 96 * 1024;   // dynamic LDS the grouped kernel may use (2 blocks per CU)
+constexpr int kSpmvLdsMax = 160 * 1024;   // one member per block: up to the whole LDS of a CU (d up to
+                                          // kMaxD: four wavefront bin sets of 32 KB and the CSR chunk)
 
-// The grouped instantiations need more than the default 64 KB of dynamic LDS for FP64 data.
+template <typename T, int M, int Z>
+static hipError_t configure_mz() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kGroupLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
+  if (e == hipSuccess && M != 1)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false, (M != 1)>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
+  return e;
+}
+
+template <typename T>
+static hipError_t configure_t() {
+  hipError_t e = hipSuccess;
+  const hipError_t es[] = {configure_mz<T, 0, 1>(), configure_mz<T, 0, 4>(), configure_mz<T, 0, 8>(),
+                           configure_mz<T, 0, 16>(), configure_mz<T, 0, 32>(), configure_mz<T, 1, 1>(),
+                           configure_mz<T, 1, 4>(), configure_mz<T, 1, 8>(), configure_mz<T, 1, 16>(),
+                           configure_mz<T, 1, 32>(), configure_mz<T, 2, 1>()};
+  for (hipError_t x : es)
+    if (x != hipSuccess) e = x;
+  return e;
+}
+
+// Dynamic LDS limits of the fused kernel's instantiations (beyond the default 64 KB).
 hipError_t configure_step_kernels() {
-  const void* fns[] = {
-      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 1, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 4, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 8, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 16, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<double, 0, 32, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 1, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 4, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 8, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 16, true>), reinterpret_cast<const void*>(&k_spmv_sketch<double, 1, 32, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 1, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 4, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 8, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 16, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<float, 0, 32, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 1, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 4, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 8, true>),
-      reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 16, true>), reinterpret_cast<const void*>(&k_spmv_sketch<float, 1, 32, true>)};
-  for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kGroupLdsMax);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const hipError_t e = configure_t<double>();
+  return e != hipSuccess ? e : configure_t<float>();
 }
 
 size_t group_lds_max() { return kGroupLdsMax; }
@@ -1077,8 +1090,10 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
     hipLaunchKernelGGL(k_orth<8>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   else if (d <= 1024)
     hipLaunchKernelGGL(k_orth<16>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
-  else
+  else if (d <= 2048)
     hipLaunchKernelGGL(k_orth<32>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
+  else
+    hipLaunchKernelGGL(k_orth<64>, g, dim3(64), 0, s, j, k, m, d, uraw, U, R, st, bs);
   return hipGetLastError();
 }
 
