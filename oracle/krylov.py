@@ -264,7 +264,10 @@ def make_rule(fun, t: float = 1.0, n_quad: int | None = None, spec=None):
 
 
 # ----------------------------------------------------------------------------- stopping test
-def tail_estimate(ynorm: float, xnorm: float, history: list) -> float:
+UNIT_ROUNDOFF = 2.0 ** -53  # FP64, the oracle's arithmetic
+
+
+def tail_estimate(ynorm: float, xnorm: float, history: list, unit_roundoff: float = UNIT_ROUNDOFF) -> float:
     """Estimated remaining relative error after a cycle (the stopping test of the restart).
 
     Section 4 estimates the error of the restarted iterate by the difference of two successive
@@ -273,15 +276,17 @@ def tail_estimate(ynorm: float, xnorm: float, history: list) -> float:
     left after cycle c is the geometric tail ||y_c|| q / (1 - q) (exact when every increment is
     the previous one times q).  q is the largest of the last TAIL_RATIOS ratios (fewer in the first
     cycles), so small ratios between growing increments (a dip in a transient) do not end the loop;
-    with q >= 1, or after the first cycle (no ratio yet), the estimate is unbounded.  ``history``
-    holds the increment norms of the earlier cycles and is extended with this one.  Relative to
-    ||x_c||.
+    with q >= 1, or after the first cycle (no ratio yet), the estimate is unbounded.  An increment
+    at or below the unit roundoff of the arithmetic relative to ||x_c|| is rounding noise: its ratio
+    to the previous one says nothing about the error, and the estimate is the increment itself.
+    ``history`` holds the increment norms of the earlier cycles and is extended with this one.
+    Relative to ||x_c||.
     """
     norms = history + [ynorm]
     history.append(ynorm)
     rel = ynorm / xnorm if xnorm > 0 else 0.0
-    if rel == 0.0:
-        return 0.0
+    if rel <= unit_roundoff:
+        return rel
     if len(norms) < 2:
         return np.inf
     q = 0.0

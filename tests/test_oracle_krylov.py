@@ -339,6 +339,25 @@ def test_tail_estimate_uses_the_largest_of_three_ratios():
     assert krylov.tail_estimate(0.0, 1.0, [1.0, 0.5]) == 0.0
 
 
+def test_tail_estimate_at_the_rounding_level():
+    """Increments that have shrunk to the unit roundoff relative to ||x|| and then scatter (ratios
+    above 1) end the test with the increment itself as the estimate; the same ratios above the
+    roundoff keep it unbounded.  Hand-computed values, FP64 roundoff 2^-53 = 1.11e-16."""
+    hist = []
+    ests = [krylov.tail_estimate(y, 1.0, hist) for y in (1.0, 1e-3, 1e-9, 1e-17, 3e-17, 2e-17)]
+    assert ests[0] == np.inf
+    assert ests[1] == pytest.approx(1e-3 * 1e-3 / (1 - 1e-3))
+    assert ests[2] == pytest.approx(1e-9 * 1e-3 / (1 - 1e-3))   # ratios 1e-6, 1e-3
+    assert ests[3:] == [1e-17, 3e-17, 2e-17]                   # at the roundoff: ratios ignored
+    hist = []
+    ests = [krylov.tail_estimate(y, 1.0, hist) for y in (1.0, 1e-3, 1e-9, 1e-14, 3e-14)]
+    assert ests[4] == np.inf                                   # ratio 3 above the roundoff
+    hist = []
+    assert [krylov.tail_estimate(y, 1.0, hist, unit_roundoff=2.0 ** -24) for y in (1.0, 1e-6, 5e-8)] == \
+        [np.inf, pytest.approx(1e-6 * 1e-6 / (1 - 1e-6)), 5e-8]  # FP32 roundoff 5.96e-8
+    assert krylov.tail_estimate(0.0, 1.0, [1.0, 0.5]) == 0.0
+
+
 def test_tail_estimate_stops_within_tol_where_the_raw_difference_does_not():
     """z^(-1/2) of the 3-D Laplacian shifted to condition number 2.6e4, d = 4m: the increments of
     the restart swing by two orders of magnitude from cycle to cycle.  Stopping at the first cycle
