@@ -11,8 +11,8 @@
 // s(u) = P - mu u^2 + 2 i mu u in s = -t z, midpoint rule with N nodes, of which the N/2 with
 // Im s < 0 are solved and the result doubled in its real part (conjugate symmetry).  The stopping
 // test is the library's: the successive difference ||V_m c|| / ||x|| continued by the geometric
-// tail q / (1 - q) of the increments' contraction ratio q (the largest of the last three),
-// stopping when that is <= tol.
+// tail q / (1 - q) of the increments' contraction ratio q (the largest of the last three), or the
+// difference alone once it is at the FP64 unit roundoff, stopping when that is <= tol.
 //
 // It is neither the oracle nor the product: it shares no code with either and exists to time the
 // plain method on the host cores of the GPU machine.
@@ -199,7 +199,7 @@ int cpu_plain_expv(int64_t n, const int32_t* rowptr, const int32_t* colind, cons
       double qb = q;  // the largest of the last three ratios
       if (cyc >= 3) qb = std::max(qb, qprev);
       if (cyc >= 4) qb = std::max(qb, qprev2);
-      const double est = (rel == 0.0) ? 0.0 : (qb < 1.0 ? rel * qb / (1.0 - qb) : inf);
+      const double est = (rel <= 0x1p-53) ? rel : (qb < 1.0 ? rel * qb / (1.0 - qb) : inf);  // roundoff: noise
       yprev = yn;
       qprev2 = qprev;
       qprev = q;

@@ -117,7 +117,11 @@ typedef struct {
                             * increments did not contract): max_t of                 *
                             * (||y_t|| / ||x_t||) q / (1 - q), q the largest of the  *
                             * last three ratios ||y_t|| / ||y_t||_prev (fewer in     *
-                            * cycles 2 and 3); the solve stops when err_est <= tol   */
+                            * cycles 2 and 3), or ||y_t|| / ||x_t|| alone where that *
+                            * is at most the unit roundoff of the value type (2^-53  *
+                            * FP64, 2^-24 FP32).  A time point that has passed       *
+                            * (estimate <= tol) keeps that estimate and is not       *
+                            * tested again; the solve stops when err_est <= tol      */
 } fab_info;
 
 typedef struct fab_ctx fab_ctx;
@@ -199,9 +203,9 @@ fab_status fab_solve(fab_ctx* ctx, const fab_op* A, int32_t fun, const double* h
  * x[(r * nt + i) * ldx + row] = f_i(A) b_r (FP64, overwritten).  Every member runs the
  * method of fab_solve with the same parameters and its own basis, sketch (the same S), restart
  * weights and stopping test; members that have finished are skipped by every kernel while the
- * others continue.  The fused product + sketch kernel reads each CSR chunk once for a group of
- * G members (G chosen once per operator and batch shape by timing G = 1 and G = 16, the grouped
- * kernel with the tile sketch on the matrix cores, on the device).
+ * others continue.  The fused product + sketch kernel reads each CSR chunk, and generates each
+ * row of S, once for a group of G members (G chosen once per operator and batch shape by timing
+ * G = 1, 4, 8 and 16 on the device; a group needs its LDS bins, G d FP64, within 96 KB).
  * The whole cycle of all members is one captured graph.  h_info has nb entries; the return value
  * is the most severe member status (errors before warnings before FAB_OK_BREAKDOWN before FAB_OK).
  * 1 <= nb <= 1024; ldb, ldx >= n; FAB_PLAIN_RESTART is not batched (FAB_E_UNSUPPORTED).
@@ -278,9 +282,10 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
  * applies to later calls on ctx.  Errors: FAB_E_INVALID (ctx NULL, limit not > 0). */
 fab_status fab_divergence_limit(fab_ctx* ctx, double limit);
 
-/* Members per block of the batched product + sketch kernel: 1, or 16 (the MFMA sketch
- * path); 0 (the default) times both on the first batched solve of each operator and batch shape
- * and keeps the faster.  Test hook: pins either path.  Errors: FAB_E_INVALID. */
+/* Members per block of the batched product + sketch kernel: 1, 4, 8 or 16 (a group that does not
+ * fit the grouped kernel's LDS falls back to 1); 0 (the default) times every candidate on the
+ * first batched solve of each operator and batch shape and keeps the fastest.  Test hook: pins a
+ * path.  Errors: FAB_E_INVALID (ctx NULL or another G). */
 fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
 
 /* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on

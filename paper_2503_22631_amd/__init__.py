@@ -255,7 +255,7 @@ def divergence_limit(ctx: Context, limit: float = 1e8):
 
 
 def batch_group(ctx: Context, G: int = 0):
-    """Pin the members per block of the batched kernel (1 or 16); 0 = autotune (default)."""
+    """Pin the members per block of the batched kernel (1, 4, 8 or 16); 0 = autotune (default)."""
     _lib.check(ctx.lib.fab_batch_group(ctx.handle, int(G)), "fab_batch_group", ok=(0,))
 
 

@@ -55,8 +55,8 @@ hipError_t launch_start(hipStream_t, int d, int m, int plain, const double* sv, 
 hipError_t launch_small(hipStream_t, const SmallArgs& a, int nb, const GrowBuffers* grow);
 hipError_t launch_pass(hipStream_t, int dtype, int grid, int n, int m, int nt, int dn, const double* C, void* W,
                        double* x, int64_t ldx, double* parts, const State* st, int nb, size_t bs, const PassSketch& ps);
-hipError_t launch_final(hipStream_t, int nt, int dn, double tol, double div_limit, const double* red, State* st,
-                        Report* rep, int nb, size_t bs);
+hipError_t launch_final(hipStream_t, int nt, int dn, double tol, double div_limit, double uround, const double* red,
+                        State* st, Report* rep, int nb, size_t bs);
 hipError_t launch_sketch_table(hipStream_t, int64_t col0, int64_t count, int d, int zeta, uint64_t seed, int* rows,
                                int8_t* signs);
 hipError_t launch_dot(hipStream_t, int64_t n, const double* x, const double* y, double* part, int max_blocks,
@@ -460,7 +460,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       FAB_TRY(launch_reduce_parts(s, 0, d + 2 * nt, g_vec, q.parts, q.red, q.st, 1, nb, bs));
     else
       FAB_TRY(launch_reduce_parts(s, d, 2 * nt, g_vec, q.parts, q.red + d, q.st, 1, nb, bs));
-    FAB_TRY(launch_final(s, nt, d, p->tol, ctx->div_limit, q.red, q.st, rep, nb, bs));
+    FAB_TRY(launch_final(s, nt, d, p->tol, ctx->div_limit, dt == 0 ? 0x1p-53 : 0x1p-24, q.red, q.st, rep, nb, bs));
   }
   return FAB_OK;
 }
@@ -737,11 +737,11 @@ fab_status fab_workspace_size_batched(const fab_op* A, const fab_params* p, int3
 // batch's own operator and workspace (HIP events, 3 launches after 1 warm-up) and the fastest is
 // kept for this operator and batch shape.  Runs before the solve's set-up, which clears what the
 // timing launches wrote.
-// Whether the grouped kernel (kGroup members per block) can serve this sketch: d <= 256 and its
-// dynamic LDS within what configure_step_kernels allows.
-static bool group_fits(int dtype, const fab_params* p) {
-  return p->d <= 256 && spmv_sketch_lds(dtype, 0, p->d, 16, p->zeta, false) <= group_lds_max() &&
-         spmv_sketch_lds(dtype, 1, p->d, 16, p->zeta, false) <= group_lds_max();
+// Whether the grouped kernel can serve G members per block: its dynamic LDS (G d FP64 bins, the
+// tile's table of S, the CSR chunk) within what configure_step_kernels allows.
+static bool group_fits(int dtype, const fab_params* p, int G) {
+  return spmv_sketch_lds(dtype, 0, p->d, G, p->zeta, false) <= group_lds_max() &&
+         spmv_sketch_lds(dtype, 1, p->d, G, p->zeta, false) <= group_lds_max();
 }
 
 static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p, int nb, const Ptrs& q, size_t bs,
@@ -749,7 +749,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   *G_out = 1;
   if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
   if (ctx->force_group > 0) {  // a forced group the grouped kernel cannot serve falls back to 1
-    *G_out = (ctx->force_group > 1 && !group_fits(A->dtype, p)) ? 1 : ctx->force_group;
+    *G_out = (ctx->force_group > 1 && !group_fits(A->dtype, p, ctx->force_group)) ? 1 : ctx->force_group;
     return FAB_OK;
   }
   for (const auto& t : ctx->tuned)
@@ -766,10 +766,10 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   int best = 1;
   float best_ms = 1e30f;
   hipError_t err = hipSuccess;
-  // candidates: one member per block, or a group of 16 (the MFMA sketch's N-tile; finished members
-  // and padding cost gathers of nothing)
-  for (int G = 1; G <= 16 && err == hipSuccess; G += 15) {
-    if (G > 1 && !group_fits(dt, p)) break;
+  // candidates: one member per block, or groups of 4, 8 or 16 (one to four members per wavefront;
+  // padding members past nb cost nothing)
+  for (int G = 1; G <= 16 && err == hipSuccess; G = (G == 1 ? 4 : 2 * G)) {
+    if (G > 1 && (!group_fits(dt, p, G) || G > 4 * nb)) break;
     const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta, A->colrel != nullptr);
     void* x0 = q.W;
     void* y0 = (char*)q.W + wcol(n, (int)es) * es;
@@ -1170,7 +1170,7 @@ fab_status fab_divergence_limit(fab_ctx* ctx, double limit) {
 }
 
 fab_status fab_batch_group(fab_ctx* ctx, int32_t G) {
-  if (!ctx || (G != 0 && G != 1 && G != 16)) return FAB_E_INVALID;
+  if (!ctx || (G != 0 && G != 1 && G != 4 && G != 8 && G != 16)) return FAB_E_INVALID;
   ctx->force_group = G;
   return FAB_OK;
 }

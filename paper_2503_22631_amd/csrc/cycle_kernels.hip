@@ -1019,10 +1019,17 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn,
 // cycles 2 and 3), the remaining error is estimated by the geometric tail
 //   err_t = (||y_c|| / ||x_c||) q / (1 - q)   for q < 1, and is unbounded for q >= 1
 // (in particular after the first cycle, which has no ratio).  Small ratios between growing
-// increments (a dip inside a transient) do not end the loop.  The solve stops when
+// increments (a dip inside a transient) do not end the loop.  A time point whose relative
+// increment is at or below the unit roundoff of the value type (uround) is converged, err_t being
+// the increment itself: there the increments are rounding noise whose ratios scatter around 1, and
+// a point that converged early (a small t) would otherwise hold back the others.  The time points
+// share one Krylov basis (the restart vector does not depend on t), so each point's estimates are
+// those of its own single solve; a point that has passed (err_t <= tol) is not tested again and
+// keeps the estimate it passed with, and the solve stops in the cycle in which the last point
+// passes, the largest of the single solves' cycle counts.  The solve stops when
 // max_t err_t <= tol.  The raw relative increment max_t ||y_c|| / ||x_c|| is reported too; it
 // decides divergence.  The norms are the fixed-order sums of the pass's partials (red + dn).
-__global__ void k_final(int nt, int dn, double tol, double div_limit, const double* __restrict__ red,
+__global__ void k_final(int nt, int dn, double tol, double div_limit, double uround, const double* __restrict__ red,
                         State* __restrict__ st, Report* __restrict__ rep, size_t bs) {
   if (threadIdx.x != 0) return;
   st = bat(st, bs);
@@ -1047,7 +1054,14 @@ __global__ void k_final(int nt, int dn, double tol, double div_limit, const doub
     double qb = q;
     if (c >= 2) qb = fmax(qb, st->qprev[it]);
     if (c >= 3) qb = fmax(qb, st->qprev2[it]);
-    const double e = (r == 0.0) ? 0.0 : (qb < 1.0 ? r * qb / (1.0 - qb) : inf);
+    // an increment at the unit roundoff of the value type is rounding noise: its own estimate
+    double e = (r <= uround) ? r : (qb < 1.0 ? r * qb / (1.0 - qb) : inf);
+    if ((st->passed_mask >> it) & 1) {
+      e = st->passed[it];  // passed in an earlier cycle: no longer tested
+    } else if (e <= tol) {
+      st->passed_mask |= 1 << it;
+      st->passed[it] = e;
+    }
     est = fmax(est, e);
     st->yprev[it] = y;
     st->qprev2[it] = st->qprev[it];
@@ -1252,9 +1266,9 @@ hipError_t launch_pass(hipStream_t s, int dtype, int grid, int n, int m, int nt,
   return hipGetLastError();
 }
 
-hipError_t launch_final(hipStream_t s, int nt, int dn, double tol, double div_limit, const double* red, State* st,
-                        Report* rep, int nb, size_t bs) {
-  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, dn, tol, div_limit, red, st, rep, bs);
+hipError_t launch_final(hipStream_t s, int nt, int dn, double tol, double div_limit, double uround, const double* red,
+                        State* st, Report* rep, int nb, size_t bs) {
+  hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(64), 0, s, nt, dn, tol, div_limit, uround, red, st, rep, bs);
   return hipGetLastError();
 }
 

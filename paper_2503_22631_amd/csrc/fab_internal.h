@@ -149,11 +149,12 @@ struct State {
   int gram_rows;  // rows of the sketched Gram matrix G = U^T U complete in this cycle (0: none kept)
   int whiten_chol;  // this cycle's T: 1 from the Cholesky factor of G, 0 from the Householder QR
   // stopping test: ||y_t|| of the previous cycle, the contraction ratios ||y_t|| / ||y_t||_prev of
-  // the previous two cycles, the cycles run so far, and the largest relative increment
-  // ||y_t|| / ||x_t|| of this cycle
-  double yprev[kMaxNt], qprev[kMaxNt], qprev2[kMaxNt];
+  // the previous two cycles, the estimate with which a time point passed (0 until it has), the
+  // cycles run so far, and the largest relative increment ||y_t|| / ||x_t|| of this cycle
+  double yprev[kMaxNt], qprev[kMaxNt], qprev2[kMaxNt], passed[kMaxNt];
   double relupd;
   int cyc;
+  int passed_mask;  // bit t: time point t has passed the test
 };
 
 // Host-visible per-cycle report (copied to pinned memory each cycle).

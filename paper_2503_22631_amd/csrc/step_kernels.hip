@@ -5,8 +5,9 @@
 //                   (the product and sketch of Algorithm 1).  S's rows and signs are regenerated
 //                   per row from its counter-based specification and scattered into LDS bins, one
 //                   set per wavefront; each block writes its partial sketch to the partial buffer.
-//                   Batches: one member per block, or 16 per block with the tile sketch on the
-//                   matrix cores.
+//                   Batches: one member per block (k_spmv_sketch), or groups of 4, 8 or 16
+//                   members per block sharing the staged CSR chunk and the generated rows of S
+//                   (k_spmv_sketch_grp).
 //   k_reduce_parts: the per-block partials summed in a fixed order (the sketch of z, the norms of
 //                   the pass): bit-for-bit the same result on every run.
 //   k_orth_update : one launch for step j's Gram-Schmidt and window update (single solves with a
@@ -156,21 +157,12 @@ __device__ __forceinline__ double row_dot(const T* sv, const I* sc, int row0, co
   return acc;
 }
 
-// LDS layout of the fused kernel: bins (one set of d FP64 per wavefront for one member per block;
-// G*d FP64, owned bin by bin by the matrix-core loop, for member groups), then for member groups
-// (G > 1) the tile's products (kThreads*G values) and S's column masks (kThreads*ceil(d/16) words),
-// then the CSR chunk (kChunk values, then kChunk column indices: 16-bit tile offsets for one member
-// per block on an operator that has them, else 32-bit columns).
+// LDS layout of the fused kernel, one member per block: bins (one set of d FP64 per wavefront), then
+// the CSR chunk (kChunk values, then kChunk column indices: 16-bit tile offsets on an operator that
+// has them, else 32-bit columns).
 constexpr int kWaves = kThreads / 64;
-__host__ __device__ inline size_t spmv_lds_bins(int mode, int d, int G) {
-  return (mode == 2) ? 0 : (((size_t)(G > 1 ? G : kWaves) * d * 8 + 15) & ~(size_t)15);
-}
-// Grouped kernel (d <= 256): per tile row, one 32-bit word per 16-bin slice of S's column: bit b
-// = the row hits bin 16 slice + b, bit 16 + b = that entry is negative.
-__host__ __device__ inline size_t spmv_lds_group(int mode, int G, int d, size_t es) {
-  if (mode == 2 || G <= 1) return 0;
-  const size_t nmt = (size_t)(d + 15) / 16;
-  return (((size_t)kThreads * G * es + (size_t)kThreads * nmt * 4) + 15) & ~(size_t)15;
+__host__ __device__ inline size_t spmv_lds_bins(int mode, int d) {
+  return (mode == 2) ? 0 : (((size_t)kWaves * d * 8 + 15) & ~(size_t)15);
 }
 
 // row_dot for MU batch members at once (the same row, entries and values, MU vectors): all
@@ -200,67 +192,46 @@ __device__ __forceinline__ void row_dot_multi(const T* sv, const int* sc, const 
   }
 }
 
-constexpr int kMembersInFlight = 4;  // batch members whose gathers are issued together
-constexpr int kGroup = 16;           // members per block in the grouped (batched) kernel: one MFMA N-tile
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
-
-// BF16 by truncation (the upper half of the FP32 bits) and back.
-__device__ __forceinline__ short bf16_trunc(float x) { return (short)(__float_as_uint(x) >> 16); }
-__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
-
-// Occupancy hint of the fused kernel: for FP32 data one member per block, at least 8 waves per SIMD
-// (the register budget then fits 8 blocks per CU; LDS allows it, and the 256^3 FP32 product runs
-// 17% faster than at the default 7).  FP64 blocks that stage 16-bit column offsets: 6 waves (LDS
-// fits 6 blocks of 27 KB at d = 200; unhinted, the compiler takes 89 VGPRs, 5 waves).  Other FP64
-// blocks are limited to 5 or 6 per CU by LDS anyway, and the grouped kernel would spill under a
-// tighter budget: no hint for them.
-template <typename T, bool GRP, bool C16>
+// Occupancy hint of the one-member kernel: for FP32 data at least 8 waves per SIMD (the register
+// budget then fits 8 blocks per CU; LDS allows it, and the 256^3 FP32 product runs 17% faster than
+// at the default 7).  FP64 blocks that stage 16-bit column offsets: 6 waves (LDS fits 6 blocks of
+// 27 KB at d = 200; unhinted, the compiler takes 89 VGPRs, 5 waves).  Other FP64 blocks are limited
+// to 5 per CU by LDS anyway: no hint.
+template <typename T, bool C16>
 constexpr int spmv_min_waves() {
-  return (sizeof(T) == 4 && !GRP) ? 8 : ((C16 && !GRP) ? 6 : 1);
+  return sizeof(T) == 4 ? 8 : (C16 ? 6 : 1);
 }
 
-// C16: the CSR chunk's columns are staged in LDS as the operator's 16-bit tile offsets (one member
-// per block on an operator that has them; a separate instantiation, since one kernel holding both
-// forms needs 101 instead of 75 VGPRs and drops from 6 to 4 waves per SIMD).
-template <typename T, int MODE, int ZMAX, bool GRP, bool C16 = false>
-__global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP, C16>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
+// C16: the CSR chunk's columns are staged in LDS as the operator's 16-bit tile offsets (a separate
+// instantiation, since one kernel holding both forms needs 101 instead of 75 VGPRs and drops from
+// 6 to 4 waves per SIMD).
+template <typename T, int MODE, int ZMAX, bool C16 = false>
+__global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_sketch(int n, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind,
                                                           const int16_t* __restrict__ colrel,
                                                           const T* __restrict__ vals,
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           int d, int zeta, T scale, uint32_t k0, uint32_t k1,
                                                           double* __restrict__ parts,
-                                                          const State* __restrict__ st, int nb, int G, size_t bs) {
+                                                          const State* __restrict__ st, size_t bs) {
   extern __shared__ unsigned char smem_raw[];
-  // This block serves batch members r0 .. r0+gn-1 (one member for single solves): the CSR chunk is
-  // staged once and applied to every member's vector, and the rows of S are generated once per row.
-  if (!GRP) G = 1;  // the single-member instantiation
-  const int r0 = blockIdx.y * G;
-  const int gn = min(G, nb - r0);
-  const size_t o_grp = spmv_lds_bins(MODE, d, G);
-  const size_t o_chk = o_grp + spmv_lds_group(MODE, G, d, sizeof(T));
-  const int nmt = (d + 15) >> 4;                       // 16-bin slices of the sketch
-  double* bins = reinterpret_cast<double*>(smem_raw);  // [bin][member]
-  T* ztile = reinterpret_cast<T*>(smem_raw + o_grp);   // [row][member]        (G > 1)
-  uint32_t* mtile = reinterpret_cast<uint32_t*>(smem_raw + o_grp + (size_t)kThreads * G * sizeof(T));  // [row][slice]
+  // This block serves batch member blockIdx.y (0 for single solves).
+  const int r0 = blockIdx.y;
+  {
+    const State* sg = st ? bat(st, bs, r0) : nullptr;
+    if (sg && (sg->brk || sg->done)) return;  // uniform over the block
+  }
+  const size_t o_chk = spmv_lds_bins(MODE, d);
+  double* bins = reinterpret_cast<double*>(smem_raw);
   T* sv = reinterpret_cast<T*>(smem_raw + o_chk);
   int* sc = reinterpret_cast<int*>(smem_raw + o_chk + kChunk * sizeof(T));
   int16_t* sc16 = C16 ? reinterpret_cast<int16_t*>(sc) : nullptr;
-  uint32_t live_mask = 0;  // members still iterating (block-uniform)
-  for (int g = 0; g < gn; ++g) {
-    const State* sg = st ? bat(st, bs, r0 + g) : nullptr;
-    if (!sg || !(sg->brk || sg->done)) live_mask |= 1u << g;
-  }
-  if (live_mask == 0) return;
-  const int nbins = (GRP ? G : kWaves) * d;
-  double* wbins = bins + (GRP ? 0 : (threadIdx.x >> 6) * d);  // this wavefront's set (one member per block)
+  double* wbins = bins + (threadIdx.x >> 6) * d;  // this wavefront's set
   if (MODE != 2) {
-    for (int i = threadIdx.x; i < nbins; i += kThreads) bins[i] = 0.0;
+    for (int i = threadIdx.x; i < kWaves * d; i += kThreads) bins[i] = 0.0;
     __syncthreads();
   }
+  const T* xg = bat(x, bs, r0);
   const int ntiles = (n + kThreads - 1) / kThreads;
   TileWalk tw(ntiles);
   for (int tt = tw.local; tt < tw.per_xcd; tt += tw.nloc) {
@@ -285,163 +256,221 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, GRP, C16>())) void k_s
       __builtin_amdgcn_s_setprio(2);
       if (one_chunk) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc, sc16);
     }
-    if (GRP && (MODE == 1 || !one_chunk)) __syncthreads();  // the previous tile's group scatter is done
-    int rows[ZMAX];
-    uint32_t sb = 0;
-    if (MODE == 0 && GRP && one_chunk) {
-      // members in flights of kMembersInFlight: one round trip of gathers per flight
-      for (int g0 = 0; g0 < G; g0 += kMembersInFlight) {
-        const T* xs[kMembersInFlight];
-        double acc[kMembersInFlight];
-#pragma unroll
-        for (int u = 0; u < kMembersInFlight; ++u) {
-          const int g = g0 + u;
-          xs[u] = (g < gn && ((live_mask >> g) & 1u)) ? bat(x, bs, r0 + g) : nullptr;
-          acc[u] = 0.0;
-        }
-        row_dot_multi<T, kMembersInFlight>(sv, sc, xs, my_lo, my_hi, p0, acc);
-#pragma unroll
-        for (int u = 0; u < kMembersInFlight; ++u) {
-          const int g = g0 + u;
-          const T z = (T)acc[u];  // 0 for finished members and padding
-          if (xs[u] != nullptr && live) bat(y, bs, r0 + g)[row] = z;
-          ztile[threadIdx.x * G + g] = z;
+    T z = T(0);
+    if (MODE != 1) {
+      double acc = 0.0;  // FP64 row sums for either value type (see the note above)
+      if (one_chunk) {
+        if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, my_lo, my_hi, p0, acc);
+        else acc = row_dot(sv, sc, row0, xg, my_lo, my_hi, p0, acc);
+      } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
+        for (int cs = p0; cs < p1; cs += kChunk) {
+          const int len = min(kChunk, p1 - cs);
+          stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc, sc16);
+          if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
+          else acc = row_dot(sv, sc, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
         }
       }
-    } else
-    for (int g = 0; g < G; ++g) {
-      if (g >= gn || !((live_mask >> g) & 1u)) {  // uniform over the block
-        if (GRP) ztile[threadIdx.x * G + g] = T(0);
-        continue;
-      }
-      const T* xg = bat(x, bs, r0 + g);
-      T z = T(0);
-      if (MODE != 1) {
-        double acc = 0.0;  // FP64 row sums for either value type (see the note above)
-        if (one_chunk) {
-          if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, my_lo, my_hi, p0, acc);
-          else acc = row_dot(sv, sc, row0, xg, my_lo, my_hi, p0, acc);
-        } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
-          for (int cs = p0; cs < p1; cs += kChunk) {
-            const int len = min(kChunk, p1 - cs);
-            stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc, sc16);
-            if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
-            else acc = row_dot(sv, sc, row0, xg, max(my_lo, cs), min(my_hi, cs + len), cs, acc);
-          }
-        }
-        z = (T)acc;
-        if (live) bat(y, bs, r0 + g)[row] = z;
-      } else if (live) {
-        z = xg[row];
-      }
-      if (MODE != 2) {
-        if (!GRP) {  // single member: scatter straight from the row's lane
-          if (live) {
-            __builtin_amdgcn_s_setprio(0);
-            sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
-            const double zs = (double)z * (double)scale;
+      z = (T)acc;
+      if (live) bat(y, bs, r0)[row] = z;
+    } else if (live) {
+      z = xg[row];
+    }
+    if (MODE != 2 && live) {  // scatter straight from the row's lane
+      int rows[ZMAX];
+      uint32_t sb = 0;
+      __builtin_amdgcn_s_setprio(0);
+      sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
+      const double zs = (double)z * (double)scale;
 #pragma unroll
-            for (int l = 0; l < ZMAX; ++l)
-              if (l < zeta) unsafeAtomicAdd(&wbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
-          }
-        } else {
-          ztile[threadIdx.x * G + g] = z;
+      for (int l = 0; l < ZMAX; ++l)
+        if (l < zeta) unsafeAtomicAdd(&wbins[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+    }
+  }
+  if (MODE != 2) {  // the block's partial sketch, the wavefront sets added in a fixed order
+    __syncthreads();
+    const size_t pidx = part_index();
+    double* pg = bat(parts, bs, r0);
+    for (int b = threadIdx.x; b < d; b += kThreads) {
+      double v = bins[b];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) v += bins[w * d + b];
+      pg[(size_t)b * kMaxParts + pidx] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batch members in groups of G (4, 8 or 16) per block: the tile's CSR chunk is staged once and
+// applied to every member's vector, and the rows and signs of S are generated once per row, into
+// an LDS table, while the chunk's loads are in flight.  Wavefront w then owns members
+// w G/4 .. (w+1) G/4 - 1 over all rows of the tile (lane = row, 64 rows at a time, so the gathers
+// of each member stay coalesced) and scatters their rows of the sketch into one FP64 bin set per
+// block, laid out [member][bin]: every (member, bin) entry has a single writer wavefront, whose
+// LDS atomics apply in program order (and in the hardware's fixed lane order within one
+// instruction), so the block's partial is the same on every run.  S is sparse (zeta of d entries
+// per column): the scatter does zeta updates per row and member, where a dense contraction on the
+// matrix cores would multiply by d - zeta zeros.
+// LDS: bins (G d FP64), the tile's table (ZMAX 16-bit rows and a 32-bit sign word per row), then
+// (products) the CSR chunk with 32-bit columns.
+// ---------------------------------------------------------------------------------------------
+constexpr int kGroupMax = 16;                    // largest group (4 members per wavefront)
+constexpr int kWaveMembers = kGroupMax / kWaves;  // members a wavefront owns at most
+
+__host__ __device__ inline size_t grp_lds_bins(int d, int G) { return ((size_t)G * d * 8 + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t grp_lds_table(int zmax) {
+  return ((size_t)kThreads * (2 * zmax + 4) + 15) & ~(size_t)15;
+}
+
+// Occupancy hint: LDS holds 5 FP32 or 4 FP64 blocks per CU at d = 80 (bins, table, chunk), and the
+// registers of four members' gathers fit those waves without spilling.
+template <typename T>
+constexpr int grp_min_waves() {
+  return sizeof(T) == 4 ? 5 : 4;
+}
+
+template <typename T, int MODE, int ZMAX>
+__global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_grp(int n, const int* __restrict__ rowptr,
+                                                              const int* __restrict__ colind,
+                                                              const int16_t* __restrict__ colrel,
+                                                              const T* __restrict__ vals,
+                                                              const T* __restrict__ x, T* __restrict__ y, int d,
+                                                              int zeta, T scale, uint32_t k0, uint32_t k1,
+                                                              double* __restrict__ parts,
+                                                              const State* __restrict__ st, int nb, int G,
+                                                              size_t bs) {
+  static_assert(MODE == 0 || MODE == 1, "the grouped kernel forms sketches");
+  extern __shared__ unsigned char smem_raw[];
+  const int r0 = blockIdx.y * G;
+  const int gn = min(G, nb - r0);
+  uint32_t live_mask = 0;  // members still iterating (block-uniform)
+  for (int g = 0; g < gn; ++g) {
+    const State* sg = st ? bat(st, bs, r0 + g) : nullptr;
+    if (!sg || !(sg->brk || sg->done)) live_mask |= 1u << g;
+  }
+  if (live_mask == 0) return;
+  const size_t o_tab = grp_lds_bins(d, G);
+  const size_t o_chk = o_tab + grp_lds_table(ZMAX);
+  double* bins = reinterpret_cast<double*>(smem_raw);                       // [member][bin]
+  uint16_t* trow = reinterpret_cast<uint16_t*>(smem_raw + o_tab);           // [row][ZMAX]
+  uint32_t* tsgn = reinterpret_cast<uint32_t*>(trow + kThreads * ZMAX);     // [row]
+  T* sv = reinterpret_cast<T*>(smem_raw + o_chk);
+  int* sc = reinterpret_cast<int*>(smem_raw + o_chk + kChunk * sizeof(T));
+  for (int i = threadIdx.x; i < G * d; i += kThreads) bins[i] = 0.0;
+  // the wavefront index as a scalar: the member pointers below then live in scalar registers and
+  // the per-member branches are scalar branches
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int per_wave = G / kWaves;
+  const T* xs[kWaveMembers];
+  T* ys[kWaveMembers];
+  int gs[kWaveMembers];
+#pragma unroll
+  for (int u = 0; u < kWaveMembers; ++u) {
+    const int g = wv * per_wave + u;
+    const bool own = u < per_wave && g < gn && ((live_mask >> g) & 1u);
+    gs[u] = g;
+    xs[u] = own ? bat(x, bs, r0 + g) : nullptr;
+    ys[u] = own ? bat(y, bs, r0 + g) : nullptr;
+  }
+  const double dscale = (double)scale;
+  const int ntiles = (n + kThreads - 1) / kThreads;
+  TileWalk tw(ntiles);
+  for (int tt = tw.local; tt < tw.per_xcd; tt += tw.nloc) {
+    const int tile = tw.xcd * tw.per_xcd + tt;
+    if (tile >= ntiles) break;  // uniform over the block
+    const int row0 = tile * kThreads;
+    int p0 = 0, p1 = 0;
+    bool one_chunk = true;
+    if (MODE == 0) {
+      p0 = rowptr[row0];
+      p1 = rowptr[min(row0 + kThreads, n)];
+      one_chunk = (p1 - p0) <= kChunk;
+    }
+    __syncthreads();  // the previous tile's chunk and table have been read (and the bins zeroed)
+    T tv[kChunk / kThreads];
+    int tc[kChunk / kThreads];
+    if (MODE == 0 && one_chunk) {
+#pragma unroll
+      for (int q = 0; q < kChunk / kThreads; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        if (e < p1 - p0) {
+          tv[q] = vals[p0 + e];
+          tc[q] = colrel ? row0 + (int)colrel[p0 + e] : colind[p0 + e];
         }
       }
     }
-    if (MODE != 2 && GRP) {
-      // The row's S entries are generated after the products (so the gathers are in flight first)
-      // and kept as per-slice masks.  The tile's sketch for the kGroup members is then a dense
-      // contraction on the matrix cores, bins(d x 16) += S_tile(d x rows) Z_tile(rows x 16):
-      // wavefront w owns 16-bin slices w, w+4, ...; the +-1 entries of S_tile come from the masks
-      // (no dense S in LDS); the scale 1/sqrt(zeta) is applied to the result.
-      //   FP64 data: v_mfma_f64_16x16x4 (lane l: A[l%16][l/16], B[l/16][l%16], D[4r + l/16][l%16]).
-      //   FP32 data: v_mfma_f32_16x16x16bf16 on three BF16 parts of z (hi, mid, lo by truncation;
-      //   they sum to z within 2^-24 |z|, and +-1 times a BF16 value is exact), FP32 accumulation
-      //   (lane l: A[l%16][4(l/16)+v], B[4(l/16)+v][l%16], D[4(l/16)+r][l%16]).
-      if (live) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
-      for (int q = 0; q < nmt; ++q) mtile[threadIdx.x * nmt + q] = 0u;
-      if (live) {
+    {  // the table row of this thread's row, generated while the chunk's loads are in flight
+      const int row = row0 + threadIdx.x;
+      int rows[ZMAX];
+      uint32_t sb = 0;
+      if (row < n) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
 #pragma unroll
-        for (int l = 0; l < ZMAX; ++l)
-          if (l < zeta) {
-            const int bq = rows[l];
-            mtile[threadIdx.x * nmt + (bq >> 4)] |= (1u << (bq & 15)) | ((((sb >> l) & 1u)) << (16 + (bq & 15)));
-          }
+      for (int l = 0; l < ZMAX; ++l) trow[threadIdx.x * ZMAX + l] = (row < n) ? (uint16_t)rows[l] : (uint16_t)0;
+      tsgn[threadIdx.x] = sb;
+    }
+    if (MODE == 0 && one_chunk) {
+#pragma unroll
+      for (int q = 0; q < kChunk / kThreads; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        if (e < p1 - p0) {
+          sv[e] = tv[q];
+          sc[e] = tc[q];
+        }
       }
-      __syncthreads();
-      const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-      const int nrow = min(kThreads, n - row0);
-      const double dscale = (double)scale;
-      const int col = lane & 15, bit = lane & 15;
-      for (int mt = wv; mt < nmt; mt += kThreads / 64) {
-        if constexpr (sizeof(T) == 8) {
-          v4d acc = {0.0, 0.0, 0.0, 0.0};
-          for (int k0r = 0; k0r < nrow; k0r += 4) {
-            const int kk = k0r + (lane >> 4);
-            double a = 0.0, bz = 0.0;
-            if (kk < nrow) {
-              const uint32_t mk = mtile[kk * nmt + mt];
-              a = ((mk >> bit) & 1u) ? (((mk >> (16 + bit)) & 1u) ? -1.0 : 1.0) : 0.0;
-              bz = (double)ztile[kk * G + col];
-            }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bz, acc, 0, 0, 0);
-          }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int rg = 0; rg < kWaves; ++rg) {  // uniform over the block
+      const int lr = rg * 64 + lane;
+      const int row = row0 + lr;
+      const bool live = row < n;
+      double acc[kWaveMembers];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int bb = mt * 16 + 4 * r + (lane >> 4);
-            if (bb < d) bins[bb * G + col] += acc[r] * dscale;  // owner-exclusive (bin, member)
-          }
-        } else {
-          v4f acc = {0.f, 0.f, 0.f, 0.f};
-          for (int k0r = 0; k0r < nrow; k0r += 16) {
-            v4s a, b1, b2, b3;
+      for (int u = 0; u < kWaveMembers; ++u) acc[u] = 0.0;
+      if (MODE == 0) {
+        const int lo = live ? rowptr[row] : 0, hi = live ? rowptr[row + 1] : 0;
+        if (one_chunk) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int kk = k0r + 4 * (lane >> 4) + v;
-              float av = 0.f, zf = 0.f;
-              if (kk < nrow) {
-                const uint32_t mk = mtile[kk * nmt + mt];
-                av = ((mk >> bit) & 1u) ? (((mk >> (16 + bit)) & 1u) ? -1.f : 1.f) : 0.f;
-                zf = (float)ztile[kk * G + col];
-              }
-              a[v] = bf16_trunc(av);
-              const float h = bf16_value(bf16_trunc(zf));
-              const float r1 = zf - h;
-              const float mdl = bf16_value(bf16_trunc(r1));
-              b1[v] = bf16_trunc(h);
-              b2[v] = bf16_trunc(mdl);
-              b3[v] = bf16_trunc(r1 - mdl);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b2, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b3, acc, 0, 0, 0);
-          }
+          for (int u = 0; u < kWaveMembers; ++u)
+            if (xs[u] != nullptr) acc[u] = row_dot(sv, sc, 0, xs[u], lo, hi, p0, 0.0);
+        } else {  // a tile with more than kChunk nonzeros: its chunks in turn, for this row group
+          for (int cs = p0; cs < p1; cs += kChunk) {
+            const int len = min(kChunk, p1 - cs);
+            stage_chunk(vals, colind, colrel, row0, cs, len, sv, sc);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int bb = mt * 16 + 4 * (lane >> 4) + r;
-            if (bb < d) bins[bb * G + col] += (double)acc[r] * dscale;  // owner-exclusive (bin, member)
+            for (int u = 0; u < kWaveMembers; ++u)
+              if (xs[u] != nullptr) acc[u] = row_dot(sv, sc, 0, xs[u], max(lo, cs), min(hi, cs + len), cs, acc[u]);
           }
+        }
+      } else if (live) {
+#pragma unroll
+        for (int u = 0; u < kWaveMembers; ++u)
+          if (xs[u] != nullptr) acc[u] = (double)xs[u][row];
+      }
+      if (live) {
+        uint16_t rows[ZMAX];
+#pragma unroll
+        for (int l = 0; l < ZMAX; ++l) rows[l] = trow[lr * ZMAX + l];
+        const uint32_t sb = tsgn[lr];
+#pragma unroll
+        for (int u = 0; u < kWaveMembers; ++u) {
+          if (xs[u] == nullptr) continue;  // uniform over the wavefront
+          const T z = (T)acc[u];
+          if (MODE == 0) ys[u][row] = z;
+          const double zs = (double)z * dscale;
+          double* mb = bins + (size_t)gs[u] * d;
+#pragma unroll
+          for (int l = 0; l < ZMAX; ++l)
+            if (l < zeta) unsafeAtomicAdd(&mb[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
         }
       }
     }
   }
-  if (MODE != 2) {  // the block's partial sketch of every live member, zeros included
-    __syncthreads();
-    const size_t pidx = part_index();
-    for (int i = threadIdx.x; i < G * d; i += kThreads) {
-      const int b = i / G, g = i - b * G;
-      if (g >= gn || !((live_mask >> g) & 1u)) continue;
-      double v;
-      if (GRP) {
-        v = bins[i];
-      } else {  // the wavefront sets in a fixed order
-        v = bins[b];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) v += bins[w * d + b];
-      }
-      bat(parts, bs, r0 + g)[(size_t)b * kMaxParts + pidx] = v;
-    }
+  __syncthreads();  // the block's partial sketch of every live member
+  const size_t pidx = part_index();
+  for (int i = threadIdx.x; i < G * d; i += kThreads) {
+    const int g = i / d, b = i - g * d;
+    if (g >= gn || !((live_mask >> g) & 1u)) continue;
+    bat(parts, bs, r0 + g)[(size_t)b * kMaxParts + pidx] = bins[i];
   }
 }
 
@@ -933,11 +962,13 @@ __global__ __launch_bounds__(kThreads) void k_scale_col(int n, T* __restrict__ v
 }
 
 // ------------------------------------------------------------------------------------ launchers
+static int zeta_bucket(int zeta) { return zeta <= 1 ? 1 : zeta <= 4 ? 4 : zeta <= 8 ? 8 : zeta <= 16 ? 16 : 32; }
+
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16) {
   const size_t es = dtype == 0 ? 8 : 4;
-  (void)zeta;
-  const size_t ib = (c16 && G <= 1) ? 2 : 4;  // LDS bytes per column index
-  return spmv_lds_bins(mode, d, G) + spmv_lds_group(mode, G, d, es) + (mode == 1 ? 0 : (size_t)kChunk * (es + ib));
+  const size_t chunk = (mode == 1) ? 0 : (size_t)kChunk * (es + (c16 && G <= 1 ? 2 : 4));
+  if (G > 1) return grp_lds_bins(d, G) + grp_lds_table(zeta_bucket(zeta)) + chunk;
+  return spmv_lds_bins(mode, d) + chunk;
 }
 
 template <typename T>
@@ -946,19 +977,27 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
                                        double* parts, const State* st, int nb, int G, size_t bs) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
+  if (G > 1 && (mode == 2 || G % kWaves != 0 || G > kGroupMax)) return hipErrorInvalidValue;
   const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta, cr != nullptr);
   const dim3 g2(grid, (nb + G - 1) / G);
   const bool c16 = cr != nullptr && mode != 1;  // the sketch-only mode stages no CSR chunk
-#define FAB_L(M, Z)                                                                                             \
-  if (G > 1)                                                                                                    \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
-                       scale, k0, k1, parts, st, nb, G, bs);                                                    \
-  else if (c16)                                                                                                 \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false, (M != 1)>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, \
-                       d, zeta, scale, k0, k1, parts, st, nb, 1, bs);                                           \
-  else                                                                                                          \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, false>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
-                       scale, k0, k1, parts, st, nb, 1, bs)
+#define FAB_L(M, Z)                                                                                               \
+  if (G > 1)                                                                                                      \
+    hipLaunchKernelGGL((k_spmv_sketch_grp<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
+                       scale, k0, k1, parts, st, nb, G, bs);                                                      \
+  else if (c16)                                                                                                   \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, (M != 1)>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, \
+                       zeta, scale, k0, k1, parts, st, bs);                                                       \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
+                       scale, k0, k1, parts, st, bs)
+#define FAB_LS(Z)                                                                                                 \
+  if (c16)                                                                                                        \
+    hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d,    \
+                       zeta, scale, k0, k1, parts, st, bs);                                                       \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
+                       scale, k0, k1, parts, st, bs)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -976,26 +1015,29 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
   } else if (mode == 1) {
     FAB_Z(1)
   } else {
-    FAB_L(2, 1);
+    FAB_LS(1);
   }
 #undef FAB_Z
+#undef FAB_LS
 #undef FAB_L
   return hipGetLastError();
 }
 
-constexpr int kGroupLdsMax = 96 * 1024;   // dynamic LDS the grouped kernel may use (2 blocks per CU)
+constexpr int kGroupLdsMax = 96 * 1024;   // dynamic LDS the grouped kernel may use
 constexpr int kSpmvLdsMax = 160 * 1024;   // one member per block: up to the whole LDS of a CU (d up to
                                           // kMaxD: four wavefront bin sets of 32 KB and the CSR chunk)
 
 template <typename T, int M, int Z>
 static hipError_t configure_mz() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kGroupLdsMax);
+  hipError_t e = hipSuccess;
+  if (M != 2)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch_grp<T, (M == 2 ? 0 : M), Z>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kGroupLdsMax);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
   if (e == hipSuccess && M != 1)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false, (M != 1)>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, (M != 1)>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
   return e;
 }
@@ -1023,15 +1065,15 @@ size_t group_lds_max() { return kGroupLdsMax; }
 // The instantiation launch_spmv_sketch picks, for the occupancy query below.
 template <typename T, int M, int Z>
 static const void* spmv_kernel_mz(int G, bool c16) {
-  if (G > 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, true>);
-  if (c16 && M != 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false, (M != 1)>);
-  return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, false>);
+  if (G > 1 && M != 2) return reinterpret_cast<const void*>(&k_spmv_sketch_grp<T, (M == 2 ? 0 : M), Z>);
+  if (c16 && M != 1) return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z, (M != 1)>);
+  return reinterpret_cast<const void*>(&k_spmv_sketch<T, M, Z>);
 }
 
 template <typename T>
 static const void* spmv_kernel(int mode, int zeta, int G, bool c16) {
   if (mode == 2) return spmv_kernel_mz<T, 2, 1>(G, c16);
-  const int Z = zeta <= 1 ? 1 : zeta <= 4 ? 4 : zeta <= 8 ? 8 : zeta <= 16 ? 16 : 32;
+  const int Z = zeta_bucket(zeta);
   if (mode == 0) {
     switch (Z) {
       case 1: return spmv_kernel_mz<T, 0, 1>(G, c16);

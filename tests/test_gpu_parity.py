@@ -750,11 +750,11 @@ def group(fab, ctx, request):
     fab.batch_group(ctx, 0)
 
 
-@pytest.mark.parametrize("group", [1, 16], indirect=True)
+@pytest.mark.parametrize("group", [1, 4, 8, 16], indirect=True)
 def test_batched_matches_single_solves(fab, ctx, group):
     """Five right-hand sides in one batched solve against five single solves (same S) and the
-    closed form, three time points each; one member per block and the 16-member MFMA sketch path
-    (11 padding members)."""
+    closed form, three time points each; one member per block and groups of 4, 8 and 16 members
+    per block (padding members past the fifth)."""
     N = 48
     A = wl.anisotropic_2d(N, 0.01)
     op = _op(fab, ctx, A)
@@ -774,7 +774,7 @@ def test_batched_matches_single_solves(fab, ctx, group):
             assert _rel(xb, exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)) <= 1e-9
 
 
-@pytest.mark.parametrize("group", [1, 16], indirect=True)
+@pytest.mark.parametrize("group", [1, 4, 16], indirect=True)
 def test_batched_members_finish_differently(fab, ctx, group):
     """One batch holding a zero right-hand side (exact at once), an eigenvector (breakdown after one
     step) and random vectors (several cycles): per-member statuses and results."""
@@ -797,7 +797,7 @@ def test_batched_members_finish_differently(fab, ctx, group):
             assert _rel(got, ref) <= 1e-9
 
 
-@pytest.mark.parametrize("group", [1, 16], indirect=True)
+@pytest.mark.parametrize("group", [1, 8, 16], indirect=True)
 def test_batched_fp32_anisotropic_eight_times(fab, ctx, group):
     """The batched workload's shape on a small grid: FP32 anisotropic operator, 8 right-hand sides
     x 8 log-spaced time points, m=20, k=2, d=80, tol 1e-6."""
@@ -813,6 +813,77 @@ def test_batched_fp32_anisotropic_eight_times(fab, ctx, group):
         for i, t in enumerate(CFG4_T):
             ref = exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)
             assert _rel(X[:, r, i].cpu().numpy(), ref) <= FP32_TOL, (r, t)
+
+
+def _laplacian_with_long_row(N, k, width, seed):
+    """The 2-D Laplacian (N^2 rows) plus a symmetric coupling of row k to `width` random columns
+    (weights 0.01 u, u standard normal): the 256-row tile holding row k has more nonzeros than
+    one 2048-entry LDS chunk."""
+    import scipy.sparse as sp
+    L = wl.laplacian_2d(N).to_scipy().tocoo()
+    rng = np.random.default_rng(seed)
+    cols = rng.choice(np.setdiff1d(np.arange(N * N), [k]), size=width, replace=False)
+    w = 0.01 * rng.standard_normal(width)
+    rows = np.concatenate([L.row, np.full(width, k), cols])
+    cc = np.concatenate([L.col, cols, np.full(width, k)])
+    vv = np.concatenate([L.data, w, w])
+    return sp.csr_matrix((vv, (rows, cc)), shape=(N * N, N * N))
+
+
+@pytest.mark.parametrize("group,d", [(1, 80), (4, 80), (8, 80), (16, 80), (16, 256)], indirect=["group"])
+def test_batched_groups_long_row_tile(fab, ctx, group, d):
+    """Batched solves whose operator has a tile of more than one LDS chunk (the chunk-streaming
+    path of the one-member and grouped kernels), FP64, six right-hand sides: every member against
+    its single solve (same S); in the one-member case the first also against dense exp(-tA) b
+    from the oracle (about 10 s of CPU, so once).  d = 256 with 16 members per block puts 32 KB of
+    FP64 bins in the grouped kernel's LDS."""
+    M = _laplacian_with_long_row(64, 1000, 2500, 5)
+    op = fab.CSROperator.from_arrays(ctx, M.indptr, M.indices, M.data)
+    nb, t = 6, 1e-3
+    Bm = np.stack([wl.gaussian_vector(M.shape[0], 500 + r) for r in range(nb)], axis=1)
+    kw = dict(m=20, k=2, d=d, zeta=8, seed=3, tol=1e-10, max_cycles=100)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=t, **kw)
+    assert all(i["group"] == group for i in infos), [i["group"] for i in infos]
+    for r in range(nb):
+        assert infos[r]["status"] == "FAB_OK", (r, infos[r])
+        xs, info_s = fab.solve(op, torch.as_tensor(Bm[:, r], device="cuda"), "exp", t=t, **kw)
+        assert infos[r]["cycles"] == info_s["cycles"], r
+        assert _rel(X[:, r, 0].cpu().numpy(), xs[:, 0].cpu().numpy()) <= 1e-12, r
+    if group == 1:
+        ref = exact.dense_fab("exp", M.toarray(), Bm[:, 0], t=t)
+        assert _rel(X[:, 0, 0].cpu().numpy(), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_time_points_that_converge_early_do_not_hold_back_the_stop(fab, ctx, dtype):
+    """Eight log-spaced time points in one solve on the anisotropic 256^2 operator: the oracle, one
+    time point at a time with the same S, needs 2, 2, 2, 2, 2, 3, 4 and 5 cycles at tol 1e-8.  The
+    early points' increments then fall to the rounding level, where their ratios scatter around 1;
+    the stopping test counts such an increment as converged, so the joint solve stops with the
+    slowest point: after exactly the oracle's largest count in FP64 (within one cycle in FP32, at
+    tol 1e-6), each result within tol of the closed form."""
+    N = 256
+    A = wl.anisotropic_2d(N, 0.01)
+    b = wl.gaussian_vector(A.n, 7)
+    S = sketch.sketch_matrix(A.n, 80, 8, seed=1)
+    tol = 1e-8 if dtype == torch.float64 else 1e-6
+    cyc = []
+    for t in CFG4_T:
+        _, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=20, k=2, S=S, tol=tol, max_cycles=100)
+        assert io.status == "ok"
+        cyc.append(io.cycles)
+    op = _op(fab, ctx, A, dtype)
+    x, info = fab.solve(op, torch.as_tensor(b, dtype=dtype, device="cuda"), "exp", t=CFG4_T, m=20, k=2, d=80,
+                        zeta=8, seed=1, tol=tol, max_cycles=100)
+    assert info["status"] == "FAB_OK", info
+    if dtype == torch.float64:
+        assert info["cycles"] == max(cyc), (info["cycles"], cyc)
+    else:
+        assert abs(info["cycles"] - max(cyc)) <= 1, (info["cycles"], cyc)
+    bb = b if dtype == torch.float64 else b.astype(np.float32).astype(np.float64)
+    for i, t in enumerate(CFG4_T):
+        err = _rel(x[:, i].cpu().numpy(), exact.sine_fab("exp", bb, N, [1.0, 0.01], 0.0, t=t))
+        assert err <= (tol if dtype == torch.float64 else FP32_BATCH_TOL), (t, err)
 
 
 def test_batched_1024_full_size(fab, ctx):
