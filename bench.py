@@ -12,6 +12,7 @@ restarted Arnoldi comparator on the same GPU, and the CPU oracle timed on the ho
 (which also gives the relative error of the GPU result against the exact FP64 solution).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra] [--profile]
+    python bench.py --profile-256 {f32,f64} | --profile-batched     # short runs for rocprofv3
     python bench.py --summarize-pmc FETCH_DIR WRITE_DIR    # turn rocprofv3 --pmc output into traffic
 """
 import argparse
@@ -144,7 +145,8 @@ def cpu_baseline_leg(A, b, x_gpu, x_plain, checks=(), x_cpu_plain=None):
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, out_json: str = TRAFFIC_FILE, workload: str = None,
-                  kernel_label: str = "k_spmv_sketch<double, SpMV+sketch, zeta<=8>"):
+                  kernel_label: str = "k_spmv_sketch<double, SpMV+sketch, zeta<=8>",
+                  kernel_re: str = r"k_spmv_sketch<\w+, 0,"):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel, scaled by what the
     same counters read for a device copy of known size; writes the traffic record under profiles/."""
     def load(d, counter):
@@ -164,7 +166,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_json: str = TRAFFIC_FILE, 
             return None
         return float(max(cps, key=lambda r: int(r["Grid_Size"]))["Counter_Value"])
 
-    is_spmv = lambda k: re.search(r"k_spmv_sketch<\w+, 0,", k) is not None   # mode 0 = SpMV + sketch
+    is_spmv = lambda k: re.search(kernel_re, k) is not None   # mode 0 = SpMV + sketch
     fetch = load(fetch_dir, "FETCH_SIZE")
     write = load(write_dir, "WRITE_SIZE")
     f_k, nf = avg(fetch, is_spmv)
@@ -244,6 +246,38 @@ def profile_256(dtype_name: str):
     print(json.dumps({"profile_256": dtype_name, "n": A.n, "nnz": A.nnz,
                       "spmv_bytes_per_launch": algorithmic_bytes(A.n, A.nnz, 2, es=4 if dtype_name == "f32" else 8,
                                                                  ib=op.index_bytes())[0]}))
+    return 0
+
+
+def profile_batched():
+    """A short run for rocprofv3: the batched workload (anisotropic 1024^2 operator, FP32, 64
+    right-hand sides x 8 time points, m = 20, k = 2, d = 80, zeta = 8), groups of 16 members per
+    block, two solves of two cycles each (80 launches of the grouped product + sketch), then a
+    device copy of COPY_BYTES for counter calibration."""
+    import numpy as np
+    import torch
+
+    import paper_2503_22631_amd as fab
+    import workloads as wl
+
+    N, nb = 1024, 64
+    T = [10.0 ** (-5 + 2 * i / 7) for i in range(8)]
+    A = wl.anisotropic_2d(N, 0.01)
+    Bm = np.stack([wl.gaussian_vector(A.n, 300 + r) for r in range(nb)], axis=1).astype(np.float32)
+    ctx = fab.Context()
+    fab.batch_group(ctx, 16)
+    op = fab.CSROperator.from_arrays(ctx, A.rowptr, A.colind, A.vals, dtype=torch.float32)
+    Bt = torch.as_tensor(Bm, device="cuda")
+    for _ in range(2):
+        fab.solve_batched(op, Bt, "exp", t=T, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-4, max_cycles=2, check=False)
+    torch.cuda.synchronize()
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    floor = 4 * (A.nnz * 6 + 4 * (A.n + 1)) + nb * A.n * 8  # A once per group of 16, x read, z written
+    print(json.dumps({"profile_batched": True, "n": A.n, "nnz": A.nnz, "members": nb, "group": 16,
+                      "floor_bytes_per_launch": floor}))
     return 0
 
 
@@ -466,10 +500,12 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (FP32, batched, ragged, adjoint)")
     ap.add_argument("--profile", action="store_true",
                     help="few solves, no CPU leg, plus a device copy of known size for counter calibration")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="short batched 1024^2 x 64 run for rocprofv3 (grouped kernel)")
     ap.add_argument("--profile-256", choices=("f32", "f64"),
                     help="a short 256^3 z^(-1/2) run (FP32 or FP64 values and basis) for rocprofv3")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
-                    help="FETCH_DIR WRITE_DIR [OUT_JSON WORKLOAD KERNEL_LABEL]")
+                    help="FETCH_DIR WRITE_DIR [OUT_JSON WORKLOAD KERNEL_LABEL KERNEL_REGEX]")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG", help="TRACE_DIR OUT_MD COMMAND [WORKLOAD]")
     args = ap.parse_args()
     if args.summarize_trace:
@@ -480,6 +516,8 @@ def main():
         return 0
     if args.profile_256:
         return profile_256(args.profile_256)
+    if args.profile_batched:
+        return profile_batched()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is documented, not built).", file=sys.stderr)
