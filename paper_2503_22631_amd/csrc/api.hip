@@ -319,16 +319,15 @@ static hipError_t scratch_address(int device, double** out) {
 static hipError_t record_timing_event(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s); }
 
 // Enqueue one full cycle (start, m steps, small, optionally pass + convergence test).
-// Blocks of the fused SpMV + sketch kernel per member group (gridDim.x; the groups of a batch,
-// ceil(nb / G), are gridDim.y): together as many as are resident on the device at once (the
-// occupancy calculator's count per CU, at most 8), so that each block walks many tiles and its
-// fixed work (clearing its bins, writing its partial sketch, which the reduction then reads)
-// stays small against them.
+// Blocks of the fused SpMV + sketch kernel per member group (gridDim.x; the groups of a batch are
+// gridDim.y): as many as are resident on the device at once (the occupancy calculator's count per
+// CU, at most 8).  A batch's groups then run in turn, each over a whole wave of blocks, so one
+// group's vectors are in flight at a time (sizing gridDim.x to fill the device with all groups at
+// once measured slower: 846 against 787 us for 64 members one per block).
 static int spmv_grid(const fab_ctx* ctx, int64_t n, int dtype, int mode, int d, int G = 1, int zeta = 1,
-                     bool c16 = false, int nb = 1) {
+                     bool c16 = false) {
   const int per_cu = std::max(1, std::min(8, spmv_blocks_per_cu(dtype, mode, d, G, zeta, c16)));
-  const int groups = std::max(1, (nb + G - 1) / G);
-  return stream_grid(n, std::min(per_cu * ctx->num_cu / groups, kMaxParts));  // one partial per block
+  return stream_grid(n, std::min(per_cu * ctx->num_cu, kMaxParts));  // one partial per block
 }
 
 // Batch geometry: nb members, each with a single-solve workspace bs bytes apart; the fused kernel
@@ -360,7 +359,7 @@ static fab_status enqueue_first_sketch(const fab_ctx* ctx, hipStream_t s, const 
                                        const Ptrs& q, const Batch& B) {
   if (!pass_sketches(p)) return FAB_OK;
   const int n = (int)A->n;
-  const int g_sk = spmv_grid(ctx, n, A->dtype, 1, p->d, B.G, p->zeta, false, B.nb);
+  const int g_sk = spmv_grid(ctx, n, A->dtype, 1, p->d, B.G, p->zeta);
   FAB_TRY(launch_spmv_sketch(s, A->dtype, 1, g_sk, n, A->rowptr, A->colind, A->colrel, A->vals, q.W, nullptr, p->d,
                              p->zeta, p->seed, q.parts, q.st, B.nb, B.G, B.bs));
   FAB_TRY(launch_reduce_parts(s, 0, p->d, g_sk, q.parts, q.red, q.st, 0, B.nb, B.bs));
@@ -376,8 +375,8 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   const int d = plain ? 1 : p->d;
   const int nb = B.nb;
   const size_t bs = B.bs;
-  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta, A->colrel != nullptr, nb);
-  const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta, false, nb);
+  const int g_spmv = spmv_grid(ctx, n, dt, plain ? 2 : 0, d, B.G, p->zeta, A->colrel != nullptr);
+  const int g_sk = spmv_grid(ctx, n, dt, 1, d, B.G, p->zeta);
   const int g_vec = stream_grid(n, 2048);
   auto col = [&](int j) -> void* { return (char*)q.W + (size_t)j * wcol(n, (int)es) * es; };
   const bool pass_sk = with_pass && pass_sketches(p);
@@ -457,15 +456,13 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   }
   FAB_TRY(launch_small(s, a, nb, p->method == FAB_SKETCHED_GROWING ? &gb : nullptr));
   if (with_pass) {
-    // the pass's blocks per member: 2048 over the whole batch (each writes a partial of d + 2 nt)
-    const int g_pass = stream_grid(n, std::max(kXcds, 2048 / nb));
-    FAB_TRY(launch_pass(s, dt, g_pass, n, m, nt, d, q.C, q.W, x, B.ldx, q.parts, q.st, nb, bs,
+    FAB_TRY(launch_pass(s, dt, g_vec, n, m, nt, d, q.C, q.W, x, B.ldx, q.parts, q.st, nb, bs,
                         pass_sk ? pass_sketch(p, dt) : PassSketch{}));
     // the next start's sketch (entries [0, d)) when the pass formed it, and the norms after it
     if (pass_sk)
-      FAB_TRY(launch_reduce_parts(s, 0, d + 2 * nt, g_pass, q.parts, q.red, q.st, 1, nb, bs));
+      FAB_TRY(launch_reduce_parts(s, 0, d + 2 * nt, g_vec, q.parts, q.red, q.st, 1, nb, bs));
     else
-      FAB_TRY(launch_reduce_parts(s, d, 2 * nt, g_pass, q.parts, q.red + d, q.st, 1, nb, bs));
+      FAB_TRY(launch_reduce_parts(s, d, 2 * nt, g_vec, q.parts, q.red + d, q.st, 1, nb, bs));
     FAB_TRY(launch_final(s, nt, d, p->tol, ctx->div_limit, dt == 0 ? 0x1p-53 : 0x1p-24, q.red, q.st, rep, nb, bs));
   }
   return FAB_OK;
@@ -776,7 +773,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   // padding members past nb cost nothing)
   for (int G = 1; G <= 16 && err == hipSuccess; G = (G == 1 ? 4 : 2 * G)) {
     if (G > 1 && (!group_fits(dt, p, G) || G > 4 * nb)) break;
-    const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta, A->colrel != nullptr, nb);
+    const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta, A->colrel != nullptr);
     void* x0 = q.W;
     void* y0 = (char*)q.W + wcol(n, (int)es) * es;
     for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
