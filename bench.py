@@ -52,6 +52,17 @@ def algorithmic_bytes(n: int, nnz: int, k: int, es: int = 8, ib: int = 4):
     return spmv, step
 
 
+def plain_cycle_bytes(n: int, nnz: int, m: int, nt: int = 1, es: int = 8, ib: int = 4) -> int:
+    """Bytes one cycle of the plain restarted Arnoldi comparator moves, by its kernels: the start
+    vector's norm (es n) and scaling (2 es n); per step j the product (as above), the two
+    classical Gram-Schmidt sweeps (each a Gram pass reading j + 1 basis columns and z, and an
+    update reading them and writing z: (2j + 5) es n) and the scaling of the new vector (2 es n);
+    the pass over the m + 1 basis columns and nt columns of x (read and written, FP64)."""
+    spmv = (es + ib) * nnz + 4 * (n + 1) + 2 * es * n
+    steps = sum(spmv + 2 * (2 * j + 5) * es * n + 2 * es * n for j in range(m))
+    return 3 * es * n + steps + (m + 1) * es * n + 16 * nt * n
+
+
 def update_bytes(n: int, m: int, k: int, es: int = 8) -> float:
     """Average bytes per window update of a full cycle: step j reads z and its min(k, j+1) window
     columns and writes w_{j+1}."""
@@ -589,8 +600,15 @@ def main():
         torch.cuda.synchronize()
         pdt = (time.perf_counter() - p0) / kp
         x_plain = xpv[:, 0].cpu().numpy().copy()
+        # The comparator's kernels are less tuned than the sketched path's: its bytes per solve over
+        # its time give its HBM fraction, and the time it would take at the sketched loop's
+        # fraction gives the speedup at equal bandwidth efficiency (a bound on what tuning it buys).
+        pbytes = pinfo["cycles"] * plain_cycle_bytes(A.n, A.nnz, w["m"], 1, ib=op.index_bytes())
+        p_gbs = pbytes / pdt / 1e9
         comparison = {"plain_restarted_arnoldi_solves_per_s": 1.0 / pdt, "plain_cycles": pinfo["cycles"],
-                      "plain_matvecs": pinfo["matvecs"], "sketched_speedup_time_to_tol": value * pdt}
+                      "plain_matvecs": pinfo["matvecs"], "sketched_speedup_time_to_tol": value * pdt,
+                      "plain_bytes_per_solve": pbytes, "plain_GB/s": p_gbs, "plain_frac": p_gbs / HBM_PEAK_GBS,
+                      "sketched_speedup_at_equal_frac": value * pbytes / (loop_gbs * 1e9) if loop_gbs else None}
         del wp, xp
 
     if args.profile:

@@ -225,8 +225,11 @@ def test_whitening_falls_back_to_householder_for_an_ill_conditioned_basis(fab, c
     assert _rel(T, c.T) <= 1e-6
 
 
-def test_plain_cycle_matches_arnoldi(fab, ctx):
-    A = wl.convdiff_3d(12, 50.0)
+@pytest.mark.parametrize("N", [12, 13])   # 1728 rows (27 tiles of 64), 2197 (a ragged last tile)
+def test_plain_cycle_matches_arnoldi(fab, ctx, N):
+    """The comparator's cycle (classical Gram-Schmidt applied twice) against the oracle's Arnoldi:
+    basis, Hessenberg matrix and the next-vector coupling."""
+    A = wl.convdiff_3d(N, 50.0)
     op = _op(fab, ctx, A)
     v = wl.gaussian_vector(A.n, 4)
     g = fab.cycle_debug(op, torch.as_tensor(v, device="cuda"), m=16, k=16, d=17, zeta=1, method="plain")
