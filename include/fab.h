@@ -290,12 +290,15 @@ fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
 
 /* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on
  * the context's stream (instead of replaying the cycle graph: the same kernels with the same
- * launch configuration) and records HIP events around each launch of the fused SpMV + sketch
+ * launch configuration).  on = 1: HIP events around each launch of the fused SpMV + sketch
  * kernel (the product and sketch of Algorithm 1), around each window update (Algorithm 1's basis
  * update: the fused Gram-Schmidt + update kernel, or the update kernel alone), and around each
- * cycle's m-step loop, accumulating their durations.
+ * cycle's m-step loop, accumulating their durations.  on = 2: events around each full cycle's
+ * m-step loop only (no events between its kernels, which would add their own gaps); the kernel
+ * totals stay 0.  on = 0: off (graph replay again).
  * fab_timing_read returns the totals since the last read and clears them.  Counts only steps
- * that ran (steps after a breakdown are excluded).  Errors: FAB_E_INVALID, FAB_E_HIP. */
+ * that ran (steps after a breakdown are excluded).  Errors: FAB_E_INVALID (on outside 0..2),
+ * FAB_E_HIP. */
 fab_status fab_timing_enable(fab_ctx* ctx, int32_t on);
 fab_status fab_timing_read(fab_ctx* ctx, double* h_spmv_ms, int64_t* h_spmv_launches, double* h_loop_ms,
                            int64_t* h_loop_steps, double* h_update_ms, int64_t* h_update_launches);

@@ -259,8 +259,10 @@ def batch_group(ctx: Context, G: int = 0):
     _lib.check(ctx.lib.fab_batch_group(ctx.handle, int(G)), "fab_batch_group", ok=(0,))
 
 
-def timing_enable(ctx: Context, on: bool = True):
-    _lib.check(ctx.lib.fab_timing_enable(ctx.handle, 1 if on else 0), "fab_timing_enable", ok=(0,))
+def timing_enable(ctx: Context, on=True):
+    """HIP-event timing: True/1 = each product, update and step loop; 2 = the step loops only; False/0 = off."""
+    mode = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _lib.check(ctx.lib.fab_timing_enable(ctx.handle, mode), "fab_timing_enable", ok=(0,))
 
 
 def timing_read(ctx: Context) -> dict:

@@ -104,6 +104,7 @@ struct fab_ctx {
   // benchmark timing: events around each SpMV+sketch launch and each window-update launch (2 each
   // per step; see kTevUpdate) and at the loop end (kTevEnd)
   bool timing = false;
+  bool timing_loop_only = false;  // fab_timing_enable(ctx, 2): events at the step loops' ends only
   std::vector<hipEvent_t> tev;
   double t_spmv_ms = 0.0, t_loop_ms = 0.0, t_upd_ms = 0.0;
   int64_t t_spmv_n = 0, t_loop_n = 0, t_upd_n = 0;
@@ -394,29 +395,29 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st, nb, bs));
   for (int j = 0; j < m; ++j) {
     if (!plain) {
-      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
+      if (tev && (j == 0 || !ctx->timing_loop_only)) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
                                  d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs));
-      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
+      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_reduce_parts(s, 0, d, g_spmv, q.parts, q.uraw, q.st, 0, nb, bs));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members)
       if (nb == 1 && d <= 256 && p->k <= 8) {
-        if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
+        if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
-        if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
+        if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
       }
-      if (tev) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j + 1], s));
+      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j + 1], s));
     } else {
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
-      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j], s));
+      if (tev && (j == 0 || !ctx->timing_loop_only)) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
                                  1, 1, 0, nullptr, q.st, 1, 1, 0));
-      if (tev) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
+      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set1, 0, q.st));
@@ -979,8 +980,10 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
     if (ctx->timing) {
       // the update of a step runs when the step does not break down: the steps before the last
       // always, the last one only for a full cycle (the sketched path; the plain comparator records none)
-      const int upd = (p->method == FAB_PLAIN_RESTART) ? 0 : (steps == p->m ? steps : std::max(steps - 1, 0));
-      for (int j = 0; j < steps; ++j) {
+      const int upd = (p->method == FAB_PLAIN_RESTART || ctx->timing_loop_only)
+                          ? 0
+                          : (steps == p->m ? steps : std::max(steps - 1, 0));
+      for (int j = 0; j < steps && !ctx->timing_loop_only; ++j) {
         float ms = 0.f;
         FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[2 * j], ctx->tev[2 * j + 1]));
         ctx->t_spmv_ms += ms;
@@ -990,7 +993,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
         FAB_TRY(hipEventElapsedTime(&ms, ctx->tev[kTevUpdate + 2 * j], ctx->tev[kTevUpdate + 2 * j + 1]));
         ctx->t_upd_ms += ms;
       }
-      ctx->t_spmv_n += steps;
+      ctx->t_spmv_n += ctx->timing_loop_only ? 0 : steps;
       ctx->t_upd_n += upd;
       if (steps == p->m) {
         float ms = 0.f;
@@ -1185,7 +1188,9 @@ fab_status fab_timing_enable(fab_ctx* ctx, int32_t on) {
     for (auto& e : ctx->tev)
       if (hipEventCreate(&e) != hipSuccess) return FAB_E_HIP;
   }
+  if (on < 0 || on > 2) return FAB_E_INVALID;
   ctx->timing = on != 0;
+  ctx->timing_loop_only = on == 2;
   ctx->t_spmv_ms = ctx->t_loop_ms = ctx->t_upd_ms = 0.0;
   ctx->t_spmv_n = ctx->t_loop_n = ctx->t_upd_n = 0;
   return FAB_OK;
