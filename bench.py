@@ -356,7 +356,7 @@ def extra_legs(fab, ctx):
         ss = tm["spmv_ms"] / max(tm["spmv_launches"], 1) / 1e3
         leg = {"workload": f"convdiff_3d_N128_Pe50, one cycle (no restart), m = k = 60, d = {d_un}",
                "solves_per_s": 1.0 / sec, "ms_per_solve": 1e3 * sec, "status": info["status"],
-               "update": {"kernel": "k_update<double, 64>", "avg_us": us * 1e6, "bytes_per_launch_avg": ub,
+               "update": {"kernel": "k_update_wide<double> (k = m window update)", "avg_us": us * 1e6, "bytes_per_launch_avg": ub,
                           "GB/s": ub / us / 1e9, "frac": ub / us / 1e9 / HBM_PEAK_GBS},
                "spmv_sketch": {"avg_us": ss * 1e6, "GB/s": sb / ss / 1e9, "frac": sb / ss / 1e9 / HBM_PEAK_GBS}}
         xh = x[:, 0].cpu().numpy()

@@ -842,6 +842,84 @@ __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict
   }
 }
 
+// The same update for wide windows (k > 8, up to the whole basis: the k = m update of the paper's
+// restart-rand and unrestarted rand, a tall-skinny product, Section 2.2).  The coefficients come
+// from LDS instead of registers (64 FP64 coefficients per thread cost the occupancy), the columns
+// in groups of kUpdGroup whose loads are issued together, two adjacent rows per thread (16-byte
+// loads for FP64).  The arithmetic and its order are k_update's, so the bits are the same.
+constexpr int kUpdGroup = 8;
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_wide(int n, int j, T* __restrict__ W,
+                                                          const State* __restrict__ st, size_t bs) {
+  typedef typename Pair<T>::type P;
+  __shared__ double s_coef[kMaxM + 1];
+  st = bat(st, bs);
+  if (st->brk || st->done) return;
+  W = bat(W, bs);
+  const int lo = st->step_lo, nw = j - lo + 1;
+  for (int q = threadIdx.x; q < nw; q += kThreads) s_coef[q] = st->upd_coef[q];
+  const double inv = st->inv_rho;
+  __syncthreads();
+  const size_t ld = wcol(n, sizeof(T));  // whole 4 KiB pages: every column's pairs are aligned
+  T* out = W + (size_t)(j + 1) * ld;
+  const T* base = W + (size_t)lo * ld;
+  const size_t npair = ((size_t)n + 1) / 2;
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  for (size_t pi = (size_t)blockIdx.x * kThreads + threadIdx.x; pi < npair; pi += stride) {
+    const size_t i = 2 * pi;
+    const bool two = i + 1 < (size_t)n;
+    double v0, v1 = 0.0;
+    if (two) {
+      const P zz = __builtin_nontemporal_load(reinterpret_cast<const P*>(out + i));
+      v0 = (double)zz.x;
+      v1 = (double)zz.y;
+    } else {
+      v0 = (double)__builtin_nontemporal_load(out + i);
+    }
+    for (int q0 = 0; q0 < nw; q0 += kUpdGroup) {
+      P a[kUpdGroup];
+#pragma unroll
+      for (int u = 0; u < kUpdGroup; ++u) {
+        const int q = q0 + u;
+        a[u] = P{T(0), T(0)};
+        if (q < nw) {
+          const T* col = base + (size_t)q * ld + i;
+          if (two) a[u] = __builtin_nontemporal_load(reinterpret_cast<const P*>(col));
+          else a[u].x = __builtin_nontemporal_load(col);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdGroup; ++u) {
+        if (q0 + u < nw) {
+          const double c = s_coef[q0 + u];
+          v0 -= c * (double)a[u].x;
+          v1 -= c * (double)a[u].y;
+        }
+      }
+    }
+    if (two) {
+      P r;
+      r.x = (T)(v0 * inv);
+      r.y = (T)(v1 * inv);
+      __builtin_nontemporal_store(r, reinterpret_cast<P*>(out + i));
+    } else {
+      __builtin_nontemporal_store((T)(v0 * inv), out + i);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ plain Arnoldi (CGS2) kernels
 // Partial Gram products h_i = <V_i, z>, i < j1, plus ||z||^2 in slot entry j1 when want_norm.
 template <typename T>
@@ -1165,12 +1243,8 @@ static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, 
     hipLaunchKernelGGL((k_update<T, 4>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else if (k <= 8)
     hipLaunchKernelGGL((k_update<T, 8>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
-  else if (k <= 16)
-    hipLaunchKernelGGL((k_update<T, 16>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
-  else if (k <= 32)
-    hipLaunchKernelGGL((k_update<T, 32>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
   else
-    hipLaunchKernelGGL((k_update<T, 64>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
+    hipLaunchKernelGGL((k_update_wide<T>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
 }
 
 hipError_t launch_update(hipStream_t s, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
