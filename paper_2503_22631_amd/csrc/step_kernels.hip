@@ -922,6 +922,8 @@ __global__ __launch_bounds__(kThreads) void k_update_wide(int n, int j, T* __res
 
 // ------------------------------------------------------------------ plain Arnoldi (CGS2) kernels
 // Partial Gram products h_i = <V_i, z>, i < j1, plus ||z||^2 in slot entry j1 when want_norm.
+// Columns in chunks of kGramCols (one pass over the rows per chunk, z read again for each).
+constexpr int kGramCols = 8;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram(int n, int j1, const T* __restrict__ V,
                                                    const T* __restrict__ z, double* __restrict__ slots,
@@ -929,24 +931,38 @@ __global__ __launch_bounds__(kThreads) void k_gram(int n, int j1, const T* __res
   __shared__ double part[kThreads / 64][kMaxM + 2];
   if (st->brk) return;
   const int ncol = j1 + (want_norm ? 1 : 0);
-  const size_t ld = wcol(n, sizeof(T));
+  typedef typename Pair<T>::type P;
+  const size_t ld = wcol(n, sizeof(T));  // whole 4 KiB pages: every column's pairs are aligned
+  const size_t npair = ((size_t)n + 1) / 2;
   const size_t stride = (size_t)gridDim.x * kThreads;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int c0 = 0; c0 < ncol; c0 += 16) {
-    double acc[16];
+  for (int c0 = 0; c0 < ncol; c0 += kGramCols) {
+    double acc[kGramCols];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
-      const double zi = (double)z[i];
+    for (int q = 0; q < kGramCols; ++q) acc[q] = 0.0;
+    // two adjacent rows per thread (16-byte loads for FP64)
+    for (size_t pi = (size_t)blockIdx.x * kThreads + threadIdx.x; pi < npair; pi += stride) {
+      const size_t i = 2 * pi;
+      const bool two = i + 1 < (size_t)n;
+      P zz = P{T(0), T(0)};
+      if (two) zz = *reinterpret_cast<const P*>(z + i);
+      else zz.x = z[i];
+      const double z0 = (double)zz.x, z1 = (double)zz.y;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < kGramCols; ++q) {
         const int c = c0 + q;
-        if (c < j1) acc[q] += (double)V[(size_t)c * ld + i] * zi;
-        else if (c == j1 && want_norm) acc[q] += zi * zi;
+        if (c < j1) {
+          P a = P{T(0), T(0)};
+          if (two) a = *reinterpret_cast<const P*>(V + (size_t)c * ld + i);
+          else a.x = V[(size_t)c * ld + i];
+          acc[q] += (double)a.x * z0 + (double)a.y * z1;
+        } else if (c == j1 && want_norm) {
+          acc[q] += z0 * z0 + z1 * z1;
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < kGramCols; ++q) {
       const double s = wave_sum(acc[q]);
       if (lane == 0 && c0 + q < ncol) part[w][c0 + q] = s;
     }
@@ -988,16 +1004,54 @@ __global__ __launch_bounds__(kThreads) void k_cgs_update(int n, int j, int m, T*
     }
     for (int c = threadIdx.x; c < kSlots * (kMaxM + 2); c += kThreads) slots_zero[c] = 0.0;
   }
-  const size_t ld = wcol(n, sizeof(T));
+  // two adjacent rows per thread, the basis columns in groups of kUpdGroup whose loads are issued
+  // together (one load in flight per column otherwise); column order as before
+  typedef typename Pair<T>::type P;
+  const size_t ld = wcol(n, sizeof(T));  // whole 4 KiB pages: every column's pairs are aligned
   T* z = V + (size_t)j1 * ld;
+  const size_t npair = ((size_t)n + 1) / 2;
   const size_t stride = (size_t)gridDim.x * kThreads;
   double nrm = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
-    double v = (double)z[i];
-    for (int c = 0; c < j1; ++c) v -= h[c] * (double)V[(size_t)c * ld + i];
-    const T vt = (T)v;
-    z[i] = vt;
-    nrm += (double)vt * (double)vt;
+  for (size_t pi = (size_t)blockIdx.x * kThreads + threadIdx.x; pi < npair; pi += stride) {
+    const size_t i = 2 * pi;
+    const bool two = i + 1 < (size_t)n;
+    double v0, v1 = 0.0;
+    if (two) {
+      const P zz = *reinterpret_cast<const P*>(z + i);
+      v0 = (double)zz.x;
+      v1 = (double)zz.y;
+    } else {
+      v0 = (double)z[i];
+    }
+    for (int c0 = 0; c0 < j1; c0 += kUpdGroup) {
+      P a[kUpdGroup];
+#pragma unroll
+      for (int u = 0; u < kUpdGroup; ++u) {
+        a[u] = P{T(0), T(0)};
+        if (c0 + u < j1) {
+          const T* col = V + (size_t)(c0 + u) * ld + i;
+          if (two) a[u] = *reinterpret_cast<const P*>(col);
+          else a[u].x = *col;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdGroup; ++u) {
+        if (c0 + u < j1) {
+          v0 -= h[c0 + u] * (double)a[u].x;
+          v1 -= h[c0 + u] * (double)a[u].y;
+        }
+      }
+    }
+    const T t0 = (T)v0, t1 = (T)v1;
+    if (two) {
+      P r;
+      r.x = t0;
+      r.y = t1;
+      *reinterpret_cast<P*>(z + i) = r;
+    } else {
+      z[i] = t0;
+    }
+    nrm += (double)t0 * (double)t0 + (double)t1 * (double)t1;
   }
   if (want_norm) {
     const double s = block_sum(nrm, red, phase);
