@@ -58,7 +58,9 @@ __device__ __forceinline__ double block_sum(double v, double* buf, int& phase) {
 // MODE 0: y = A x and sketch of y;  MODE 1: sketch of x only;  MODE 2: y = A x only.
 //
 // Each block walks row tiles of kThreads rows (XCD-contiguous slabs).  The tile's nonzeros are
-// staged through LDS in chunks of kChunk with coalesced loads of values and column indices, then
+// staged through LDS in chunks of kChunk with coalesced loads of values and column indices (16-byte
+// loads from the chunk start rounded down, where the arrays are 16-byte aligned: 3 - 4% on the
+// 256^3 operator, 1% on 128^3; element loads otherwise), then
 // every lane forms its own row (so stencil gathers of x stay coalesced across the wavefront).
 // The sketch of the row value is scattered into FP64 LDS bins, one set per wavefront: a
 // wavefront's LDS atomics are applied in one order (its instructions in program order, the lanes of
@@ -128,6 +130,84 @@ __device__ __forceinline__ void stage_chunk(const T* __restrict__ vals, const in
         sv[e] = tv[q];
         sc[e] = tc[q];
       }
+    }
+  }
+  __syncthreads();
+}
+
+// Vectorized staging for 32-bit columns: nonzeros [a0, p1) with a0 = p0 rounded down to 4, in
+// 16-byte loads (4 columns, 4 FP32 or 2 x 2 FP64 values per load), stored at LDS position
+// index - a0; a load that would pass nnz falls back to element loads.  Positions below p0 - a0 and
+// from p1 - a0 on hold neighbours' entries that no row of the tile reads.
+template <typename T>
+__device__ __forceinline__ void stage_chunk_vec(const T* __restrict__ vals, const int* __restrict__ colind,
+                                                int a0, int p1, int nnz, T* sv, int* sc) {
+  __syncthreads();
+  constexpr int G = kChunk / (4 * kThreads);  // 16-byte groups per thread
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  i4 cv[G];
+  t4 vv[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int s0 = a0 + 4 * ((int)threadIdx.x + q * kThreads);
+    if (s0 < p1) {
+      if (s0 + 4 <= nnz) {
+        cv[q] = *reinterpret_cast<const i4*>(colind + s0);
+        vv[q] = *reinterpret_cast<const t4*>(vals + s0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          cv[q][u] = (s0 + u < nnz) ? colind[s0 + u] : 0;
+          vv[q][u] = (s0 + u < nnz) ? vals[s0 + u] : T(0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int e = 4 * ((int)threadIdx.x + q * kThreads);
+    if (a0 + e < p1) {
+      *reinterpret_cast<i4*>(sc + e) = cv[q];
+      *reinterpret_cast<t4*>(sv + e) = vv[q];
+    }
+  }
+  __syncthreads();
+}
+
+// The same for 16-bit tile offsets: nonzeros [a0, p1) with a0 = p0 rounded down to 8, 8 offsets
+// per 16-byte load and the values in 16-byte loads, the offsets kept as 16 bits in LDS.
+template <typename T>
+__device__ __forceinline__ void stage_chunk_vec16(const T* __restrict__ vals, const int16_t* __restrict__ colrel,
+                                                  int a0, int p1, int nnz, T* sv, int16_t* sc16) {
+  __syncthreads();
+  constexpr int G = kChunk / (8 * kThreads);  // 8-entry groups per thread
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  typedef T t8 __attribute__((ext_vector_type(8)));
+  s8 cv[G];
+  t8 vv[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int s0 = a0 + 8 * ((int)threadIdx.x + q * kThreads);
+    if (s0 < p1) {
+      if (s0 + 8 <= nnz) {
+        cv[q] = *reinterpret_cast<const s8*>(colrel + s0);
+        vv[q] = *reinterpret_cast<const t8*>(vals + s0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          cv[q][u] = (s0 + u < nnz) ? colrel[s0 + u] : (short)0;
+          vv[q][u] = (s0 + u < nnz) ? vals[s0 + u] : T(0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int e = 8 * ((int)threadIdx.x + q * kThreads);
+    if (a0 + e < p1) {
+      *reinterpret_cast<s8*>(sc16 + e) = cv[q];
+      *reinterpret_cast<t8*>(sv + e) = vv[q];
     }
   }
   __syncthreads();
@@ -232,6 +312,9 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_s
     __syncthreads();
   }
   const T* xg = bat(x, bs, r0);
+  // 16-byte staging loads where the CSR arrays allow them (uniform over the grid)
+  const bool vec_ok = MODE != 1 && ((((uintptr_t)vals) | ((uintptr_t)(C16 ? (const void*)colrel : (const void*)colind))) & 15) == 0;
+  const int nnz_all = vec_ok ? rowptr[n] : 0;
   const int ntiles = (n + kThreads - 1) / kThreads;
   TileWalk tw(ntiles);
   for (int tt = tw.local; tt < tw.per_xcd; tt += tw.nloc) {
@@ -240,7 +323,7 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_s
     const int row0 = tile * kThreads;
     const int row = row0 + threadIdx.x;
     const bool live = row < n;
-    int p0 = 0, p1 = 0, my_lo = 0, my_hi = 0;
+    int p0 = 0, p1 = 0, my_lo = 0, my_hi = 0, a0 = 0;
     bool one_chunk = true;
     if (MODE != 1) {
       const int rend = min(row0 + kThreads, n);
@@ -248,20 +331,25 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_s
       p1 = rowptr[rend];
       my_lo = live ? rowptr[row] : 0;
       my_hi = live ? rowptr[row + 1] : 0;
-      one_chunk = (p1 - p0) <= kChunk;
+      a0 = vec_ok ? (p0 & (C16 ? ~7 : ~3)) : p0;
+      one_chunk = (p1 - a0) <= kChunk;
       // Wave priority: the tile's loads (CSR chunk, then the row gathers) at a raised priority,
       // the sketch arithmetic at the default one, so the sequencer issues the memory work of the
       // waiting waves first and the ALU work of the sketch fills the gaps between (159 against
       // 153.5 solves/s on the 128^3 workload; the fused kernel 38.7 against 41.0 us)
       __builtin_amdgcn_s_setprio(2);
-      if (one_chunk) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc, sc16);
+      if (one_chunk) {
+        if (!vec_ok) stage_chunk(vals, colind, colrel, row0, p0, p1 - p0, sv, sc, sc16);
+        else if constexpr (C16) stage_chunk_vec16(vals, colrel, a0, p1, nnz_all, sv, sc16);
+        else stage_chunk_vec(vals, colind, a0, p1, nnz_all, sv, sc);
+      }
     }
     T z = T(0);
     if (MODE != 1) {
       double acc = 0.0;  // FP64 row sums for either value type (see the note above)
       if (one_chunk) {
-        if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, my_lo, my_hi, p0, acc);
-        else acc = row_dot(sv, sc, row0, xg, my_lo, my_hi, p0, acc);
+        if constexpr (C16) acc = row_dot(sv, sc16, row0, xg, my_lo, my_hi, a0, acc);
+        else acc = row_dot(sv, sc, row0, xg, my_lo, my_hi, a0, acc);
       } else {  // a tile with more than kChunk nonzeros: stream it through LDS chunk by chunk
         for (int cs = p0; cs < p1; cs += kChunk) {
           const int len = min(kChunk, p1 - cs);

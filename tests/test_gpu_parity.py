@@ -116,6 +116,49 @@ def test_spmv_column_offsets_at_their_limits(fab, ctx, reach_hi, reach_lo, ib):
     assert _rel(fab.spmv(opt, xt).cpu().numpy(), M.T @ x) <= 1e-14
 
 
+def _three_planes(N=256):
+    """Three N^2-row planes coupled at +-N^2 (diagonal 6, off-diagonals -1): columns past the
+    16-bit tile offsets, so the products read int32 indices."""
+    import types
+    n = 3 * N * N
+    i = np.arange(n, dtype=np.int64)
+    cols, vals, rows = [], [], []
+    for off, v in ((-N * N, -1.0), (0, 6.0), (N * N, -1.0)):
+        ok = (i + off >= 0) & (i + off < n)
+        rows.append(i[ok]); cols.append(i[ok] + off); vals.append(np.full(ok.sum(), v))
+    import scipy.sparse as sp
+    M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    return types.SimpleNamespace(n=n, nnz=M.nnz, rowptr=M.indptr.astype(np.int32),
+                                 colind=M.indices.astype(np.int32), vals=M.data)
+
+
+@pytest.mark.parametrize("build,dtype,ib", [(lambda: wl.convdiff_3d(20, 50.0), torch.float64, 2),
+                                            (lambda: wl.anisotropic_2d(37, 0.01), torch.float32, 2),
+                                            (_three_planes, torch.float64, 4),
+                                            (_three_planes, torch.float32, 4)])
+def test_csr_arrays_off_16_byte_boundaries(fab, ctx, build, dtype, ib):
+    """The fused kernel stages the CSR chunk in 16-byte loads when the operator's arrays allow it,
+    and in element loads otherwise: operators borrowing arrays that start 4 (or 8) bytes past a
+    16-byte boundary give the same bits, in the product and in a whole solve, as aligned ones."""
+    A = build()
+    aligned = _op(fab, ctx, A, dtype)
+    nnz = A.nnz
+    ci_big = torch.zeros(nnz + 4, dtype=torch.int32, device="cuda")
+    va_big = torch.zeros(nnz + 4, dtype=dtype, device="cuda")
+    ci_big[1:1 + nnz] = torch.as_tensor(A.colind, dtype=torch.int32, device="cuda")
+    va_big[1:1 + nnz] = torch.as_tensor(A.vals, dtype=dtype, device="cuda")
+    rp = torch.as_tensor(A.rowptr, dtype=torch.int32, device="cuda")
+    shifted = fab.CSROperator(ctx, rp, ci_big[1:1 + nnz], va_big[1:1 + nnz])
+    assert shifted.colind.data_ptr() % 16 != 0 and shifted.vals.data_ptr() % 16 != 0
+    assert shifted.index_bytes() == aligned.index_bytes() == ib
+    x = torch.as_tensor(wl.gaussian_vector(A.n, 3), dtype=dtype, device="cuda")
+    assert torch.equal(fab.spmv(shifted, x), fab.spmv(aligned, x))
+    kw = dict(m=16, k=2, d=64, zeta=8, seed=1, tol=1e-30, max_cycles=2, check=False)
+    xa, _ = fab.solve(aligned, x, "exp", t=1e-4, **kw)
+    xs, _ = fab.solve(shifted, x, "exp", t=1e-4, **kw)
+    assert torch.equal(xa, xs)
+
+
 def test_index_form_of_the_grid_operators(fab, ctx):
     """The widest coupling of an N^3 grid operator in natural order is +-N^2: at N = 128 it fits
     the 16-bit offsets, at N = 256 it does not (three N^2-row planes stand in for the grid)."""
