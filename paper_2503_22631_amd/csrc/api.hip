@@ -34,7 +34,8 @@ hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* ur
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
                          size_t bs);
 hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs);
+                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
+                              const double* parts, int nparts);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -399,12 +400,17 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
                                  d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs));
       if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
-      FAB_TRY(launch_reduce_parts(s, 0, d, g_spmv, q.parts, q.uraw, q.st, 0, nb, bs));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
-      // redoes it; in a batch that redundancy would multiply by the members)
-      if (nb == 1 && d <= 256 && p->k <= 8) {
+      // redoes it; in a batch that redundancy would multiply by the members).  With at most 64
+      // product blocks (small operators) the update's Gram-Schmidt wavefront also sums their
+      // partial sketches itself, each lane its entries in block order: one launch less per step.
+      const bool fused_orth = nb == 1 && d <= 256 && p->k <= 8;
+      const bool inline_sum = fused_orth && g_spmv <= 64;
+      if (!inline_sum) FAB_TRY(launch_reduce_parts(s, 0, d, g_spmv, q.parts, q.uraw, q.st, 0, nb, bs));
+      if (fused_orth) {
         if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
-        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs));
+        FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs,
+                                   inline_sum ? q.parts : nullptr, inline_sum ? g_spmv : 0));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
         if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));

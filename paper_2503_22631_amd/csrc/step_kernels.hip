@@ -611,7 +611,8 @@ template <int PER, int KW>
 __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const double* __restrict__ uraw,
                                           double* __restrict__ U, double* __restrict__ R, State* __restrict__ st,
                                           bool write, double* coef, double* inv_out, int* ok_out,
-                                          double* unew = nullptr) {
+                                          double* unew = nullptr, const double* __restrict__ parts = nullptr,
+                                          int nparts = 0) {
   const int lane = threadIdx.x & 63;
   const int lo = max(0, j - k + 1);
   double u[PER];
@@ -625,10 +626,32 @@ __device__ __forceinline__ void orth_wave(int j, int k, int m, int d, const doub
         upre[w][q] = (lo + w <= j && e < d) ? U[(size_t)(lo + w) * d + e] : 0.0;
       }
   }
+  if (parts == nullptr) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = lane + 64 * q;
-    u[q] = (e < d) ? uraw[e] : 0.0;
+    for (int q = 0; q < PER; ++q) {
+      const int e = lane + 64 * q;
+      u[q] = (e < d) ? uraw[e] : 0.0;
+    }
+  } else {
+    // S z from the product's per-block partials (small grids, nparts <= 64): each lane adds the
+    // partials of its own entries in block order, eight loads in flight (a fixed order: the same
+    // bits on every run; not the order of k_reduce_parts)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = lane + 64 * q;
+      double acc = 0.0;
+      if (e < d) {
+        const double* src = parts + (size_t)e * kMaxParts;
+        for (int p0 = 0; p0 < nparts; p0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) v[r] = (p0 + r < nparts) ? src[p0 + r] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) acc += v[r];
+        }
+      }
+      u[q] = acc;
+    }
   }
   double loc = 0.0;
 #pragma unroll
@@ -822,11 +845,12 @@ __device__ __forceinline__ void gram_load(const double* __restrict__ U, int d, i
   }
 }
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, bool INL = false>  // INL: S z summed from the partials (see orth_wave)
 __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
                                                           const double* __restrict__ uraw, double* __restrict__ U,
                                                           double* __restrict__ R, double* __restrict__ G,
-                                                          State* __restrict__ st, size_t bs) {
+                                                          State* __restrict__ st, size_t bs,
+                                                          const double* __restrict__ parts, int nparts) {
   __shared__ double s_coef[kMaxM + 1];
   __shared__ double s_inv;
   __shared__ int s_ok;
@@ -844,7 +868,7 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
     const int ne = gram_entries(j);
     double gv[kGramGroup][4], un[4] = {0.0, 0.0, 0.0, 0.0};
     orth_wave<4, KMAX>(j, k, m, d, bat(uraw, bs), bat(U, bs), bat(R, bs), st, blockIdx.x == 0, s_coef, &s_inv,
-                       &s_ok, un);
+                       &s_ok, un, INL ? bat(parts, bs) : nullptr, nparts);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
     if (!s_ok) return;  // breakdown: row j+1 does not exist
@@ -1360,21 +1384,33 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
 }
 
 hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
-                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs) {
+                              const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
+                              const double* parts, int nparts) {
+  if (parts && (nparts < 1 || nparts > 64)) return hipErrorInvalidValue;  // one partial per lane
   const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
+#define FAB_OU(TT, KK)                                                                                               \
+  if (parts)                                                                                                         \
+    hipLaunchKernelGGL((k_orth_update<TT, KK, true>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R, G, \
+                       st, bs, parts, nparts);                                                                       \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_orth_update<TT, KK, false>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R,  \
+                       G, st, bs, parts, nparts)
   if (dtype == 0) {
-    if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<double, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, uraw, U, R, G, st, bs);
-    else
-      hipLaunchKernelGGL((k_orth_update<double, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (double*)W, uraw, U, R, G, st, bs);
+    if (k <= 4) {
+      FAB_OU(double, 4);
+    } else {
+      FAB_OU(double, 8);
+    }
   } else {
-    if (k <= 4)
-      hipLaunchKernelGGL((k_orth_update<float, 4>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, uraw, U, R, G, st, bs);
-    else
-      hipLaunchKernelGGL((k_orth_update<float, 8>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (float*)W, uraw, U, R, G, st, bs);
+    if (k <= 4) {
+      FAB_OU(float, 4);
+    } else {
+      FAB_OU(float, 8);
+    }
   }
+#undef FAB_OU
   return hipGetLastError();
 }
 
