@@ -170,6 +170,18 @@ fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT);
  * arguments). */
 fab_status fab_op_index_bytes(const fab_op* A, int32_t* h_bytes);
 
+/* Cache policy of the stores of a single solve's step: the product's z and the
+ * window update's loads and new basis vector.  Not in the paper: a property of
+ * the device's 256 MB memory-side cache.  policy 0 = by size (the setting at
+ * creation): non-temporal when the CSR arrays the products read (values, the
+ * column indices or 16-bit offsets, the row pointers) exceed 256 MB, so that
+ * they stream through that cache on every product, else the default policy;
+ * 1 = the default policy; 2 = non-temporal.  The policy changes timing only,
+ * never results.  *h_streaming (optional) = 1 when the stores are non-temporal.
+ * Batched and ragged solves keep their own kernels' policy.  Errors:
+ * FAB_E_INVALID (A null, policy outside 0..2). */
+fab_status fab_op_store_policy(fab_op* A, int32_t policy, int32_t* h_streaming);
+
 /* Copy an operator's arrays (rowptr[n+1], colind[nnz], vals[nnz] in its dtype)
  * into caller-provided device buffers (test hook for fab_op_transpose). */
 fab_status fab_op_copy_arrays(fab_ctx* ctx, const fab_op* A, int32_t* rowptr, int32_t* colind, void* vals);

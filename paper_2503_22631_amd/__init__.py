@@ -104,6 +104,16 @@ class CSROperator:
         _lib.check(self.ctx.lib.fab_op_index_bytes(self.handle, ctypes.byref(v)), "fab_op_index_bytes", ok=(0,))
         return v.value
 
+    def store_policy(self, policy: str = "size") -> bool:
+        """Cache policy of a single solve's step stores: "size" (non-temporal when the CSR arrays
+        exceed the 256 MB memory-side cache), "default" or "streaming".  Returns True when the
+        stores are non-temporal.  Timing only: results do not change."""
+        code = {"size": 0, "default": 1, "streaming": 2}[policy]
+        v = ctypes.c_int32()
+        _lib.check(self.ctx.lib.fab_op_store_policy(self.handle, code, ctypes.byref(v)), "fab_op_store_policy",
+                   ok=(0,))
+        return bool(v.value)
+
     def arrays(self):
         """Copies of the operator's (rowptr, colind, vals) as device tensors."""
         dev = self.ctx.device

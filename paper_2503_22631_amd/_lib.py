@@ -15,7 +15,7 @@ STATUS = {
     -5: "FAB_E_DIVERGED", -6: "FAB_E_WORKSPACE",
 }
 EXPORTS = ["fab_create", "fab_destroy", "fab_csr_create", "fab_op_destroy", "fab_op_transpose",
-           "fab_op_index_bytes", "fab_op_copy_arrays", "fab_workspace_size", "fab_workspace_size_batched", "fab_solve",
+           "fab_op_index_bytes", "fab_op_store_policy", "fab_op_copy_arrays", "fab_workspace_size", "fab_workspace_size_batched", "fab_solve",
            "fab_solve_batched", "fab_workspace_size_ragged", "fab_solve_ragged", "fab_spmv", "fab_sketch_apply", "fab_sketch_apply_noalloc",
            "fab_sketch_table", "fab_cycle_debug", "fab_dot", "fab_batch_group", "fab_divergence_limit", "fab_timing_enable", "fab_timing_read",
            "fab_status_string", "fab_last_error"]
@@ -64,6 +64,7 @@ def load():
         "fab_op_destroy": ([c_void_p], c_int32),
         "fab_op_transpose": ([c_void_p, c_void_p, P(c_void_p)], c_int32),
         "fab_op_index_bytes": ([c_void_p, P(c_int32)], c_int32),
+        "fab_op_store_policy": ([c_void_p, c_int32, P(c_int32)], c_int32),
         "fab_op_copy_arrays": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
         "fab_dot": ([c_void_p, c_int64, c_void_p, c_void_p, c_void_p], c_int32),
         "fab_workspace_size": ([c_void_p, P(fab_params), c_int32, P(c_size_t)], c_int32),

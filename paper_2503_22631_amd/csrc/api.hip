@@ -21,7 +21,7 @@
 namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* parts, const State* st, int nb, int G, size_t bs);
+                              double* parts, const State* st, int nb, int G, size_t bs, int nts = 0);
 hipError_t launch_reduce_parts(hipStream_t, int e0, int len, int nparts, const double* parts, double* out,
                                const State* st, int skip, int nb, size_t bs);
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16);
@@ -35,7 +35,7 @@ hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, 
                          size_t bs);
 hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
-                              const double* parts, int nparts);
+                              const double* parts, int nparts, int nts);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -85,7 +85,7 @@ struct GraphKey {
   int m, k, d, zeta, nt, fun, method, nq, dtype;
   uint64_t seed;
   double tol;
-  int timing, nb, G, pad;
+  int timing, nb, G, nts;
   int64_t ldx;
   size_t bs;
   double div_limit;
@@ -141,7 +141,21 @@ struct fab_op {
   uint64_t serial = 0;  // unique per operator for the process: keys the cached graphs, whose kernel
                         // arguments hold this operator's arrays (an address can be reused after a destroy)
   int16_t* colrel = nullptr;  // library-owned 16-bit column offsets (see derive_col_offsets), else null
+  int nts = 0;  // the step's z and basis stores non-temporal (fab_op_store_policy; set by size_policy)
 };
+
+// The memory-side cache (MALL) of the device: 256 MB on MI355X.
+constexpr int64_t kMallBytes = (int64_t)256 << 20;
+
+// Cache policy of a single solve's step by operator size: CSR arrays as the products read them
+// (values, the 16-bit offsets when present else the int32 columns, row pointers) larger than the
+// memory-side cache stream through it on every product, and the step's vectors then store
+// non-temporal.  Measured: default policy 3% faster on a 154 MB CSR, non-temporal 2-3% per cycle
+// faster on a 1.4 GB one.
+static int size_policy(const fab_op* A) {
+  const int64_t es = A->dtype == FAB_F64 ? 8 : 4, ib = A->colrel ? 2 : 4;
+  return A->nnz * (es + ib) + 4 * (A->n + 1) > kMallBytes ? 1 : 0;
+}
 
 static uint64_t next_op_serial() {
   static std::atomic<uint64_t> counter{0};
@@ -398,7 +412,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
     if (!plain) {
       if (tev && (j == 0 || !ctx->timing_loop_only)) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
-                                 d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs));
+                                 d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs, A->nts));
       if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members).  With at most 64
@@ -410,7 +424,7 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       if (fused_orth) {
         if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs,
-                                   inline_sum ? q.parts : nullptr, inline_sum ? g_spmv : 0));
+                                   inline_sum ? q.parts : nullptr, inline_sum ? g_spmv : 0, A->nts));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
         if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
@@ -617,6 +631,7 @@ fab_status fab_csr_create(fab_ctx* ctx, int64_t n, int64_t nnz, const int32_t* r
     delete o;
     return st;
   }
+  o->nts = size_policy(o);
   *op = o;
   return FAB_OK;
 }
@@ -689,6 +704,7 @@ fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT) {
     (void)fab_op_destroy(o);
     return st;
   }
+  o->nts = size_policy(o);
   *AT = o;
   return FAB_OK;
 }
@@ -696,6 +712,13 @@ fab_status fab_op_transpose(fab_ctx* ctx, const fab_op* A, fab_op** AT) {
 fab_status fab_op_index_bytes(const fab_op* A, int32_t* h_bytes) {
   if (!A || !h_bytes) return FAB_E_INVALID;
   *h_bytes = A->colrel ? 2 : 4;
+  return FAB_OK;
+}
+
+fab_status fab_op_store_policy(fab_op* A, int32_t policy, int32_t* h_streaming) {
+  if (!A || policy < 0 || policy > 2) return FAB_E_INVALID;
+  A->nts = policy == 0 ? size_policy(A) : policy - 1;
+  if (h_streaming) *h_streaming = A->nts;
   return FAB_OK;
 }
 
@@ -947,6 +970,7 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
   key.ldx = ldx;
   key.bs = bs;
   key.div_limit = ctx->div_limit;
+  key.nts = A->nts;
   hipGraphExec_t exec = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) exec = g.exec;
@@ -1102,6 +1126,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   key.push_back((uintptr_t)divbits);
   for (int i = 0; i < nops; ++i) {  // operators by serial: a destroyed operator's address can be reused
     key.push_back((uintptr_t)ops[i]->serial);
+    key.push_back((uintptr_t)ops[i]->nts);
     key.push_back((uintptr_t)x[i]);
   }
   auto cycle_of = [&](int i, hipStream_t st) {

@@ -293,9 +293,10 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_s
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           int d, int zeta, T scale, uint32_t k0, uint32_t k1,
                                                           double* __restrict__ parts,
-                                                          const State* __restrict__ st, size_t bs) {
+                                                          const State* __restrict__ st, size_t bs, int nts) {
   extern __shared__ unsigned char smem_raw[];
-  // This block serves batch member blockIdx.y (0 for single solves).
+  // This block serves batch member blockIdx.y (0 for single solves).  nts: store z non-temporal
+  // (operators whose CSR arrays exceed the memory-side cache; see k_orth_update).
   const int r0 = blockIdx.y;
   {
     const State* sg = st ? bat(st, bs, r0) : nullptr;
@@ -359,7 +360,10 @@ __global__ __launch_bounds__(kThreads, (spmv_min_waves<T, C16>())) void k_spmv_s
         }
       }
       z = (T)acc;
-      if (live) bat(y, bs, r0)[row] = z;
+      if (live) {
+        if (nts) __builtin_nontemporal_store(z, bat(y, bs, r0) + row);
+        else bat(y, bs, r0)[row] = z;
+      }
     } else if (live) {
       z = xg[row];
     }
@@ -758,28 +762,36 @@ constexpr int kOuBlocksPerCu = 2;
 // Raw buffer accesses (untyped, byte offsets): the hardware checks every lane's offset against the
 // resource's size, returns 0 for a load beyond it and drops a store beyond it, so a ragged batch
 // needs no branch.  Word 3 of the gfx9-family descriptor: 32-bit data format (a valid format is
-// required for untyped accesses), all other fields zero.  Loads and stores use the default cache
-// policy: the new basis vector is gathered by the next step's product and read by the next
-// windows, and z and the window columns were written moments ago (non-temporal hints on these
-// accesses measured 0.5 us per step slower once the operator's CSR arrays left room in the
-// memory-side cache).
+// required for untyped accesses), all other fields zero.  The cache policy is the operator's: the
+// default one when its CSR arrays fit the 256 MB memory-side cache with room to spare, since the
+// new basis vector is gathered by the next step's product and read by the next windows, and z and
+// the window columns were written moments ago (non-temporal hints measured 0.5 us per step slower
+// on a 154 MB CSR); non-temporal when the CSR arrays stream through that cache anyway, where the
+// default policy lets the vectors evict the arrays' lines for nothing (measured 2-3% per cycle
+// on a 1.4 GB CSR).
 constexpr int kBufWord3 = 0x00020000;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufWord3);
 }
+// AUX: the cache-policy operand of the access, 0 (default) or kAuxNt (non-temporal).
+constexpr int kAuxNt = 2;
+template <int AUX>
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
 }
+template <int AUX>
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
 }
+template <int AUX>
 __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
 }
+template <int AUX>
 __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
 }
 
 // Elements of one batch: those of [b0, b0 + kOuBatch) below n (none when b0 >= n: a size-0
@@ -788,7 +800,7 @@ __device__ __forceinline__ int ou_count(int n, int64_t b0) {
   return b0 < n ? (int)min((int64_t)kOuBatch, (int64_t)n - b0) : 0;
 }
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, size_t ld,
                                         int nw, int64_t b0, int t, T (&zv)[kOuPer], T (&wv)[kOuPer][KMAX]) {
   const int cnt = ou_count(n, b0);
@@ -801,15 +813,15 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
 #pragma unroll
   for (int e = 0; e < kOuPer; ++e) {
     const int off = (e * kThreads + t) * (int)sizeof(T);
-    zv[e] = buf_load(rz, off, T());
+    zv[e] = buf_load<AUX>(rz, off, T());
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) wv[e][q] = buf_load(rw[q], off, T());
+    for (int q = 0; q < KMAX; ++q) wv[e][q] = buf_load<AUX>(rw[q], off, T());
   }
 }
 
 // FP64 arithmetic for either value type: z is nearly in the span of the window, so the difference
 // cancels; only the stored w_{j+1} is rounded to T.  coef is zero beyond the window.
-template <typename T, int KMAX>
+template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0, int t, const double (&coef)[KMAX],
                                          double inv, const T (&zv)[kOuPer], const T (&wv)[kOuPer][KMAX]) {
   const int cnt = ou_count(n, b0);
@@ -819,7 +831,29 @@ __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0,
     double v = (double)zv[e];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
-    buf_store((T)(v * inv), rz, (e * kThreads + t) * (int)sizeof(T));
+    buf_store<AUX>((T)(v * inv), rz, (e * kThreads + t) * (int)sizeof(T));
+  }
+}
+
+// The update's batches after the first: two register sets in turn; the prefetch past the block's
+// last batch has size 0 (no memory traffic), so every trip issues the same loads and stores
+// (loads at raised wave priority, as in the fused product: measured 0.1 us per step).
+template <typename T, int KMAX, int AUX, typename Start>
+__device__ __forceinline__ void ou_stream(T* __restrict__ out, const T* __restrict__ base, int n, size_t ld, int nw,
+                                          int cnt, Start start, int t, const double (&coef)[KMAX], double inv,
+                                          T (&za)[kOuPer], T (&wa)[kOuPer][KMAX], T (&zb)[kOuPer],
+                                          T (&wb)[kOuPer][KMAX]) {
+  for (int it = 0;;) {
+    __builtin_amdgcn_s_setprio(2);
+    ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
+    __builtin_amdgcn_s_setprio(0);
+    ou_store<T, KMAX, AUX>(out, n, start(it), t, coef, inv, za, wa);
+    if (++it >= cnt) break;
+    __builtin_amdgcn_s_setprio(2);
+    ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(it + 1), t, za, wa);
+    __builtin_amdgcn_s_setprio(0);
+    ou_store<T, KMAX, AUX>(out, n, start(it), t, coef, inv, zb, wb);
+    if (++it >= cnt) break;
   }
 }
 
@@ -845,7 +879,9 @@ __device__ __forceinline__ void gram_load(const double* __restrict__ U, int d, i
   }
 }
 
-template <typename T, int KMAX, bool INL = false>  // INL: S z summed from the partials (see orth_wave)
+// INL: S z summed from the partials (see orth_wave); AUX: the cache policy of the update's loads and
+// stores (see buf_rsrc)
+template <typename T, int KMAX, bool INL = false, int AUX = 0>
 __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k, int m, int d, T* __restrict__ W,
                                                           const double* __restrict__ uraw, double* __restrict__ U,
                                                           double* __restrict__ R, double* __restrict__ G,
@@ -901,28 +937,14 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   const int cnt = (nbat - 1 - (int)blockIdx.x) / (int)gridDim.x + 1;
   auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * kOuBatch; };
   T za[kOuPer], wa[kOuPer][KMAX], zb[kOuPer], wb[kOuPer][KMAX];
-  ou_load<T, KMAX>(out, base, n, ld, nw, start(0), t, za, wa);
+  ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(0), t, za, wa);
   __syncthreads();
   if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
   const double inv = s_inv;
   double coef[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) coef[q] = (q < nw) ? s_coef[q] : 0.0;
-  // two register sets in turn; the prefetch past the block's last batch has size 0 (no memory
-  // traffic), so every trip issues the same loads and stores
-  // (loads at raised wave priority, as in the fused product: measured 0.1 us per step)
-  for (int it = 0;;) {
-    __builtin_amdgcn_s_setprio(2);
-    ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
-    __builtin_amdgcn_s_setprio(0);
-    ou_store<T, KMAX>(out, n, start(it), t, coef, inv, za, wa);
-    if (++it >= cnt) break;
-    __builtin_amdgcn_s_setprio(2);
-    ou_load<T, KMAX>(out, base, n, ld, nw, start(it + 1), t, za, wa);
-    __builtin_amdgcn_s_setprio(0);
-    ou_store<T, KMAX>(out, n, start(it), t, coef, inv, zb, wb);
-    if (++it >= cnt) break;
-  }
+  ou_stream<T, KMAX, AUX>(out, base, n, ld, nw, cnt, start, t, coef, inv, za, wa, zb, wb);
 }
 
 // w_{j+1} = (z - sum_{i=lo..j} r_i w_i) / rho, in place on column j+1 of W (n x (m+1)).
@@ -1218,7 +1240,7 @@ size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16) {
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
                                        const int16_t* cr, const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
-                                       double* parts, const State* st, int nb, int G, size_t bs) {
+                                       double* parts, const State* st, int nb, int G, size_t bs, int nts) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
   if (G > 1 && (mode == 2 || G % kWaves != 0 || G > kGroupMax)) return hipErrorInvalidValue;
@@ -1231,17 +1253,17 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
                        scale, k0, k1, parts, st, nb, G, bs);                                                      \
   else if (c16)                                                                                                   \
     hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, (M != 1)>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, \
-                       zeta, scale, k0, k1, parts, st, bs);                                                       \
+                       zeta, scale, k0, k1, parts, st, bs, nts);                                                  \
   else                                                                                                            \
     hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
-                       scale, k0, k1, parts, st, bs)
+                       scale, k0, k1, parts, st, bs, nts)
 #define FAB_LS(Z)                                                                                                 \
   if (c16)                                                                                                        \
     hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d,    \
-                       zeta, scale, k0, k1, parts, st, bs);                                                       \
+                       zeta, scale, k0, k1, parts, st, bs, nts);                                                  \
   else                                                                                                            \
     hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
-                       scale, k0, k1, parts, st, bs)
+                       scale, k0, k1, parts, st, bs, nts)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -1349,14 +1371,14 @@ int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta, bool c16) {
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* parts, const State* st, int nb, int G, size_t bs) {
+                              double* parts, const State* st, int nb, int G, size_t bs, int nts) {
   // the partials need a grid of whole XCD rounds within the partial buffer (part_index)
   if (mode != 2 && (grid < kXcds || grid > kMaxParts || grid % kXcds != 0)) return hipErrorInvalidValue;
   if (dtype == 0)
     return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, cr, (const double*)va, (const double*)x,
-                                        (double*)y, d, zeta, seed, parts, st, nb, G, bs);
+                                        (double*)y, d, zeta, seed, parts, st, nb, G, bs, nts);
   return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, cr, (const float*)va, (const float*)x, (float*)y, d,
-                                     zeta, seed, parts, st, nb, G, bs);
+                                     zeta, seed, parts, st, nb, G, bs, nts);
 }
 
 hipError_t launch_reduce_parts(hipStream_t s, int e0, int len, int nparts, const double* parts, double* out,
@@ -1385,32 +1407,41 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
 
 hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
-                              const double* parts, int nparts) {
+                              const double* parts, int nparts, int nts) {
   if (parts && (nparts < 1 || nparts > 64)) return hipErrorInvalidValue;  // one partial per lane
   const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
-#define FAB_OU(TT, KK)                                                                                               \
-  if (parts)                                                                                                         \
-    hipLaunchKernelGGL((k_orth_update<TT, KK, true>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R, G, \
-                       st, bs, parts, nparts);                                                                       \
-  else                                                                                                               \
-    hipLaunchKernelGGL((k_orth_update<TT, KK, false>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R,  \
-                       G, st, bs, parts, nparts)
+#define FAB_OU2(TT, KK, INL, AUX)                                                                              \
+  hipLaunchKernelGGL((k_orth_update<TT, KK, INL, AUX>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R, \
+                     G, st, bs, parts, nparts)
+#define FAB_OU(TT, KK)               \
+  if (parts) {                       \
+    if (nts) {                       \
+      FAB_OU2(TT, KK, true, kAuxNt); \
+    } else {                         \
+      FAB_OU2(TT, KK, true, 0);      \
+    }                                \
+  } else if (nts) {                  \
+    FAB_OU2(TT, KK, false, kAuxNt);  \
+  } else {                           \
+    FAB_OU2(TT, KK, false, 0);       \
+  }
   if (dtype == 0) {
     if (k <= 4) {
-      FAB_OU(double, 4);
+      FAB_OU(double, 4)
     } else {
-      FAB_OU(double, 8);
+      FAB_OU(double, 8)
     }
   } else {
     if (k <= 4) {
-      FAB_OU(float, 4);
+      FAB_OU(float, 4)
     } else {
-      FAB_OU(float, 8);
+      FAB_OU(float, 8)
     }
   }
 #undef FAB_OU
+#undef FAB_OU2
   return hipGetLastError();
 }
 

@@ -520,6 +520,29 @@ def test_solves_are_bitwise_reproducible(fab, ctx, dtype):
     assert runs[0][1]["cycles"] > 30, runs[0][1]  # the sensitive regime was exercised
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,k", [(16, 2), (40, 6)])
+def test_store_policy_changes_no_bits(fab, ctx, dtype, N, k):
+    """The step's cache policy (default, or non-temporal z and update) moves the same values: a
+    solve under either gives the same bits and cycle count, for both update widths (k <= 4 and
+    k <= 8) and with the product's partial sketches summed by the update (16^3) or by their own
+    launch (40^3)."""
+    A = wl.shifted_laplacian_3d(N, 1.0)
+    op = _op(fab, ctx, A, dtype)
+    b = torch.as_tensor(wl.gaussian_vector(A.n, 3), dtype=dtype, device="cuda")
+    kw = dict(m=30, k=k, d=120, zeta=8, seed=1, tol=1e-7, spec=_laplacian_3d_interval(N, 1.0), max_cycles=60)
+    assert not op.store_policy("size")  # small CSR arrays: the default policy
+    runs = []
+    for pol in ("default", "streaming", "default"):
+        assert op.store_policy(pol) == (pol == "streaming")
+        x, info = fab.solve(op, b, "invsqrt", **kw)
+        runs.append((x.clone(), info))
+    op.store_policy("size")
+    assert runs[0][1]["status"] == "FAB_OK", runs[0][1]
+    for x, info in runs[1:]:
+        assert info["cycles"] == runs[0][1]["cycles"] and torch.equal(x, runs[0][0])
+
+
 # --------------------------------------------------------------- full-size workload (bench shape)
 def test_convdiff_128_full_size(fab, ctx):
     """3-D convection-diffusion, 128^3 (n = 2.1M), Pe 50, exp(-1e-4 A) b, m=50, k=4, d=200, zeta=8:
@@ -535,6 +558,7 @@ def test_convdiff_128_full_size(fab, ctx):
     ref = exact.kron_exp_fab(b, factors, 1e-4)
     assert info["status"] == "FAB_OK", info
     assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-8
+    assert not op.store_policy("size")  # 154 MB of CSR arrays: the default cache policy
 
 
 def test_timing_hooks_count_launches(fab, ctx):
@@ -660,6 +684,13 @@ def test_invsqrt_256_full_size(fab, ctx, dtype, d, tol, bar):
     if d == 120:
         x2, info2 = fab.solve(op, bt, "invsqrt", **kw)
         assert info2["cycles"] == info["cycles"] and torch.equal(x2[:, 0], x)
+        # the CSR arrays exceed the memory-side cache: the step streams its stores by default;
+        # the other cache policy gives the same bits
+        assert op.store_policy("size")
+        assert not op.store_policy("default")
+        x3, info3 = fab.solve(op, bt, "invsqrt", **kw)
+        op.store_policy("size")
+        assert info3["cycles"] == info["cycles"] and torch.equal(x3[:, 0], x)
 
 
 # ---------------------------------------------------- adjoint and differentiation (A^T, autograd)
