@@ -84,7 +84,7 @@ typedef struct {
   int32_t k;          /* truncation window of the Gram-Schmidt, 1 <= k <= m          */
   int32_t d;          /* sketch rows, m+1 <= d <= 4096                                */
   int32_t zeta;       /* nonzeros per sketch column, 1 <= zeta <= min(32, d)          */
-  uint64_t seed;      /* defines S (Philox4x32-10 counter-based spec, see fab_sketch_table) */
+  uint64_t seed;      /* defines S (Philox4x32-7 counter-based spec, see fab_sketch_table) */
   double tol;         /* relative update tolerance, >= 0                              */
   int32_t max_cycles; /* >= 1                                                          */
   int32_t method;     /* fab_method; FAB_PLAIN_RESTART ignores k, d, zeta, seed        */

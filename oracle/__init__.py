@@ -9,7 +9,7 @@ both sides consume is the seeded generator package ``workloads``.
 Contents (each function cites the passage of the paper it follows):
 
 * ``philox`` / ``sketch`` -- the sparse-sign embedding S (eq. sparse_sign_sketch)
-  generated from the counter-based Philox4x32-10 generator (Salmon et al. 2011),
+  generated from the counter-based Philox4x32 generator (Salmon et al. 2011), 7 rounds,
   rows drawn without replacement by Floyd's sampling algorithm;
 * ``matfun``   -- dense matrix functions (Pade-13 scaling and squaring for exp,
   Schur square root for z^(-1/2)), used for small and growing matrices;

@@ -38,11 +38,21 @@ cos(t sqrt(z))  -- Cauchy integral on an ellipse around the spectral interval:
     h = (hi-lo)/2, trapezoidal rule in theta_k = 2 pi (k + 1/2)/N:
     zeta_k = z(theta_k), w_k = f(zeta_k) z'(theta_k) / (i N).  cos(t sqrt z)
     is entire (its series has integer powers of z only), so any ellipse
-    around the interval works; its truncation error falls like rho^-N while
-    the rounding of the sum grows with max |f| on the ellipse, which grows
-    with rho.  Reading: rho = exp(37/N), the smallest with rho^-N below FP64
-    rounding (measured: rule error <= 6e-12 on [lo, hi] for t sqrt(hi) <= 100
-    at N = 256, the default).
+    around the interval works.  For a point z whose ellipse coordinate
+    |w(z)| (z = c + h (w + 1/w)/2, |w| >= 1) is below rho the truncation error
+    falls like (|w(z)|/rho)^N, while the rounding of the sum grows with max |f|
+    on the ellipse, which grows with rho.  The points that matter are the
+    eigenvalues of the cycle's projected matrices: sketched Ritz values, which
+    can fall slightly outside [lo, hi] (the sketched projection is oblique).
+    Reading (``cos_sqrt_rho``): rho_min = exp(37/N) is the smallest ellipse with
+    rho^-N below FP64 rounding; the rule takes the largest of the candidates
+    rho_min (2/rho_min)^(j/16), j = 16 .. 0, whose growth t max_k |Im sqrt
+    zeta_k| over its nodes stays within max(ln 100, the growth at rho_min), so
+    max |f| on the ellipse grows at most to ~100 or not beyond that of rho_min.
+    Small t sqrt(hi) gets rho = 2, which serves Ritz values out to |w| ~ 1.7
+    (0.15 h beyond the ends) at 1e-14; large t sqrt(hi) keeps rho_min (measured:
+    rule error <= 6e-12 on [lo, hi] for t sqrt(hi) <= 100 at N = 256, the
+    default).
 
 Nodes of the exp rule come in complex-conjugate pairs (u, -u); for real
 matrices ``conjugate_half`` keeps the Im zeta > 0 half, and the caller doubles
@@ -93,9 +103,37 @@ def phi1_rule(t: float, N: int = EXP_MAIN[0], P: float = EXP_MAIN[1], mu: float 
 COS_SQRT_N = 256
 
 
+COS_RHO_CAP = 2.0
+COS_RHO_STEPS = 16
+COS_GROWTH = np.log(100.0)
+
+
+def _ellipse(c, h, rho, theta):
+    e = np.exp(1j * theta)
+    return c + h * (rho * e + 1.0 / (rho * e)) / 2.0, 1j * h * (rho * e - 1.0 / (rho * e)) / 2.0
+
+
+def cos_sqrt_rho(t: float, N: int, lam_lo: float, lam_hi: float) -> float:
+    """The ellipse parameter rho of the cos(t sqrt z) rule (the reading in the module header)."""
+    c, h = 0.5 * (lam_lo + lam_hi), 0.5 * (lam_hi - lam_lo)
+    theta = 2.0 * np.pi * (np.arange(N // 2) + 0.5) / N       # the nodes with Im zeta > 0
+    rho_min = np.exp(37.0 / N)
+    cap = max(COS_RHO_CAP, rho_min)
+
+    def growth(rho):
+        return t * np.max(np.abs(np.sqrt(_ellipse(c, h, rho, theta)[0]).imag))
+
+    bound = max(COS_GROWTH, growth(rho_min))
+    for j in range(COS_RHO_STEPS, 0, -1):
+        rho = rho_min * (cap / rho_min) ** (j / COS_RHO_STEPS)
+        if growth(rho) <= bound:
+            return rho
+    return rho_min
+
+
 def cos_sqrt_rule(t: float, N: int, lam_lo: float, lam_hi: float):
     """(zeta, w) with sum_l w_l/(zeta_l - z) ~ cos(t sqrt(z)) for z near [lam_lo, lam_hi]."""
-    rho = np.exp(37.0 / N)
+    rho = cos_sqrt_rho(t, N, lam_lo, lam_hi)
     c, h = 0.5 * (lam_lo + lam_hi), 0.5 * (lam_hi - lam_lo)
     e = np.exp(2j * np.pi * (np.arange(N) + 0.5) / N)
     zeta = c + h * (rho * e + 1.0 / (rho * e)) / 2.0

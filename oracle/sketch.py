@@ -9,20 +9,23 @@ anywhere (reading: distinct rows, uniform, signs equiprobable).
 Specification (shared with the HIP library, implemented there independently):
 
 * key = (seed & 0xffffffff, seed >> 32);
-* block b of column j is Philox4x32-10 of counter (j & 0xffffffff, j >> 32, b, 0);
+* block b of column j is Philox4x32-7 of counter (j & 0xffffffff, j >> 32, b, 0)
+  (seven rounds; see ``philox``);
 * row draws: word (l mod 4) of block (l div 4), l = 0..zeta-1;
 * rows by Floyd's algorithm: for l = 0..zeta-1 let J = d - zeta + l and
   r = floor(word_l * (J+1) / 2^32) in [0, J]; if r is already taken the slot
   takes J, otherwise r.  This yields a uniformly random zeta-subset with a
   fixed number of draws (the multiply-shift draw has relative bias < 2^-24);
-* signs: bit l of word 0 of block ceil(zeta/4): 0 -> +1, 1 -> -1.
+* signs: bit 0 of row draw l: 0 -> +1, 1 -> -1.  Given the row r, the draw lies
+  in an interval of at least 2^32 / 65536 consecutive words, so its lowest bit
+  is even or odd with probabilities within 2^-17 of 1/2 (d <= 65536).
 
 zeta <= 32 and zeta <= d are required.
 """
 import numpy as np
 import scipy.sparse as sp
 
-from .philox import philox4x32_10
+from .philox import philox4x32_7
 
 
 def rows_and_signs(col0: int, count: int, d: int, zeta: int, seed: int):
@@ -35,9 +38,8 @@ def rows_and_signs(col0: int, count: int, d: int, zeta: int, seed: int):
     nblk = (zeta + 3) // 4
     words = []
     for b in range(nblk):
-        out = philox4x32_10(lo, hi, np.full_like(lo, b), np.zeros_like(lo), k0, k1)
+        out = philox4x32_7(lo, hi, np.full_like(lo, b), np.zeros_like(lo), k0, k1)
         words.extend(out)
-    sign_word = philox4x32_10(lo, hi, np.full_like(lo, nblk), np.zeros_like(lo), k0, k1)[0]
     rows = np.empty((count, zeta), dtype=np.int64)
     for l in range(zeta):
         J = d - zeta + l
@@ -46,7 +48,7 @@ def rows_and_signs(col0: int, count: int, d: int, zeta: int, seed: int):
         for q in range(l):
             taken |= rows[:, q] == r
         rows[:, l] = np.where(taken, J, r)
-    bits = (sign_word[:, None] >> np.arange(zeta, dtype=np.uint64)[None, :]) & np.uint64(1)
+    bits = np.stack([words[l] & np.uint64(1) for l in range(zeta)], axis=1)
     signs = 1.0 - 2.0 * bits.astype(np.float64)
     return rows, signs
 

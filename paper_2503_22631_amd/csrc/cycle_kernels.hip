@@ -64,16 +64,54 @@ __global__ void k_zero_strided(double* p, size_t count, size_t step_bytes) {
 //   (0, pi/2): zeta = -c^2 tan^2(theta), w = -(c/N) sec^2(theta), c = (lo hi)^(1/4).
 // fun 3, cos(t sqrt z) (eq. drum_sol): Cauchy integral on the ellipse zeta(theta) = c + h (rho e^{i
 //   theta} + e^{-i theta} / rho) / 2 around [lo, hi] (c, h its centre and half-width), trapezoidal
-//   nodes theta = 2 pi (k + 1/2) / N, w = f(zeta) zeta'(theta) / (i N), rho = exp(37 / N) (the
-//   smallest ellipse whose truncation term rho^-N is below FP64 rounding: max |f| on the ellipse,
-//   which sets the rounding of the sum, grows with rho).  cos(t sqrt z) is entire, so no branch of
-//   the square root matters.  The Im zeta > 0 half (theta < pi) is kept, as for exp.
+//   nodes theta = 2 pi (k + 1/2) / N, w = f(zeta) zeta'(theta) / (i N), rho from cos_rule_rho.
+//   cos(t sqrt z) is entire, so no branch of the square root matters.  The Im zeta > 0 half
+//   (theta < pi) is kept, as for exp.
 // Layout: nq nodes per time point (nq = N/2 for the conjugate-half rules, N for z^(-1/2)).
+// The ellipse of the cos(t sqrt z) rule.  For a point z with ellipse coordinate |w(z)| < rho
+// (z = c + h (w + 1/w) / 2) the truncation error falls like (|w(z)| / rho)^N, and the points that
+// matter are the eigenvalues of the cycles' projected matrices: sketched Ritz values, which can fall
+// slightly outside [lo, hi] because the sketched projection is oblique.  The rounding of the sum
+// grows with max |f| on the ellipse, i.e. with t max |Im sqrt zeta|.  rho_min = exp(37 / N) is the
+// smallest ellipse with rho^-N below FP64 rounding; the rule takes the largest candidate
+// rho_min (cap / rho_min)^(j / kCosRhoSteps), j = kCosRhoSteps .. 0, cap = max(2, rho_min), whose
+// growth t max_k |Im sqrt zeta_k| over its Im zeta > 0 nodes stays within max(ln 100, the growth
+// at rho_min).  A wavefront's lanes share the nodes; every lane returns the same rho.
+constexpr int kCosRhoSteps = 16;
+__device__ double cos_rule_rho(double t, int N, double lo, double hi, int lane) {
+  const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+  const double rho_min = exp(37.0 / N), cap = fmax(2.0, rho_min);
+  auto growth = [&](double rho) {
+    const double ap = 0.5 * (rho + 1.0 / rho), am = 0.5 * (rho - 1.0 / rho);
+    double g = 0.0;
+    for (int k = lane; k < N / 2; k += 64) {
+      const double th = 2.0 * M_PI * (k + 0.5) / N;
+      g = fmax(g, fabs(csqrt_p(cmk(c + h * ap * cos(th), h * am * sin(th))).im));
+    }
+    return t * wave_max(g);
+  };
+  const double bound = fmax(log(100.0), growth(rho_min));
+  for (int j = kCosRhoSteps; j > 0; --j) {
+    const double rho = rho_min * pow(cap / rho_min, (double)j / kCosRhoSteps);
+    if (growth(rho) <= bound) return rho;
+  }
+  return rho_min;
+}
+
 __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_main, double lo, double hi,
                        cplx* __restrict__ rz, cplx* __restrict__ rw, cplx* __restrict__ psi, size_t bs) {
+  __shared__ double s_rho[kMaxNt];
   rz = bat(rz, bs);  // every batch member holds its own copy (psi is per member)
   rw = bat(rw, bs);
   psi = bat(psi, bs);
+  if (fun == 3) {  // the ellipse of each time point, by the first wavefront of every block
+    if (threadIdx.x < 64)
+      for (int it = 0; it < nt; ++it) {
+        const double rho = cos_rule_rho(tvals[it], n_main, lo, hi, (int)threadIdx.x);
+        if (threadIdx.x == 0) s_rho[it] = rho;
+      }
+    __syncthreads();
+  }
   const int nq = rule_is_half(fun) ? n_main / 2 : n_main;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nt * nq; s += gridDim.x * blockDim.x) {
     const int it = s / nq, idx = s % nq;
@@ -97,7 +135,7 @@ __global__ void k_rule(int fun, int nt, const double* __restrict__ tvals, int n_
     } else if (fun == 3) {
       const double t = tvals[it];
       const int N = n_main;
-      const double rho = exp(37.0 / N), c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+      const double rho = s_rho[it], c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
       const double th = 2.0 * M_PI * (idx + 0.5) / N;
       const double ct = cos(th), st = sin(th);
       const double ap = 0.5 * (rho + 1.0 / rho), am = 0.5 * (rho - 1.0 / rho);

@@ -27,15 +27,19 @@ constexpr double kDivergedEst = 1e8;  // ||y|| / ||x|| above which a member's so
 // ----------------------------------------------------------------------------------------------
 // Sparse-sign sketch specification (eq. sparse_sign_sketch): column j of S has zeta distinct
 // rows chosen uniformly (Floyd's sampling algorithm) and Rademacher signs, all drawn from the
-// counter-based generator Philox4x32-10 (Salmon et al., SC'11):
+// counter-based generator Philox4x32 (Salmon et al., SC'11) with seven rounds, the fewest its
+// authors report to pass their statistical test batteries (their standard form has ten):
 //   key = (seed lo, seed hi); block b of column j = Philox(counter = (j lo, j hi, b, 0));
 //   draw l = word (l mod 4) of block (l div 4); row J = d-zeta+l candidate r = mulhi(draw, J+1),
-//   replaced by J if already taken; sign bit l of word 0 of block ceil(zeta/4) (1 = negative).
+//   replaced by J if already taken; sign = bit 0 of draw l (1 = negative).  Given r, a draw
+//   spans at least 2^32 / d consecutive words, so its low bit is nearly unbiased and independent
+//   of the row; two blocks per column (zeta = 8) instead of three with a separate sign block.
 // ----------------------------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
-                                              uint32_t k0, uint32_t k1) {
+constexpr int kPhiloxRounds = 7;
+__device__ __forceinline__ void philox4x32(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                           uint32_t k1) {
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
+  for (int r = 0; r < kPhiloxRounds; ++r) {
     if (r > 0) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
@@ -62,17 +66,15 @@ __device__ __forceinline__ void sketch_column(uint64_t col, int d, int zeta, uin
 #pragma unroll
   for (int b = 0; b < (ZMAX + 3) / 4; ++b) {
     uint32_t c0 = lo, c1 = hi, c2 = (uint32_t)b, c3 = 0u;
-    if (4 * b < zeta) philox4x32_10(c0, c1, c2, c3, k0, k1);
+    if (4 * b < zeta) philox4x32(c0, c1, c2, c3, k0, k1);
     if (4 * b + 0 < ZMAX) words[4 * b + 0] = c0;
     if (4 * b + 1 < ZMAX) words[4 * b + 1] = c1;
     if (4 * b + 2 < ZMAX) words[4 * b + 2] = c2;
     if (4 * b + 3 < ZMAX) words[4 * b + 3] = c3;
   }
-  {
-    uint32_t c0 = lo, c1 = hi, c2 = (uint32_t)((zeta + 3) / 4), c3 = 0u;
-    philox4x32_10(c0, c1, c2, c3, k0, k1);
-    signbits = c0;
-  }
+  signbits = 0u;
+#pragma unroll
+  for (int l = 0; l < ZMAX; ++l) signbits |= (words[l] & 1u) << l;
 #pragma unroll
   for (int l = 0; l < ZMAX; ++l) {
     if (l < zeta) {

@@ -214,7 +214,7 @@ _OPS = {"lap32": lambda: wl.laplacian_2d(32), "lap64": lambda: wl.laplacian_2d(6
 @pytest.mark.parametrize("name,m,k,d", [("lap32", 8, 1, 40), ("lap64", 8, 1, 40), ("cd12", 12, 1, 40)])
 def test_whitening_from_the_gram_matrix_below_the_condition_limit(fab, ctx, name, m, k, d):
     """A window of one vector (k = 1) leaves the sketched basis ill-conditioned, kappa_F(T) from
-    270 to 480 here, below the limit of 1e3: T comes from the Cholesky factor of the Gram matrix
+    290 to 480 here, below the limit of 1e3: T comes from the Cholesky factor of the Gram matrix
     kept by the steps and equals the oracle's Householder factor."""
     A = _OPS[name]()
     op = _op(fab, ctx, A)
@@ -229,9 +229,9 @@ def test_whitening_from_the_gram_matrix_below_the_condition_limit(fab, ctx, name
     assert _rel(g["T"].cpu().numpy(), c.T) <= 1e-10
 
 
-@pytest.mark.parametrize("name,m,k,d", [("lap64", 40, 2, 82), ("cd12", 16, 1, 40)])
+@pytest.mark.parametrize("name,m,k,d", [("lap64", 40, 2, 80), ("cd12", 16, 1, 40)])
 def test_whitening_refuses_the_gram_matrix_above_the_condition_limit(fab, ctx, name, m, k, d):
-    """kappa_F(T) of 1.9e3 and 4.6e3 while every pivot keeps at least 3e-4 of its column: the
+    """kappa_F(T) of 2.0e3 in both cases while every pivot keeps at least 2e-4 of its column: the
     condition test, not the pivots, sends these cycles to the Householder QR, whose T equals the
     oracle's.  (The first case is the kind of cycle that, factored by Cholesky, moved a 256^3
     z^(-1/2) solve off its path.)"""
@@ -616,11 +616,18 @@ def _laplacian_3d_interval(N, shift):
 
 
 FP32_TOL = 2e-6   # FP32 values and basis (FP64 row sums, bins and cycle end; x in FP64), small grids
-# Batched anisotropic FP32 workload (1024^2, t up to 1e-3, t lambda_max ~ 4e3, ~30 cycles): FP32
-# rounding of each cycle's basis sets a floor that a tighter tol does not move (measured, worst of
-# sampled members: 3e-7 at t = 1e-5 rising to 2.5e-5 at t = 1e-3, at tol 1e-6 and 1e-7 alike; FP64
-# at the same settings: 3.6e-7 at tol 1e-6, 7.6e-9 at tol 1e-7).  Bar: twice the floor.
-FP32_BATCH_TOL = 5e-5
+
+
+def fp32_exp_floor(t, lam_max, b, fb):
+    """Error floor of exp(-t A) b with an FP32 basis (x and every small part in FP64): rounding each
+    basis vector to FP32 is a relative backward error of u = 2^-24 in the cycle's Arnoldi relation,
+    which the propagator exp(-t A) carries into x with a factor up to t ||A|| in norm, against
+    ||b||; relative to ||f(A) b|| that is u t lambda_max ||b|| / ||f(A) b||.  A tighter tol does
+    not move this floor.  On the batched anisotropic workload (1024^2, d = 4m) the measured error of
+    sampled members stays 4 - 600 times below it over 30 sketches (10 seeds, three generator
+    variants), while the floor itself spans 4e-6 to 1.3e-3 from sketch to sketch: the d = 4m
+    sketch's distortion sets how much of the bound is used."""
+    return 2.0 ** -24 * t * lam_max * np.linalg.norm(b) / np.linalg.norm(fb)
 
 
 def test_fp32_exp_anisotropic(fab, ctx):
@@ -656,14 +663,18 @@ def test_fp32_invsqrt_shifted_laplacian(fab, ctx):
 # With the sketch size of the workload, d = 120 = 4m, the sketch's distortion makes the restart's
 # increments swing by 10x from cycle to cycle while the error falls by ~5% a cycle (the convergence
 # spikes the paper reports for small sketches), so no estimate built from the increments tracks the
-# error there.  Every sum is formed in a fixed order, so each case gives the same bits on every run;
-# the bars are the measured results plus 30% (a regression guard, not a tolerance claim):
-#   FP64 d = 120 tol 1e-6: 34 cycles, 3.05e-6     FP32 d = 120 tol 1e-6: 36 cycles, 1.12e-5
-#   FP64 d = 480 tol 1e-8: 63 cycles, 3.69e-8     FP32 d = 480 tol 1e-6: 95 cycles, 3.19e-7
-# (the tail estimate stops 3 - 11x above tol at d = 4m; at d = 16m within tol in FP32 and 3.7x above
-# it in FP64).  The reference is the closed form of b rounded to the value type.
+# error there.  Every sum is formed in a fixed order, so each case gives the same bits on every run.
+# The stop depends on the sketch: over sketch seeds 1-8 (FP64) the error at the stop spans 2e-10 to
+# 3e-5 at d = 120, tol 1e-6, in 62 - 147 cycles, and 4e-14 to 6e-8 at d = 480, tol 1e-8, in 57 - 141
+# cycles.  Seed 1, the workload's sketch:
+#   FP64 d = 120 tol 1e-6: 130 cycles, 1.15e-7    FP32 d = 120 tol 1e-6: 53 cycles, 7.79e-6
+#   FP64 d = 480 tol 1e-8: 99 cycles, 5.96e-10    FP32 d = 480 tol 1e-6: 84 cycles, 7.18e-7
+# Bars: at d = 4m the errors of seed 1 under the two sketch generators measured so far (the older one
+# stopped at 3.05e-6 FP64 and 1.12e-5 FP32) plus 30%, a regression guard and not a tolerance claim;
+# at d = 16m FP32 the tolerance, which both generators met (3.19e-7, 7.18e-7), and FP64 the older
+# generator's 3.69e-8 plus 30%.  The reference is the closed form of b rounded to the value type.
 @pytest.mark.parametrize("dtype,d,tol,bar", [(torch.float64, 120, 1e-6, 4e-6), (torch.float32, 120, 1e-6, 1.5e-5),
-                                             (torch.float64, 480, 1e-8, 4.8e-8), (torch.float32, 480, 1e-6, 4.2e-7)])
+                                             (torch.float64, 480, 1e-8, 4.8e-8), (torch.float32, 480, 1e-6, 1e-6)])
 def test_invsqrt_256_full_size(fab, ctx, dtype, d, tol, bar):
     """(A + I)^(-1/2) b on the 256^3 Laplacian (FP64, or FP32 values and basis), m=30, k=2, zeta=8:
     the whole vector against the sine-basis closed form; the solve repeated gives the same bits."""
@@ -967,9 +978,11 @@ def test_time_points_that_converge_early_do_not_hold_back_the_stop(fab, ctx, dty
     else:
         assert abs(info["cycles"] - max(cyc)) <= 1, (info["cycles"], cyc)
     bb = b if dtype == torch.float64 else b.astype(np.float32).astype(np.float64)
+    lam_max = 4 * (N + 1) ** 2 * (1 + 0.01)
     for i, t in enumerate(CFG4_T):
-        err = _rel(x[:, i].cpu().numpy(), exact.sine_fab("exp", bb, N, [1.0, 0.01], 0.0, t=t))
-        assert err <= (tol if dtype == torch.float64 else FP32_BATCH_TOL), (t, err)
+        ref = exact.sine_fab("exp", bb, N, [1.0, 0.01], 0.0, t=t)
+        err = _rel(x[:, i].cpu().numpy(), ref)
+        assert err <= (tol if dtype == torch.float64 else tol + fp32_exp_floor(t, lam_max, bb, ref)), (t, err)
 
 
 def test_batched_1024_full_size(fab, ctx):
@@ -985,15 +998,18 @@ def test_batched_1024_full_size(fab, ctx):
                                  seed=1, tol=1e-6, max_cycles=200)
     assert all(i["status"] == "FAB_OK" for i in infos), [i["status"] for i in infos]
     assert bool(torch.isfinite(X).all())
-    worst = 0.0
+    worst, used = 0.0, 0.0
+    lam_max = 4 * (N + 1) ** 2 * (1 + 0.01)
     for r in (0, 21, 42, 63):
         b64 = Bm[:, r].astype(np.float64)
         for i, t in enumerate(CFG4_T):
             ref = exact.sine_fab("exp", b64, N, [1.0, 0.01], 0.0, t=t)
-            worst = max(worst, _rel(X[:, r, i].cpu().numpy(), ref))
-    print(f"batched 1024^2 x 64 x 8: cycles {max(i['cycles'] for i in infos)} worst sampled rel err {worst:.2e}",
-          flush=True)
-    assert worst <= FP32_BATCH_TOL
+            err = _rel(X[:, r, i].cpu().numpy(), ref)
+            worst = max(worst, err)
+            used = max(used, err / fp32_exp_floor(t, lam_max, b64, ref))
+    print(f"batched 1024^2 x 64 x 8: cycles {max(i['cycles'] for i in infos)} worst sampled rel err {worst:.2e}, "
+          f"{used:.2f} of the FP32 floor", flush=True)
+    assert used <= 1.0
 
 
 
@@ -1052,13 +1068,16 @@ def test_ragged_32_laplacians_full_size(fab, ctx):
         bs.append(torch.as_tensor(b, device="cuda"))
         bs64.append(b.astype(np.float64))
     xs, infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6, max_cycles=300)
-    worst = 0.0
+    worst, used = 0.0, 0.0
     for i, N in enumerate(Ns):
         assert infos[i]["status"] == "FAB_OK", (i, N, infos[i])
-        worst = max(worst, _rel(xs[i][:, 0].cpu().numpy(), exact.sine_fab("exp", bs64[i], N, [1, 1], 0.0, t=1e-3)))
-    print(f"ragged 32 Laplacians 64^2..512^2: cycles {max(i['cycles'] for i in infos)} worst rel err {worst:.2e}",
-          flush=True)
-    assert worst <= FP32_BATCH_TOL
+        ref = exact.sine_fab("exp", bs64[i], N, [1, 1], 0.0, t=1e-3)
+        err = _rel(xs[i][:, 0].cpu().numpy(), ref)
+        worst = max(worst, err)
+        used = max(used, err / (1e-6 + fp32_exp_floor(1e-3, 8 * (N + 1) ** 2, bs64[i], ref)))
+    print(f"ragged 32 Laplacians 64^2..512^2: cycles {max(i['cycles'] for i in infos)} worst rel err {worst:.2e}, "
+          f"{used:.2f} of tol + the FP32 floor", flush=True)
+    assert used <= 1.0
 
 
 # --------------------------------------------------------------- growing-matrix restart (Alg. 2)
@@ -1253,7 +1272,7 @@ def test_too_small_sketch_with_the_growing_restart_gives_up(fab, ctx):
     """The paper's restart with a sketch that is too small diverges (Section 5.2, the d = 160 and 240
     rows of its membrane table).  Here: the full window (k = m = 20) with the growing-matrix restart,
     d = m + 1 rows and one nonzero per column of S, on the 2-D Laplacian N = 48 at t = 3e-2: the
-    oracle twin with the same S sees an increment of ~1e9 ||x||.  On the GPU the growing matrix's
+    oracle twin with the same S sees an increment of ~2e8 ||x||.  On the GPU the growing matrix's
     norm then asks for more than 16384 Taylor steps of exp(-t M) e_1, and the solve stops with
     FAB_E_UNSUPPORTED (reproducibly: every sum is in a fixed order) instead of returning garbage."""
     N, t = 48, 3e-2
@@ -1261,10 +1280,10 @@ def test_too_small_sketch_with_the_growing_restart_gives_up(fab, ctx):
     op = _op(fab, ctx, A)
     b = wl.gaussian_vector(A.n, 1)
     kw = dict(m=20, k=20, tol=1e-10, max_cycles=30)
-    S = sketch.sketch_matrix(A.n, 21, 1, seed=3)
+    S = sketch.sketch_matrix(A.n, 21, 1, seed=25)
     _, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, S=S, evaluation="growing", **kw)
     assert max(h["est"] for h in io.history) > 1e8
-    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, d=21, zeta=1, seed=3, method="growing",
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, d=21, zeta=1, seed=25, method="growing",
                         check=False, **kw)
     assert info["status"] in ("FAB_E_UNSUPPORTED", "FAB_E_DIVERGED"), info
 

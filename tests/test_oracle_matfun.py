@@ -162,6 +162,35 @@ def test_phi1_rule_scalar_accuracy(t):
     assert quadrature.rule_error("phi1", zh, wh, True, t=t) < 1e-12
 
 
+@pytest.mark.parametrize("kappa", [0.3, 4.0, 20.0, 45.0, 100.0])
+def test_cos_sqrt_ellipse_widens_while_the_growth_allows(kappa):
+    """The ellipse parameter: rho = 2 for few oscillations, rho_min = exp(37/N) for many, and in
+    between the largest candidate whose max |f| on the nodes stays within the bound.  Inside the
+    chosen ellipse the rule reproduces cos(t sqrt z) directly (no quadrature), also for points
+    outside [lo, hi] where sketched Ritz values can fall: out to ellipse coordinate
+    |w| = rho e^(-40/N) the truncation term (|w|/rho)^N is below e^-40."""
+    lo, hi, N = 30.6, 2029.0, quadrature.COS_SQRT_N
+    t = kappa / np.sqrt(hi)
+    rho = quadrature.cos_sqrt_rho(t, N, lo, hi)
+    rho_min = np.exp(37.0 / N)
+    assert rho_min - 1e-15 <= rho <= 2.0 + 1e-15
+    if kappa <= 4.0:
+        assert rho == pytest.approx(2.0, rel=1e-14)
+    if kappa >= 100.0:
+        assert rho == pytest.approx(rho_min, rel=1e-14)
+    zeta, w = quadrature.cos_sqrt_rule(t, N, lo, hi)
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    growth = t * np.max(np.abs(np.sqrt(zeta).imag))  # ln max |f| on the nodes, within ~ln 100 here
+    assert growth <= np.log(100.0) + 1e-12 or rho == pytest.approx(rho_min, rel=1e-14)
+    # points on the ellipse of radius rho e^(-40/N): the interval's ends pushed out, and off the axis
+    r_in = rho * np.exp(-40.0 / N)
+    ph = np.linspace(0.0, 2 * np.pi, 64, endpoint=False)
+    zz = c + h * (r_in * np.exp(1j * ph) + np.exp(-1j * ph) / r_in) / 2
+    r = quadrature.rational_scalar(zeta, w, zz)
+    fmax = np.exp(growth)
+    assert np.max(np.abs(r - np.cos(t * np.sqrt(zz)))) < 1e-12 * fmax
+
+
 @pytest.mark.parametrize("kappa", [1.0, 20.0, 60.0])
 def test_cos_sqrt_rule_accuracy(kappa):
     """The ellipse rule reproduces cos(t sqrt z) on [lo, hi] (t sqrt(hi) = kappa oscillations), on a

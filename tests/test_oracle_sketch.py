@@ -25,6 +25,30 @@ def test_philox_known_answers(inp, out):
     assert got == out
 
 
+@pytest.mark.parametrize("inp,out", list(_kat()))
+def test_seven_round_form_is_the_prefix_of_the_published_generator(inp, out):
+    """The sketch's seven-round Philox is the first seven rounds of the published ten-round form:
+    rounds 7, 8 and 9 (keys advanced 7, 8, 9 times) carry its output to the known answers.  A
+    wrong key schedule, round count or round function in either part misses them."""
+    seven = philox.philox4x32_7(*inp)
+    got = [int(x) for x in philox.philox4x32_rounds(*seven, inp[4], inp[5], 3, first=7)]
+    assert got == out
+    # and it is not the ten-round output itself
+    assert [int(x) for x in seven] != out
+
+
+def test_sketch_signs_are_the_low_bits_of_the_row_draws():
+    """Signs: bit 0 of each row draw; balanced and uncorrelated with the row they go with."""
+    rows, signs = sketch.rows_and_signs(0, 200000, 80, 8, seed=5)
+    neg = signs < 0
+    assert abs(neg.mean() - 0.5) < 4 * 0.5 / np.sqrt(neg.size)
+    # sign frequency per row index: chi-square test of independence of row and sign
+    table = np.zeros((80, 2))
+    np.add.at(table, (rows.ravel(), neg.ravel().astype(int)), 1)
+    _, pval, _, _ = stats.chi2_contingency(table)
+    assert pval > 1e-4
+
+
 def test_philox_vectorised_matches_scalar():
     c = np.arange(17, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15 & 0xFFFFFFFF)
     vec = philox.philox4x32_10(c, c + np.uint64(1), c * np.uint64(3), c ^ np.uint64(5), 11, 12)
