@@ -949,10 +949,27 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
 
 // w_{j+1} = (z - sum_{i=lo..j} r_i w_i) / rho, in place on column j+1 of W (n x (m+1)).
 // KMAX bounds the window so the coefficients live in registers.  Streaming loads and stores are
-// non-temporal: a batch's basis columns exceed the memory-side cache many times over.
+// non-temporal: a batch's basis columns exceed the memory-side cache many times over.  Each thread
+// takes 16 bytes of every column at once (4 FP32 or 2 FP64 values: columns start on 4 KB pages, so
+// the vectors are aligned), the last n mod that count elements one by one; per element the
+// arithmetic and its order are those of one element at a time, so the bits do not depend on it
+// (FP32, 64 members of 1024^2: 279 -> 158 us per launch in the trace, 0.85 of HBM peak).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict__ W,
                                                      const State* __restrict__ st, size_t bs) {
+  typedef typename Vec16<T>::type V;
+  constexpr int kV = (int)(16 / sizeof(T));
   st = bat(st, bs);
   if (st->brk || st->done) return;
   W = bat(W, bs);
@@ -966,13 +983,32 @@ __global__ __launch_bounds__(kThreads) void k_update(int n, int j, T* __restrict
   const size_t ld = wcol(n, sizeof(T));
   T* out = W + (size_t)(j + 1) * ld;
   const T* base = W + (size_t)lo * ld;
-  const size_t stride = (size_t)gridDim.x * kThreads;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < (size_t)n; i += stride) {
-    double v = (double)__builtin_nontemporal_load(&out[i]);
+  const int nv = n / kV;
+  const int stride = (int)gridDim.x * kThreads;
+  const int t0 = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+  for (int i = t0; i < nv; i += stride) {
+    const V zv = __builtin_nontemporal_load(reinterpret_cast<const V*>(out) + i);
+    V wv[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (q < nw) v -= coef[q] * (double)__builtin_nontemporal_load(&base[(size_t)q * ld + i]);
-    __builtin_nontemporal_store((T)(v * inv), &out[i]);
+      if (q < nw) wv[q] = __builtin_nontemporal_load(reinterpret_cast<const V*>(base + (size_t)q * ld) + i);
+    V r;
+#pragma unroll
+    for (int e = 0; e < kV; ++e) {
+      double v = (double)zv[e];
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q < nw) v -= coef[q] * (double)wv[q][e];
+      r[e] = (T)(v * inv);
+    }
+    __builtin_nontemporal_store(r, reinterpret_cast<V*>(out) + i);
+  }
+  for (int i = nv * kV + t0; i < n; i += stride) {  // the last n mod kV elements
+    double v = (double)out[i];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < nw) v -= coef[q] * (double)base[(size_t)q * ld + i];
+    out[i] = (T)(v * inv);
   }
 }
 
@@ -1448,10 +1484,15 @@ hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j
 template <typename T>
 static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st, int nb, size_t bs) {
   const dim3 g(grid, nb);
+  // k_update: one 16-byte vector per thread and trip, so a quarter (FP32) or half (FP64) of the
+  // element grid, in whole XCD rounds
+  const int nv = n / (int)(16 / sizeof(T));
+  const int gv = std::max(kXcds, std::min(grid, ((nv + kThreads - 1) / kThreads + kXcds - 1) / kXcds * kXcds));
+  const dim3 g16(gv, nb);
   if (k <= 4)
-    hipLaunchKernelGGL((k_update<T, 4>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
+    hipLaunchKernelGGL((k_update<T, 4>), g16, dim3(kThreads), 0, s, n, j, W, st, bs);
   else if (k <= 8)
-    hipLaunchKernelGGL((k_update<T, 8>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
+    hipLaunchKernelGGL((k_update<T, 8>), g16, dim3(kThreads), 0, s, n, j, W, st, bs);
   else
     hipLaunchKernelGGL((k_update_wide<T>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
 }
