@@ -955,6 +955,14 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn,
                                                    T* __restrict__ W, double* __restrict__ x, int64_t ldx,
                                                    double* __restrict__ parts, const State* __restrict__ st,
                                                    size_t bs, PassSketch ps) {
+  // From four time points on, the weights C (nt + 1 per basis column) outgrow the scalar registers:
+  // the compiler then spills them to vector lanes and reads them back with one VALU instruction per
+  // word (k_pass<float, 8>: 1.8e9 VALU instructions per launch on the batched 1024^2 workload).  So
+  // they go to LDS once per block instead, a row of kCs per column, read by broadcast (that pass:
+  // 3.95 -> 2.99 ms per launch, same bits).
+  constexpr bool kLdsC = NT >= 4;
+  constexpr int kCs = (NT + 2) & ~1;  // q = 0 .. NT - 1 time points, q = NT the restart, then 0
+  __shared__ double sC[kLdsC ? (kMaxM + 1) * kCs : 1];
   __shared__ double part[kThreads / 64][2 * NT];
   extern __shared__ double pbins[];  // (kThreads / 64) x ps.d bins when sketching
   st = bat(st, bs);
@@ -968,10 +976,14 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn,
   const int ncol = brk ? mm : mm + 1;
   const bool sk = ps.on && !brk;  // block-uniform
   double* wbins = pbins + (threadIdx.x >> 6) * ps.d;
-  if (sk) {
+  if (sk)
     for (int b = threadIdx.x; b < (kThreads / 64) * ps.d; b += kThreads) pbins[b] = 0.0;
-    __syncthreads();
-  }
+  if constexpr (kLdsC)
+    for (int e = threadIdx.x; e < ncol * kCs; e += kThreads) {
+      const int j = e / kCs, q = e % kCs;
+      sC[e] = q < nt ? C[(size_t)q * (m + 1) + j] : (q == NT ? C[(size_t)nt * (m + 1) + j] : 0.0);
+    }
+  if (sk || kLdsC) __syncthreads();
   double yn[NT], xn[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) yn[q] = xn[q] = 0.0;
@@ -997,7 +1009,9 @@ __global__ __launch_bounds__(kThreads) void k_pass(int n, int m, int nt, int dn,
         const double w = (j0 + u < ncol) ? (double)wv[u] : 0.0;
 #pragma unroll
         for (int q = 0; q <= NT; ++q) {  // q = NT: the restart column, stored after the nt time points
-          const double cq = (q < nt) ? C[(size_t)q * (m + 1) + j] : (q == NT ? C[(size_t)nt * (m + 1) + j] : 0.0);
+          double cq;
+          if constexpr (kLdsC) cq = sC[j * kCs + q];
+          else cq = (q < nt) ? C[(size_t)q * (m + 1) + j] : (q == NT ? C[(size_t)nt * (m + 1) + j] : 0.0);
           acc[q] = fma(w, cq, acc[q]);
         }
       }
