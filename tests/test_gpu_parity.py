@@ -521,7 +521,7 @@ def test_solves_are_bitwise_reproducible(fab, ctx, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("N,k", [(16, 2), (40, 6)])
+@pytest.mark.parametrize("N,k", [(16, 2), (40, 6), (23, 2)])
 def test_store_policy_changes_no_bits(fab, ctx, dtype, N, k):
     """The step's cache policy (default, or non-temporal z and update) moves the same values: a
     solve under either gives the same bits and cycle count, for both update widths (k <= 4 and
@@ -646,9 +646,10 @@ def test_fp32_exp_anisotropic(fab, ctx):
         assert _rel(x[:, i].cpu().numpy(), ref) <= FP32_TOL, t
 
 
-def test_fp32_invsqrt_shifted_laplacian(fab, ctx):
-    """FP32 loop, (A + I)^(-1/2) b on the 3-D Laplacian, N = 24."""
-    N = 24
+@pytest.mark.parametrize("N", [24, 25])
+def test_fp32_invsqrt_shifted_laplacian(fab, ctx, N):
+    """FP32 loop, (A + I)^(-1/2) b on the 3-D Laplacian, N = 24 (n = 27 whole update batches of 512)
+    and N = 25 (n = 15625: a partial last batch, which the update takes element by element)."""
     A = wl.shifted_laplacian_3d(N, 1.0)
     op = _op(fab, ctx, A, torch.float32)
     b = wl.gaussian_vector(A.n, 0)
