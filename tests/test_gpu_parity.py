@@ -415,6 +415,44 @@ def test_ragged_sizes_and_tiny_n(fab, ctx):
         assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-10, (N, info)
 
 
+@pytest.mark.parametrize("case", ["zero", "one_by_one", "diagonal"])
+def test_degenerate_operators(fab, ctx, case):
+    """Degenerate operators: A = 0 (z = 0 at the first step: a breakdown, and exp(0) b = b exactly),
+    a 1 x 1 matrix (the Krylov space is the whole space after one step), and a diagonal matrix with
+    1000 distinct eigenvalues (x_i = exp(-t lambda_i) b_i).  The oracle twin with the same S ends the
+    same way (breakdown in one cycle for the first two)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(5)
+    if case == "zero":
+        n = 1000
+        rowptr, colind, vals = np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0)
+        b = rng.standard_normal(n)
+        ref = b.copy()
+    elif case == "one_by_one":
+        n = 1
+        rowptr, colind, vals = np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])
+        b = np.array([2.0])
+        ref = b * np.exp(-0.1 * 3.0)
+    else:
+        n = 1000
+        lam = 1.0 + 99.0 * rng.random(n)
+        rowptr, colind, vals = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), lam
+        b = rng.standard_normal(n)
+        ref = np.exp(-0.1 * lam) * b
+    op = fab.CSROperator.from_arrays(ctx, rowptr, colind, vals)
+    x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=0.1, m=20, k=2, d=80, zeta=8, seed=1,
+                        tol=1e-12, max_cycles=100)
+    assert _rel(x[:, 0].cpu().numpy(), ref) <= 1e-13, (case, info)
+    A = sp.csr_matrix((vals, colind, rowptr), shape=(n, n))
+    _, io = krylov.restart_solve(A, b, "exp", 0.1, m=20, k=2, S=sketch.sketch_matrix(n, 80, 8, seed=1), tol=1e-12,
+                                 max_cycles=100)
+    if case == "diagonal":
+        assert info["status"] == "FAB_OK" and io.status == "ok", info
+    else:
+        assert info["status"] in ("FAB_OK", "FAB_OK_BREAKDOWN") and io.status == "breakdown", info
+        assert info["cycles"] == io.cycles == 1
+
+
 def test_breakdown_on_eigenvector(fab, ctx):
     N = 16
     Phi, lam = exact.sine_basis(N)
