@@ -751,7 +751,7 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
 // Blocks of 1 + 4 wavefronts: the first redoes the sketch-space Gram-Schmidt (the same
 // arithmetic on the same S z in every block, so every block gets the same coefficients; block 0 also stores
 // R, U and the state) while the other four load their first batch of elements (z and the window).
-// After the barrier they stream the block's batches of kOuBatch elements, and the loads of the
+// After the barrier they stream the block's batches of OuBatch elements, and the loads of the
 // next batch are issued before the current one is updated and stored, so reads and writes of the
 // whole grid overlap instead of running in two phases.  (A wavefront's loads complete in order, so
 // the Gram-Schmidt gets a wavefront of its own: streaming loads issued by the same wavefront would
@@ -759,9 +759,18 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
 // with no branch around a load, the compiler can count the loads in flight and wait for one batch
 // only.  Saves the separate single-wavefront launch, whose latency would sit between product and
 // update, and runs the Gram-Schmidt once per block rather than once per 1024 elements.
-constexpr int kOuPer = 2;                     // elements per streaming thread and batch
-constexpr int kOuThreads = 64 + kThreads;     // Gram-Schmidt wavefront + streaming wavefronts
-constexpr int kOuBatch = kThreads * kOuPer;   // elements per block and batch
+// Elements per streaming thread and batch: 2 FP64, or 4 FP32 (twice the loads in flight for half
+// the bytes each: the 256^3 FP32 step 298 -> 290 us; with 2 its update ran at 0.66 of peak against
+// 0.77 for FP64).
+template <typename T>
+struct OuPer {
+  static constexpr int v = sizeof(T) == 4 ? 4 : 2;
+};
+constexpr int kOuThreads = 64 + kThreads;  // Gram-Schmidt wavefront + streaming wavefronts
+template <typename T>
+struct OuBatch {  // elements per block and batch
+  static constexpr int v = kThreads * OuPer<T>::v;
+};
 constexpr int kOuBlocksPerCu = 2;
 
 // Raw buffer accesses (untyped, byte offsets): the hardware checks every lane's offset against the
@@ -799,16 +808,17 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
 }
 
-// Elements of one batch: those of [b0, b0 + kOuBatch) below n (none when b0 >= n: a size-0
+// Elements of one batch: those of [b0, b0 + OuBatch) below n (none when b0 >= n: a size-0
 // resource, whose loads return 0 without touching memory).
+template <typename T>
 __device__ __forceinline__ int ou_count(int n, int64_t b0) {
-  return b0 < n ? (int)min((int64_t)kOuBatch, (int64_t)n - b0) : 0;
+  return b0 < n ? (int)min((int64_t)OuBatch<T>::v, (int64_t)n - b0) : 0;
 }
 
 template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, size_t ld,
-                                        int nw, int64_t b0, int t, T (&zv)[kOuPer], T (&wv)[kOuPer][KMAX]) {
-  const int cnt = ou_count(n, b0);
+                                        int nw, int64_t b0, int t, T (&zv)[OuPer<T>::v], T (&wv)[OuPer<T>::v][KMAX]) {
+  const int cnt = ou_count<T>(n, b0);
   const int64_t o = cnt ? b0 : 0;
   const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + o, cnt * (int)sizeof(T));
   __amdgpu_buffer_rsrc_t rw[KMAX];
@@ -816,7 +826,7 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
   for (int q = 0; q < KMAX; ++q)  // columns beyond the window: size 0 (their coefficients are 0)
     rw[q] = buf_rsrc(base + (size_t)min(q, nw - 1) * ld + o, q < nw ? cnt * (int)sizeof(T) : 0);
 #pragma unroll
-  for (int e = 0; e < kOuPer; ++e) {
+  for (int e = 0; e < OuPer<T>::v; ++e) {
     const int off = (e * kThreads + t) * (int)sizeof(T);
     zv[e] = buf_load<AUX>(rz, off, T());
 #pragma unroll
@@ -828,11 +838,11 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
 // cancels; only the stored w_{j+1} is rounded to T.  coef is zero beyond the window.
 template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0, int t, const double (&coef)[KMAX],
-                                         double inv, const T (&zv)[kOuPer], const T (&wv)[kOuPer][KMAX]) {
-  const int cnt = ou_count(n, b0);
+                                         double inv, const T (&zv)[OuPer<T>::v], const T (&wv)[OuPer<T>::v][KMAX]) {
+  const int cnt = ou_count<T>(n, b0);
   const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + (cnt ? b0 : 0), cnt * (int)sizeof(T));
 #pragma unroll
-  for (int e = 0; e < kOuPer; ++e) {
+  for (int e = 0; e < OuPer<T>::v; ++e) {
     double v = (double)zv[e];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
@@ -846,8 +856,8 @@ __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0,
 template <typename T, int KMAX, int AUX, typename Start>
 __device__ __forceinline__ void ou_stream(T* __restrict__ out, const T* __restrict__ base, int n, size_t ld, int nw,
                                           int cnt, Start start, int t, const double (&coef)[KMAX], double inv,
-                                          T (&za)[kOuPer], T (&wa)[kOuPer][KMAX], T (&zb)[kOuPer],
-                                          T (&wb)[kOuPer][KMAX]) {
+                                          T (&za)[OuPer<T>::v], T (&wa)[OuPer<T>::v][KMAX], T (&zb)[OuPer<T>::v],
+                                          T (&wb)[OuPer<T>::v][KMAX]) {
   for (int it = 0;;) {
     __builtin_amdgcn_s_setprio(2);
     ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
@@ -938,10 +948,10 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   }
   // batches blockIdx.x, blockIdx.x + gridDim.x, ...; the launch keeps gridDim.x <= the batch count
   const int t = threadIdx.x - 64;
-  const int nbat = (n + kOuBatch - 1) / kOuBatch;
+  const int nbat = (n + OuBatch<T>::v - 1) / OuBatch<T>::v;
   const int cnt = (nbat - 1 - (int)blockIdx.x) / (int)gridDim.x + 1;
-  auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * kOuBatch; };
-  T za[kOuPer], wa[kOuPer][KMAX], zb[kOuPer], wb[kOuPer][KMAX];
+  auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * OuBatch<T>::v; };
+  T za[OuPer<T>::v], wa[OuPer<T>::v][KMAX], zb[OuPer<T>::v], wb[OuPer<T>::v][KMAX];
   ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(0), t, za, wa);
   __syncthreads();
   if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
@@ -1450,7 +1460,8 @@ hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
                               const double* parts, int nparts, int nts) {
   if (parts && (nparts < 1 || nparts > 64)) return hipErrorInvalidValue;  // one partial per lane
-  const int nbat = (int)((n + kOuBatch - 1) / kOuBatch);
+  const int ob = dtype == 0 ? OuBatch<double>::v : OuBatch<float>::v;
+  const int nbat = (int)((n + ob - 1) / ob);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
 #define FAB_OU2(TT, KK, INL, AUX)                                                                              \
