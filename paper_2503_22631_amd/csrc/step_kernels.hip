@@ -759,17 +759,18 @@ __global__ __launch_bounds__(64) void k_orth(int j, int k, int m, int d, const d
 // with no branch around a load, the compiler can count the loads in flight and wait for one batch
 // only.  Saves the separate single-wavefront launch, whose latency would sit between product and
 // update, and runs the Gram-Schmidt once per block rather than once per 1024 elements.
-// Elements per streaming thread and batch: 2 FP64, or 4 FP32 (twice the loads in flight for half
-// the bytes each: the 256^3 FP32 step 298 -> 290 us; with 2 its update ran at 0.66 of peak against
-// 0.77 for FP64).
-template <typename T>
+// Elements per streaming thread and batch: 4, except 2 for FP64 under the non-temporal policy
+// (operators beyond the memory-side cache).  Measured against 2 throughout: the 256^3 FP32 step
+// 298 -> 290 us (its update had run at 0.66 of peak against 0.77 for FP64), the 128^3 FP64 step
+// 53.85 -> 53.27 us; the 256^3 FP64 step 457.9 -> 460.7 us with 4, hence 2 there.
+template <typename T, int AUX>
 struct OuPer {
-  static constexpr int v = sizeof(T) == 4 ? 4 : 2;
+  static constexpr int v = (sizeof(T) == 8 && AUX != 0) ? 2 : 4;
 };
 constexpr int kOuThreads = 64 + kThreads;  // Gram-Schmidt wavefront + streaming wavefronts
-template <typename T>
+template <typename T, int AUX>
 struct OuBatch {  // elements per block and batch
-  static constexpr int v = kThreads * OuPer<T>::v;
+  static constexpr int v = kThreads * OuPer<T, AUX>::v;
 };
 constexpr int kOuBlocksPerCu = 2;
 
@@ -810,15 +811,15 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int
 
 // Elements of one batch: those of [b0, b0 + OuBatch) below n (none when b0 >= n: a size-0
 // resource, whose loads return 0 without touching memory).
-template <typename T>
+template <typename T, int AUX>
 __device__ __forceinline__ int ou_count(int n, int64_t b0) {
-  return b0 < n ? (int)min((int64_t)OuBatch<T>::v, (int64_t)n - b0) : 0;
+  return b0 < n ? (int)min((int64_t)OuBatch<T, AUX>::v, (int64_t)n - b0) : 0;
 }
 
 template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __restrict__ base, int n, size_t ld,
-                                        int nw, int64_t b0, int t, T (&zv)[OuPer<T>::v], T (&wv)[OuPer<T>::v][KMAX]) {
-  const int cnt = ou_count<T>(n, b0);
+                                        int nw, int64_t b0, int t, T (&zv)[OuPer<T, AUX>::v], T (&wv)[OuPer<T, AUX>::v][KMAX]) {
+  const int cnt = ou_count<T, AUX>(n, b0);
   const int64_t o = cnt ? b0 : 0;
   const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + o, cnt * (int)sizeof(T));
   __amdgpu_buffer_rsrc_t rw[KMAX];
@@ -826,7 +827,7 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
   for (int q = 0; q < KMAX; ++q)  // columns beyond the window: size 0 (their coefficients are 0)
     rw[q] = buf_rsrc(base + (size_t)min(q, nw - 1) * ld + o, q < nw ? cnt * (int)sizeof(T) : 0);
 #pragma unroll
-  for (int e = 0; e < OuPer<T>::v; ++e) {
+  for (int e = 0; e < OuPer<T, AUX>::v; ++e) {
     const int off = (e * kThreads + t) * (int)sizeof(T);
     zv[e] = buf_load<AUX>(rz, off, T());
 #pragma unroll
@@ -838,11 +839,11 @@ __device__ __forceinline__ void ou_load(const T* __restrict__ out, const T* __re
 // cancels; only the stored w_{j+1} is rounded to T.  coef is zero beyond the window.
 template <typename T, int KMAX, int AUX>
 __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0, int t, const double (&coef)[KMAX],
-                                         double inv, const T (&zv)[OuPer<T>::v], const T (&wv)[OuPer<T>::v][KMAX]) {
-  const int cnt = ou_count<T>(n, b0);
+                                         double inv, const T (&zv)[OuPer<T, AUX>::v], const T (&wv)[OuPer<T, AUX>::v][KMAX]) {
+  const int cnt = ou_count<T, AUX>(n, b0);
   const __amdgpu_buffer_rsrc_t rz = buf_rsrc(out + (cnt ? b0 : 0), cnt * (int)sizeof(T));
 #pragma unroll
-  for (int e = 0; e < OuPer<T>::v; ++e) {
+  for (int e = 0; e < OuPer<T, AUX>::v; ++e) {
     double v = (double)zv[e];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) v -= coef[q] * (double)wv[e][q];
@@ -856,8 +857,8 @@ __device__ __forceinline__ void ou_store(T* __restrict__ out, int n, int64_t b0,
 template <typename T, int KMAX, int AUX, typename Start>
 __device__ __forceinline__ void ou_stream(T* __restrict__ out, const T* __restrict__ base, int n, size_t ld, int nw,
                                           int cnt, Start start, int t, const double (&coef)[KMAX], double inv,
-                                          T (&za)[OuPer<T>::v], T (&wa)[OuPer<T>::v][KMAX], T (&zb)[OuPer<T>::v],
-                                          T (&wb)[OuPer<T>::v][KMAX]) {
+                                          T (&za)[OuPer<T, AUX>::v], T (&wa)[OuPer<T, AUX>::v][KMAX], T (&zb)[OuPer<T, AUX>::v],
+                                          T (&wb)[OuPer<T, AUX>::v][KMAX]) {
   for (int it = 0;;) {
     __builtin_amdgcn_s_setprio(2);
     ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(it + 1), t, zb, wb);
@@ -948,10 +949,10 @@ __global__ __launch_bounds__(kOuThreads) void k_orth_update(int n, int j, int k,
   }
   // batches blockIdx.x, blockIdx.x + gridDim.x, ...; the launch keeps gridDim.x <= the batch count
   const int t = threadIdx.x - 64;
-  const int nbat = (n + OuBatch<T>::v - 1) / OuBatch<T>::v;
+  const int nbat = (n + OuBatch<T, AUX>::v - 1) / OuBatch<T, AUX>::v;
   const int cnt = (nbat - 1 - (int)blockIdx.x) / (int)gridDim.x + 1;
-  auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * OuBatch<T>::v; };
-  T za[OuPer<T>::v], wa[OuPer<T>::v][KMAX], zb[OuPer<T>::v], wb[OuPer<T>::v][KMAX];
+  auto start = [&](int it) { return ((int64_t)blockIdx.x + (int64_t)it * gridDim.x) * OuBatch<T, AUX>::v; };
+  T za[OuPer<T, AUX>::v], wa[OuPer<T, AUX>::v][KMAX], zb[OuPer<T, AUX>::v], wb[OuPer<T, AUX>::v][KMAX];
   ou_load<T, KMAX, AUX>(out, base, n, ld, nw, start(0), t, za, wa);
   __syncthreads();
   if (!s_ok) return;  // breakdown (or non-finite): the cycle ends at this step
@@ -1460,7 +1461,8 @@ hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
                               const double* parts, int nparts, int nts) {
   if (parts && (nparts < 1 || nparts > 64)) return hipErrorInvalidValue;  // one partial per lane
-  const int ob = dtype == 0 ? OuBatch<double>::v : OuBatch<float>::v;
+  const int ob = dtype == 0 ? (nts ? OuBatch<double, kAuxNt>::v : OuBatch<double, 0>::v)
+                            : (nts ? OuBatch<float, kAuxNt>::v : OuBatch<float, 0>::v);
   const int nbat = (int)((n + ob - 1) / ob);
   const int grid = std::max(1, std::min(nbat, kOuBlocksPerCu * num_cu));
   const dim3 g(grid, nb);
