@@ -1093,6 +1093,46 @@ def test_ragged_small_mixed(fab, ctx):
     assert all(_rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12 for a, b in zip(xs, xs2) if b.abs().max() > 0)
 
 
+def test_ragged_mixed_types_and_zero_rhs(fab):
+    """One ragged solve over operators of uneven size and type: FP64 and FP32 Laplacians of four
+    grid sizes, the anisotropic operator, and a zero right-hand side (x = 0 exactly); each against
+    the closed form and against its own single solve.  It runs in a context of its own, whose first
+    ragged call it is (a second call with other outputs, which re-captures the ragged graph, is the
+    skipped case above)."""
+    own = fab.Context()
+    ops = []
+    try:
+        Ns = [9, 20, 33, 47, 64]
+        bs, refs, dts = [], [], []
+        for i, N in enumerate(Ns):
+            A = wl.laplacian_2d(N) if i != 2 else wl.anisotropic_2d(N, 0.01)
+            dt = torch.float32 if i == 3 else torch.float64
+            b = wl.gaussian_vector(A.n, 40 + i) if i != 4 else np.zeros(A.n)
+            ops.append(_op(fab, own, A, dt))
+            bs.append(torch.as_tensor(b, dtype=dt, device="cuda"))
+            coefs = [1.0, 0.01] if i == 2 else [1.0, 1.0]
+            bb = b.astype(np.float32).astype(np.float64) if dt == torch.float32 else b
+            refs.append(exact.sine_fab("exp", bb, N, coefs, 0.0, t=1e-3))
+            dts.append(dt)
+        kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=200)
+        xs, infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw)
+        for i in range(len(Ns)):
+            assert infos[i]["status"] == "FAB_OK", (i, infos[i])
+            got = xs[i][:, 0].cpu().numpy()
+            if i == 4:
+                assert not np.any(got)
+                continue
+            assert _rel(got, refs[i]) <= (FP32_TOL if dts[i] == torch.float32 else 1e-9), i
+            xs1, info1 = fab.solve(ops[i], bs[i], "exp", t=1e-3, **kw)
+            assert info1["cycles"] == infos[i]["cycles"]
+            assert _rel(got, xs1[:, 0].cpu().numpy()) <= (1e-6 if dts[i] == torch.float32 else 1e-12), i
+    finally:
+        torch.cuda.synchronize()
+        for op in ops:
+            op.close()
+        own.close()
+
+
 def test_ragged_32_laplacians_full_size(fab, ctx):
     """The ragged half of the batched workload: 32 Laplacians on grids from 64^2 to 512^2 (FP32),
     t = 1e-3, b_i from seed 1000+i, m=20, k=2, d=80, tol 1e-6, in one ragged solve; every operator
