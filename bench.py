@@ -7,7 +7,8 @@ Workload (one "step" = one complete solve, i.e. every cycle of the hot path):
   sketched restarted Krylov m = 50, window k = 4, sketch d = 200 rows, zeta = 8, seed 1, tol 1e-8.
 
 Prints one JSON line: solves/s, the roofline of the dominant kernel (fused SpMV + sketch, timed
-with HIP events on its own stream during the timed solves), the step-loop bandwidth, the plain
+with HIP events that each launch's dispatch records on the kernel's stream, over solves timed
+like the headline ones), the step-loop bandwidth, the plain
 restarted Arnoldi comparator on the same GPU, and the CPU oracle timed on the host as baseline
 (which also gives the relative error of the GPU result against the exact FP64 solution).
 
@@ -380,8 +381,9 @@ def extra_legs(fab, ctx):
                                                   spec=spec, max_cycles=300))
         leg[name] = {"solves_per_s": 1.0 / sec, "cycles": info["cycles"], "ms_per_cycle": 1e3 * sec / info["cycles"],
                      "status": info["status"], "kappa_T": info["kappa_T"]}
-        # HBM roofline of this workload's loop: three cycles again with HIP events around every launch
-        # of the fused SpMV + sketch kernel and every step loop (algorithmic bytes as for the headline)
+        # HBM roofline of this workload's loop: three cycles again with HIP events recorded by every
+        # launch of the fused SpMV + sketch kernel and around every step loop (algorithmic bytes as for
+        # the headline)
         fab.timing_enable(ctx, True)
         fab.solve(op, bt, "invsqrt", m=30, k=2, d=120, zeta=8, seed=1, tol=1e-6, spec=spec, max_cycles=3,
                   check=False)
@@ -573,8 +575,9 @@ def main():
     x_gpu = xv[:, 0].cpu().numpy().copy()
     elapsed = t1 - t0
     value = args.steps / elapsed
-    # instrumented region: the same K solves with HIP events around every launch of the fused
-    # SpMV + sketch kernel and around each step loop (cycles enqueued directly on the stream)
+    # instrumented region: the same K solves with HIP events recorded by every launch of the fused
+    # SpMV + sketch kernel (start and end of its dispatch) and around each step loop (cycles enqueued
+    # directly on the stream)
     fab.timing_enable(ctx, True)
     torch.cuda.synchronize()
     i0 = time.perf_counter()
@@ -642,8 +645,9 @@ def main():
                         "kernel": "k_spmv_sketch (fused CSR SpMV + sparse-sign sketch)",
                         "bytes_per_launch": spmv_bytes, "avg_launch_us": spmv_avg_s * 1e6,
                         "launches_timed": tm["spmv_launches"],
-                        "timing": "HIP events on the kernel's stream around every launch, over the instrumented "
-                                  f"region ({args.steps} solves, {1e3 * (i1 - i0) / args.steps:.2f} ms/solve)"},
+                        "timing": "HIP events recorded by every launch's dispatch on the kernel's stream "
+                                  "(hipExtLaunchKernelGGL start/stop events), over the instrumented region "
+                                  f"({args.steps} solves, {1e3 * (i1 - i0) / args.steps:.2f} ms/solve)"},
            "loop": {"GB/s": loop_gbs, "frac": (loop_gbs / HBM_PEAK_GBS) if loop_gbs else None,
                     "bytes_per_step": step_bytes, "steps_timed": tl["loop_steps"],
                     "avg_step_us": 1e3 * tl["loop_ms"] / max(tl["loop_steps"], 1),

@@ -21,7 +21,8 @@
 namespace fab {
 hipError_t launch_spmv_sketch(hipStream_t, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* parts, const State* st, int nb, int G, size_t bs, int nts = 0);
+                              double* parts, const State* st, int nb, int G, size_t bs, int nts = 0,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_reduce_parts(hipStream_t, int e0, int len, int nparts, const double* parts, double* out,
                                const State* st, int skip, int nb, size_t bs);
 size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16);
@@ -32,10 +33,11 @@ size_t group_lds_max();
 hipError_t launch_orth(hipStream_t, int j, int k, int m, int d, const double* uraw, double* U, double* R,
                        State* st, int nb, size_t bs);
 hipError_t launch_update(hipStream_t, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
-                         size_t bs);
+                         size_t bs, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_orth_update(hipStream_t, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
-                              const double* parts, int nparts, int nts);
+                              const double* parts, int nparts, int nts, hipEvent_t e0 = nullptr,
+                              hipEvent_t e1 = nullptr);
 hipError_t launch_gram(hipStream_t, int dtype, int grid, int n, int j1, const void* V, const void* z,
                        double* slots, int want_norm, const State* st);
 hipError_t launch_cgs_update(hipStream_t, int dtype, int grid, int n, int j, int m, void* V, const double* slots,
@@ -408,12 +410,16 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
   FAB_TRY(launch_start(s, d, m, plain ? 1 : 0, q.red, q.slots_start, q.slots_step, q.step_len, q.U, q.R, q.st, nb,
                        bs));
   FAB_TRY(launch_scale_col(s, dt, g_vec, n, col(0), &q.st->inv_alpha, q.st, nb, bs));
+  // Timing: with events around every kernel (fab_timing_enable(ctx, 1)) the product's and the
+  // update's dispatches record them themselves (the kernels' own intervals); with events at the loop
+  // ends only (2), one event before the first step and one after the last.
+  const bool kev = tev && !ctx->timing_loop_only;
+  auto ev = [&](int i) { return kev ? (*tev)[i] : (hipEvent_t) nullptr; };
+  if (tev && ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[0], s));
   for (int j = 0; j < m; ++j) {
     if (!plain) {
-      if (tev && (j == 0 || !ctx->timing_loop_only)) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 0, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
-                                 d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs, A->nts));
-      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
+                                 d, p->zeta, p->seed, q.parts, q.st, nb, B.G, bs, A->nts, ev(2 * j), ev(2 * j + 1)));
       // Gram-Schmidt folded into the update launch for single solves (every block of the update
       // redoes it; in a batch that redundancy would multiply by the members).  With at most 64
       // product blocks (small operators) the update's Gram-Schmidt wavefront also sums their
@@ -422,22 +428,19 @@ static fab_status enqueue_cycle(const fab_ctx* ctx, hipStream_t s, const fab_op*
       const bool inline_sum = fused_orth && g_spmv <= 64;
       if (!inline_sum) FAB_TRY(launch_reduce_parts(s, 0, d, g_spmv, q.parts, q.uraw, q.st, 0, nb, bs));
       if (fused_orth) {
-        if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
         FAB_TRY(launch_orth_update(s, dt, ctx->num_cu, n, j, p->k, m, d, q.W, q.uraw, q.U, q.R, q.G, q.st, nb, bs,
-                                   inline_sum ? q.parts : nullptr, inline_sum ? g_spmv : 0, A->nts));
+                                   inline_sum ? q.parts : nullptr, inline_sum ? g_spmv : 0, A->nts,
+                                   ev(kTevUpdate + 2 * j), ev(kTevUpdate + 2 * j + 1)));
       } else {
         FAB_TRY(launch_orth(s, j, p->k, m, d, q.uraw, q.U, q.R, q.st, nb, bs));
-        if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j], s));
-        FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs));
+        FAB_TRY(launch_update(s, dt, g_vec, n, j, p->k, q.W, q.st, nb, bs, ev(kTevUpdate + 2 * j),
+                              ev(kTevUpdate + 2 * j + 1)));
       }
-      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[kTevUpdate + 2 * j + 1], s));
     } else {
       double* set0 = q.slots_step;
       double* set1 = q.slots_step + q.step_len;
-      if (tev && (j == 0 || !ctx->timing_loop_only)) FAB_TRY(record_timing_event((*tev)[2 * j], s));
       FAB_TRY(launch_spmv_sketch(s, dt, 2, g_spmv, n, A->rowptr, A->colind, A->colrel, A->vals, col(j), col(j + 1),
-                                 1, 1, 0, nullptr, q.st, 1, 1, 0));
-      if (tev && !ctx->timing_loop_only) FAB_TRY(record_timing_event((*tev)[2 * j + 1], s));
+                                 1, 1, 0, nullptr, q.st, 1, 1, 0, 0, ev(2 * j), ev(2 * j + 1)));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set0, 1, q.st));
       FAB_TRY(launch_cgs_update(s, dt, g_vec, n, j, m, q.W, set0, set1, nullptr, 0, q.R, q.st));
       FAB_TRY(launch_gram(s, dt, g_vec, n, j + 1, q.W, col(j + 1), set1, 0, q.st));

@@ -20,6 +20,8 @@
 //                   plain restarted Arnoldi comparator.
 #include "fab_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace fab {
 
 // Row tile of a block: blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8.
@@ -1292,33 +1294,46 @@ size_t spmv_sketch_lds(int dtype, int mode, int d, int G, int zeta, bool c16) {
   return spmv_lds_bins(mode, d) + chunk;
 }
 
+// A launch that, when timing events are given, has the dispatch itself record them at the kernel's
+// start and end (hipExtLaunchKernelGGL): the interval is the kernel's own, as in a trace, without
+// the gap a separate event record leaves before the dispatch.
+template <typename K, typename... Args>
+static void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, e0, e1, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 template <typename T>
 static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n, const int* rp, const int* ci,
                                        const int16_t* cr, const T* va, const T* x, T* y, int d, int zeta, uint64_t seed,
-                                       double* parts, const State* st, int nb, int G, size_t bs, int nts) {
+                                       double* parts, const State* st, int nb, int G, size_t bs, int nts,
+                                       hipEvent_t e0, hipEvent_t e1) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
   if (G > 1 && (mode == 2 || G % kWaves != 0 || G > kGroupMax)) return hipErrorInvalidValue;
   const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta, cr != nullptr);
   const dim3 g2(grid, (nb + G - 1) / G);
   const bool c16 = cr != nullptr && mode != 1;  // the sketch-only mode stages no CSR chunk
-#define FAB_L(M, Z)                                                                                               \
-  if (G > 1)                                                                                                      \
-    hipLaunchKernelGGL((k_spmv_sketch_grp<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta, \
-                       scale, k0, k1, parts, st, nb, G, bs);                                                      \
-  else if (c16)                                                                                                   \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z, (M != 1)>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, \
-                       zeta, scale, k0, k1, parts, st, bs, nts);                                                  \
-  else                                                                                                            \
-    hipLaunchKernelGGL((k_spmv_sketch<T, M, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
-                       scale, k0, k1, parts, st, bs, nts)
-#define FAB_LS(Z)                                                                                                 \
-  if (c16)                                                                                                        \
-    hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z, true>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d,    \
-                       zeta, scale, k0, k1, parts, st, bs, nts);                                                  \
-  else                                                                                                            \
-    hipLaunchKernelGGL((k_spmv_sketch<T, 2, Z>), g2, dim3(kThreads), lds, s, n, rp, ci, cr, va, x, y, d, zeta,     \
-                       scale, k0, k1, parts, st, bs, nts)
+#define FAB_L(M, Z)                                                                                                \
+  if (G > 1)                                                                                                       \
+    launch_timed(k_spmv_sketch_grp<T, M, Z>, g2, dim3(kThreads), lds, s, e0, e1, n, rp, ci, cr, va, x, y, d, zeta,   \
+                 scale, k0, k1, parts, st, nb, G, bs);                                                             \
+  else if (c16)                                                                                                    \
+    launch_timed(k_spmv_sketch<T, M, Z, (M != 1)>, g2, dim3(kThreads), lds, s, e0, e1, n, rp, ci, cr, va, x, y, d,   \
+                 zeta, scale, k0, k1, parts, st, bs, nts);                                                         \
+  else                                                                                                             \
+    launch_timed(k_spmv_sketch<T, M, Z>, g2, dim3(kThreads), lds, s, e0, e1, n, rp, ci, cr, va, x, y, d, zeta,       \
+                 scale, k0, k1, parts, st, bs, nts)
+#define FAB_LS(Z)                                                                                                  \
+  if (c16)                                                                                                         \
+    launch_timed(k_spmv_sketch<T, 2, Z, true>, g2, dim3(kThreads), lds, s, e0, e1, n, rp, ci, cr, va, x, y, d, zeta, \
+                 scale, k0, k1, parts, st, bs, nts);                                                               \
+  else                                                                                                             \
+    launch_timed(k_spmv_sketch<T, 2, Z>, g2, dim3(kThreads), lds, s, e0, e1, n, rp, ci, cr, va, x, y, d, zeta,       \
+                 scale, k0, k1, parts, st, bs, nts)
 #define FAB_Z(M)           \
   if (zeta <= 1) {         \
     FAB_L(M, 1);           \
@@ -1426,14 +1441,15 @@ int spmv_blocks_per_cu(int dtype, int mode, int d, int G, int zeta, bool c16) {
 
 hipError_t launch_spmv_sketch(hipStream_t s, int dtype, int mode, int grid, int n, const int* rp, const int* ci,
                               const int16_t* cr, const void* va, const void* x, void* y, int d, int zeta, uint64_t seed,
-                              double* parts, const State* st, int nb, int G, size_t bs, int nts) {
+                              double* parts, const State* st, int nb, int G, size_t bs, int nts, hipEvent_t e0,
+                              hipEvent_t e1) {
   // the partials need a grid of whole XCD rounds within the partial buffer (part_index)
   if (mode != 2 && (grid < kXcds || grid > kMaxParts || grid % kXcds != 0)) return hipErrorInvalidValue;
   if (dtype == 0)
     return launch_spmv_sketch_t<double>(s, mode, grid, n, rp, ci, cr, (const double*)va, (const double*)x,
-                                        (double*)y, d, zeta, seed, parts, st, nb, G, bs, nts);
+                                        (double*)y, d, zeta, seed, parts, st, nb, G, bs, nts, e0, e1);
   return launch_spmv_sketch_t<float>(s, mode, grid, n, rp, ci, cr, (const float*)va, (const float*)x, (float*)y, d,
-                                     zeta, seed, parts, st, nb, G, bs, nts);
+                                     zeta, seed, parts, st, nb, G, bs, nts, e0, e1);
 }
 
 hipError_t launch_reduce_parts(hipStream_t s, int e0, int len, int nparts, const double* parts, double* out,
@@ -1462,7 +1478,7 @@ hipError_t launch_orth(hipStream_t s, int j, int k, int m, int d, const double* 
 
 hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j, int k, int m, int d, void* W,
                               const double* uraw, double* U, double* R, double* G, State* st, int nb, size_t bs,
-                              const double* parts, int nparts, int nts) {
+                              const double* parts, int nparts, int nts, hipEvent_t e0, hipEvent_t e1) {
   if (parts && (nparts < 1 || nparts > 64)) return hipErrorInvalidValue;  // one partial per lane
   const int ob = dtype == 0 ? (nts ? OuBatch<double, kAuxNt>::v : OuBatch<double, 0>::v)
                             : (nts ? OuBatch<float, kAuxNt>::v : OuBatch<float, 0>::v);
@@ -1470,8 +1486,8 @@ hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j
   const int grid = std::max(1, std::min(nbat, ou_blocks_per_cu(nts) * num_cu));
   const dim3 g(grid, nb);
 #define FAB_OU2(TT, KK, INL, AUX)                                                                              \
-  hipLaunchKernelGGL((k_orth_update<TT, KK, INL, AUX>), g, dim3(kOuThreads), 0, s, n, j, k, m, d, (TT*)W, uraw, U, R, \
-                     G, st, bs, parts, nparts)
+  launch_timed(k_orth_update<TT, KK, INL, AUX>, g, dim3(kOuThreads), 0, s, e0, e1, n, j, k, m, d, (TT*)W, uraw, U, R, \
+               G, st, bs, parts, nparts)
 #define FAB_OU(TT, KK)               \
   if (parts) {                       \
     if (nts) {                       \
@@ -1503,7 +1519,8 @@ hipError_t launch_orth_update(hipStream_t s, int dtype, int num_cu, int n, int j
 }
 
 template <typename T>
-static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st, int nb, size_t bs) {
+static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, const State* st, int nb, size_t bs,
+                            hipEvent_t e0, hipEvent_t e1) {
   const dim3 g(grid, nb);
   // k_update: one 16-byte vector per thread and trip, so a quarter (FP32) or half (FP64) of the
   // element grid, in whole XCD rounds
@@ -1511,19 +1528,19 @@ static void launch_update_t(hipStream_t s, int grid, int n, int j, int k, T* W, 
   const int gv = std::max(kXcds, std::min(grid, ((nv + kThreads - 1) / kThreads + kXcds - 1) / kXcds * kXcds));
   const dim3 g16(gv, nb);
   if (k <= 4)
-    hipLaunchKernelGGL((k_update<T, 4>), g16, dim3(kThreads), 0, s, n, j, W, st, bs);
+    launch_timed(k_update<T, 4>, g16, dim3(kThreads), 0, s, e0, e1, n, j, W, st, bs);
   else if (k <= 8)
-    hipLaunchKernelGGL((k_update<T, 8>), g16, dim3(kThreads), 0, s, n, j, W, st, bs);
+    launch_timed(k_update<T, 8>, g16, dim3(kThreads), 0, s, e0, e1, n, j, W, st, bs);
   else
-    hipLaunchKernelGGL((k_update_wide<T>), g, dim3(kThreads), 0, s, n, j, W, st, bs);
+    launch_timed(k_update_wide<T>, g, dim3(kThreads), 0, s, e0, e1, n, j, W, st, bs);
 }
 
 hipError_t launch_update(hipStream_t s, int dtype, int grid, int n, int j, int k, void* W, const State* st, int nb,
-                         size_t bs) {
+                         size_t bs, hipEvent_t e0, hipEvent_t e1) {
   if (dtype == 0)
-    launch_update_t<double>(s, grid, n, j, k, (double*)W, st, nb, bs);
+    launch_update_t<double>(s, grid, n, j, k, (double*)W, st, nb, bs, e0, e1);
   else
-    launch_update_t<float>(s, grid, n, j, k, (float*)W, st, nb, bs);
+    launch_update_t<float>(s, grid, n, j, k, (float*)W, st, nb, bs, e0, e1);
   return hipGetLastError();
 }
 
