@@ -786,9 +786,17 @@ __global__ __launch_bounds__(kThreads) void k_combine(SmallArgs a0) {
   for (int e = threadIdx.x; e < (m + 1) * nt; e += kThreads) {
     const int i = e % (m + 1), it = e / (m + 1);
     double v = 0.0;
-    if (!zero && i < mm) {
+    if (!zero && i < mm) {  // eight loads in flight, added in node order
       const double* g = a.gbuf + (size_t)it * nq * m + i;
-      for (int l = 0; l < nq; ++l) v += g[(size_t)l * m];
+      int l = 0;
+      for (; l + 8 <= nq; l += 8) {
+        double t8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t8[u] = g[(size_t)(l + u) * m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t8[u];
+      }
+      for (; l < nq; ++l) v += g[(size_t)l * m];
     }
     a.C[e] = v;
   }
