@@ -302,10 +302,11 @@ fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
 
 /* Kernel timing for benchmarks.  While enabled, every fab_solve enqueues its cycles directly on
  * the context's stream (instead of replaying the cycle graph: the same kernels with the same
- * launch configuration).  on = 1: HIP events around each launch of the fused SpMV + sketch
- * kernel (the product and sketch of Algorithm 1), around each window update (Algorithm 1's basis
- * update: the fused Gram-Schmidt + update kernel, or the update kernel alone), and around each
- * cycle's m-step loop, accumulating their durations.  on = 2: events around each full cycle's
+ * launch configuration).  on = 1: HIP events recorded by each launch of the fused SpMV + sketch
+ * kernel (the product and sketch of Algorithm 1) and of each window update (Algorithm 1's basis
+ * update: the fused Gram-Schmidt + update kernel, or the update kernel alone) at the kernel's own
+ * start and end (extended launches that record them), and around each cycle's m-step loop,
+ * accumulating their durations.  on = 2: events around each full cycle's
  * m-step loop only (no events between its kernels, which would add their own gaps); the kernel
  * totals stay 0.  on = 0: off (graph replay again).
  * fab_timing_read returns the totals since the last read and clears them.  Counts only steps
