@@ -45,6 +45,11 @@ def test_status_strings_and_null_argument_checks():
     assert lib.fab_destroy(None) == -1
     p = _lib.fab_params(20, 2, 80, 8, 1, 1e-10, 10, 0, 0, 0.0, 0.0)
     assert lib.fab_workspace_size(None, ctypes.byref(p), 1, None) == -1
+    flag = ctypes.c_int32(7)
+    assert lib.fab_op_store_policy(None, 0, ctypes.byref(flag)) == -1 and flag.value == 7
+    assert lib.fab_op_index_bytes(None, ctypes.byref(flag)) == -1
+    assert lib.fab_batch_group(None, 4) == -1
+    assert lib.fab_timing_enable(None, 1) == -1
 
 
 def test_ctypes_struct_layout_matches_c(tmp_path):
