@@ -1219,22 +1219,30 @@ def test_growing_restart_unsupported_cases(fab, ctx):
     assert codes == [-2, -2, -2]  # FAB_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("N,d,zeta", [(20, 1200, 8), (40, 3600, 8), (40, 3600, 1)])
-def test_unrestarted_large_sketch_matches_oracle(fab, ctx, N, d, zeta):
+@pytest.mark.parametrize("N,d,zeta,m", [(20, 1200, 8, 60), (40, 3600, 8, 60), (40, 3600, 1, 60),
+                                         (40, 4096, 8, 64)])
+def test_unrestarted_large_sketch_matches_oracle(fab, ctx, N, d, zeta, m):
     """One cycle (no restart) with full sketched Gram-Schmidt (k = m) and a large sketch, d = 1200
     and 3600 (the paper's sketch for its unrestarted method on the membrane, Section 5.4): the shape
     of the paper's unrestarted randomized Arnoldi; exercises the whitening with the basis in global
     scratch (d > 512), the large-d Gram-Schmidt wavefront and, at d = 3600, the product kernel with
-    its four 28 KB bin sets (one block per CU)."""
+    its four 28 KB bin sets (one block per CU).  The last case is the largest the library takes,
+    d = 4096 and m = 64; one row or one step more is refused."""
     A = wl.convdiff_3d(N, 20.0)
     op = _op(fab, ctx, A)
     b = wl.gaussian_vector(A.n, 21)
     t = 2e-4
-    kw = dict(m=60, k=60, d=d, zeta=zeta, seed=9, tol=1e-12, max_cycles=1)
+    kw = dict(m=m, k=m, d=d, zeta=zeta, seed=9, tol=1e-12, max_cycles=1)
+    if d == 4096:
+        bt = torch.as_tensor(b, device="cuda")
+        for bad in (dict(kw, d=4097), dict(kw, m=65, k=65)):
+            with pytest.raises(fab.FabError) as err:  # refused when the workspace is sized
+                fab.solve(op, bt, "exp", t=t, check=False, **bad)
+            assert err.value.status == -1, bad  # FAB_E_INVALID
     x, info = fab.solve(op, torch.as_tensor(b, device="cuda"), "exp", t=t, check=False, **kw)
     assert info["cycles"] == 1 and info["code"] >= 0
     S = sketch.sketch_matrix(A.n, d, zeta, seed=9)
-    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=60, k=60, S=S, tol=1e-12, max_cycles=1)
+    xo, io = krylov.restart_solve(A.to_scipy(), b, "exp", t, m=m, k=m, S=S, tol=1e-12, max_cycles=1)
     assert _rel(x[:, 0].cpu().numpy(), xo) <= 1e-10
     # full window: S W orthonormal up to the loss of orthogonality of one modified Gram-Schmidt pass
     assert info["kappa_T"] == pytest.approx(1.0, abs=1e-7)
