@@ -910,6 +910,27 @@ def test_batched_matches_single_solves(fab, ctx, group):
             assert _rel(xb, exact.sine_fab("exp", Bm[:, r], N, [1.0, 0.01], 0.0, t=t)) <= 1e-9
 
 
+def test_batched_at_the_member_limit(fab, ctx):
+    """1024 right-hand sides, the most one batched solve takes, on the 2-D Laplacian N = 16: every
+    member converges, and members 0, 511 and 1023 match their single solves and the closed form; a
+    1025th member is refused."""
+    N, nb = 16, 1024
+    A = wl.laplacian_2d(N)
+    op = _op(fab, ctx, A)
+    Bm = np.stack([wl.gaussian_vector(A.n, 5000 + r) for r in range(nb)], axis=1)
+    kw = dict(m=10, k=2, d=40, zeta=8, seed=3, tol=1e-10, max_cycles=100)
+    X, infos = fab.solve_batched(op, torch.as_tensor(Bm, device="cuda"), "exp", t=1e-2, **kw)
+    assert all(i["status"] == "FAB_OK" for i in infos), {i["status"] for i in infos}
+    for r in (0, 511, 1023):
+        xs, info_s = fab.solve(op, torch.as_tensor(Bm[:, r], device="cuda"), "exp", t=1e-2, **kw)
+        assert infos[r]["cycles"] == info_s["cycles"]
+        assert _rel(X[:, r, 0].cpu().numpy(), xs[:, 0].cpu().numpy()) <= 1e-12
+        assert _rel(X[:, r, 0].cpu().numpy(), exact.sine_fab("exp", Bm[:, r], N, [1, 1], t=1e-2)) <= 1e-9
+    with pytest.raises(fab.FabError) as err:
+        fab.solve_batched(op, torch.zeros((A.n, nb + 1), dtype=torch.float64, device="cuda"), "exp", t=1e-2, **kw)
+    assert err.value.status == -1  # FAB_E_INVALID
+
+
 @pytest.mark.parametrize("group", [1, 4, 16], indirect=True)
 def test_batched_members_finish_differently(fab, ctx, group):
     """One batch holding a zero right-hand side (exact at once), an eigenvector (breakdown after one
