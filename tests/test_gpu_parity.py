@@ -332,6 +332,24 @@ def test_multiple_time_points(fab, ctx):
         assert _rel(x[:, i].cpu().numpy(), ref) <= 1e-9, t
 
 
+def test_sixteen_time_points(fab, ctx):
+    """16 time points in one solve, the most the library takes (the pass's widest form): each column
+    against the closed form; a 17th is refused."""
+    N = 40
+    A = wl.anisotropic_2d(N, 0.01)
+    op = _op(fab, ctx, A)
+    b = wl.gaussian_vector(A.n, 2)
+    ts = [10.0 ** (-5 + 2 * i / 15) for i in range(16)]
+    bt = torch.as_tensor(b, device="cuda")
+    x, info = fab.solve(op, bt, "exp", t=ts, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10, max_cycles=200)
+    assert info["status"] == "FAB_OK", info
+    for i, t in enumerate(ts):
+        assert _rel(x[:, i].cpu().numpy(), exact.sine_fab("exp", b, N, [1, 0.01], t=t)) <= 1e-9, t
+    with pytest.raises(fab.FabError) as err:
+        fab.solve(op, bt, "exp", t=ts + [2e-3], m=20, k=2, d=80, zeta=8, seed=1, tol=1e-10)
+    assert err.value.status == -1  # FAB_E_INVALID
+
+
 def test_invsqrt_shifted_laplacian(fab, ctx):
     N = 16
     A = wl.shifted_laplacian_3d(N, 1.0)
