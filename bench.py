@@ -470,7 +470,8 @@ def extra_legs(fab, ctx):
         ops.append(fab.CSROperator.from_arrays(ctx, Ag.rowptr, Ag.colind, Ag.vals, dtype=torch.float32))
         bs.append(torch.as_tensor(bg, device="cuda"))
         b64s.append(bg.astype(np.float64))
-    sec, (xs, infos) = _timed(lambda: fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw))
+    xs_out = fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw)[0]   # outputs kept: the timed calls replay one graph
+    sec, (xs, infos) = _timed(lambda: fab.solve_ragged(ops, bs, "exp", t=1e-3, xs=xs_out, **kw))
     xr = [v[:, 0].cpu().numpy() for v in xs]
     leg = {"workload": "32 laplacian_2d, N = 64 .. 512 (geometric), exp t = 1e-3", "values": "f32",
            "rows_total": sum(Ng * Ng for Ng in Ns), "operators_per_s": 32 / sec, "seconds": sec,
@@ -478,7 +479,7 @@ def extra_legs(fab, ctx):
     checks.append((leg, "rel_err_max", lambda ex, xr=xr, b64s=b64s, Ns=Ns: max(
         rel(xr[i], ex.sine_fab("exp", b64s[i], Ng, [1, 1], 0.0, t=1e-3)) for i, Ng in enumerate(Ns))))
     out["ragged_32"] = leg
-    del ops, bs, xs
+    del ops, bs, xs, xs_out
     torch.cuda.empty_cache()
     # --- gradient of <c, exp(-tA) b>: 96^3 convection-diffusion, Pe 20, t = 1e-4
     N, t = 96, 1e-4

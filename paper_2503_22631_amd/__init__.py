@@ -226,11 +226,15 @@ def solve_batched(op: CSROperator, B: torch.Tensor, fun: str = "exp", t=1e-3, wo
     return x.view(nb, nt, op.n).permute(2, 0, 1), [_info_dict(infos[r], st) for r in range(nb)]
 
 
-def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None, check: bool = True, **kw):
+def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = None, check: bool = True,
+                 xs=None, **kw):
     """[f(A_i) b_i] for operators of uneven size in one ragged solve (fab_solve_ragged).
 
     ``ops`` and ``bs`` are equal-length lists (b_i on the device, in A_i's dtype).  Returns
-    (xs, infos): xs[i] of shape (n_i, nt) FP64, and one info dict per operator.
+    (xs, infos): xs[i] of shape (n_i, nt) FP64, and one info dict per operator.  ``xs`` may pass in
+    the outputs of an earlier call (or tensors of that shape and layout) to be written again: the
+    captured ragged graph is keyed on the output addresses among other things, so a repeated call on
+    the same outputs replays it without capturing it again.
     """
     ctx = ops[0].ctx
     nops = len(ops)
@@ -241,7 +245,13 @@ def solve_ragged(ops, bs, fun: str = "exp", t=1e-3, work: torch.Tensor | None = 
     bs = [b.contiguous() for b in bs]
     for op, b in zip(ops, bs):
         assert b.is_cuda and b.dtype == op.dtype and b.numel() == op.n
-    xs = [torch.empty((nt, op.n), dtype=torch.float64, device=ctx.device) for op in ops]
+    if xs is None:
+        xs = [torch.empty((nt, op.n), dtype=torch.float64, device=ctx.device) for op in ops]
+    else:
+        assert len(xs) == nops
+        xs = [v.t() for v in xs]
+        for op, v in zip(ops, xs):
+            assert v.is_cuda and v.dtype == torch.float64 and v.shape == (nt, op.n) and v.is_contiguous()
     handles = (ctypes.c_void_p * nops)(*[op.handle.value for op in ops])
     nbytes = ctypes.c_size_t()
     _lib.check(ctx.lib.fab_workspace_size_ragged(nops, handles, ctypes.byref(p), nt, ctypes.byref(nbytes)),

@@ -1175,7 +1175,8 @@ def test_ragged_mixed_types_and_zero_rhs(fab):
 def test_ragged_32_laplacians_full_size(fab, ctx):
     """The ragged half of the batched workload: 32 Laplacians on grids from 64^2 to 512^2 (FP32),
     t = 1e-3, b_i from seed 1000+i, m=20, k=2, d=80, tol 1e-6, in one ragged solve; every operator
-    against the closed form."""
+    against the closed form.  A second call into the same outputs (the cached graph replayed, as the
+    benchmark times it) repeats the bits and cycle counts."""
     Ns = _ragged_sizes(32)
     assert Ns[0] == 64 and Ns[-1] == 512
     ops, bs, bs64 = [], [], []
@@ -1196,6 +1197,13 @@ def test_ragged_32_laplacians_full_size(fab, ctx):
     print(f"ragged 32 Laplacians 64^2..512^2: cycles {max(i['cycles'] for i in infos)} worst rel err {worst:.2e}, "
           f"{used:.2f} of tol + the FP32 floor", flush=True)
     assert used <= 1.0
+    first = [v.cpu().clone() for v in xs]
+    ptrs = [v.data_ptr() for v in xs]
+    xs2, infos2 = fab.solve_ragged(ops, bs, "exp", t=1e-3, xs=xs, m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6,
+                                   max_cycles=300)
+    assert [v.data_ptr() for v in xs2] == ptrs
+    assert [i["cycles"] for i in infos2] == [i["cycles"] for i in infos]
+    assert all(torch.equal(a.cpu(), b) for a, b in zip(xs2, first))
 
 
 # --------------------------------------------------------------- growing-matrix restart (Alg. 2)
