@@ -778,9 +778,10 @@ fab_status fab_workspace_size_batched(const fab_op* A, const fab_params* p, int3
 // kept for this operator and batch shape.  Runs before the solve's set-up, which clears what the
 // timing launches wrote.
 // Whether the grouped kernel can serve G members per block: its dynamic LDS (G d FP64 bins, the
-// tile's table of S, the CSR chunk) within what configure_step_kernels allows.
-static bool group_fits(int dtype, const fab_params* p, int G) {
-  return spmv_sketch_lds(dtype, 0, p->d, G, p->zeta, false) <= group_lds_max() &&
+// tile's table of S, the CSR chunk) within what configure_step_kernels allows, and each member's
+// vector addressable as one buffer (n times the value size below 2^31 bytes).
+static bool group_fits(int dtype, int64_t n, const fab_params* p, int G) {
+  return n * (dtype == 0 ? 8 : 4) <= INT32_MAX && spmv_sketch_lds(dtype, 0, p->d, G, p->zeta, false) <= group_lds_max() &&
          spmv_sketch_lds(dtype, 1, p->d, G, p->zeta, false) <= group_lds_max();
 }
 
@@ -789,7 +790,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   *G_out = 1;
   if (nb <= 1 || p->method == FAB_PLAIN_RESTART) return FAB_OK;
   if (ctx->force_group > 0) {  // a forced group the grouped kernel cannot serve falls back to 1
-    *G_out = (ctx->force_group > 1 && !group_fits(A->dtype, p, ctx->force_group)) ? 1 : ctx->force_group;
+    *G_out = (ctx->force_group > 1 && !group_fits(A->dtype, A->n, p, ctx->force_group)) ? 1 : ctx->force_group;
     return FAB_OK;
   }
   for (const auto& t : ctx->tuned)
@@ -809,7 +810,7 @@ static fab_status tune_group(fab_ctx* ctx, const fab_op* A, const fab_params* p,
   // candidates: one member per block, or groups of 4, 8 or 16 (one to four members per wavefront;
   // padding members past nb cost nothing)
   for (int G = 1; G <= 16 && err == hipSuccess; G = (G == 1 ? 4 : 2 * G)) {
-    if (G > 1 && (!group_fits(dt, p, G) || G > 4 * nb)) break;
+    if (G > 1 && (!group_fits(dt, A->n, p, G) || G > 4 * nb)) break;
     const int grid = spmv_grid(ctx, n, dt, 0, d, G, p->zeta, A->colrel != nullptr);
     void* x0 = q.W;
     void* y0 = (char*)q.W + wcol(n, (int)es) * es;

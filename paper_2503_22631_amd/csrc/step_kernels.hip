@@ -415,11 +415,57 @@ __host__ __device__ inline size_t grp_lds_table(int zmax) {
   return ((size_t)kThreads * (2 * zmax + 4) + 15) & ~(size_t)15;
 }
 
-// Occupancy hint: LDS holds 5 FP32 or 4 FP64 blocks per CU at d = 80 (bins, table, chunk), and the
-// registers of four members' gathers fit those waves without spilling.
+// Occupancy hint: 4 waves per SIMD, whose 128 registers hold the gathers of four FP32 members
+// (two FP64) in flight without spilling; at 5 (the most LDS allows for FP32 blocks at d = 80) the
+// FP32 kernel spills.
 template <typename T>
 constexpr int grp_min_waves() {
   return sizeof(T) == 4 ? 5 : 4;
+}
+
+// Buffer resources and loads (defined with the window update below).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int bytes);
+template <int AUX>
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off, double);
+template <int AUX>
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, float);
+
+// row_dot for the NM members a wavefront owns in the grouped kernel (NM = G / 4).  Each pass reads
+// its kGather LDS entries once (entries past the row's end read its last entry, with value 0 and
+// the byte offset `end`, one past every member's resource) and forms their byte offsets once;
+// every member's gathers are then buffer loads at those offsets (rx[u]: member u's x, of `end`
+// bytes; a size-0 resource for a member that has finished), with no address arithmetic and no
+// branch per member, two members' gathers issued before their products.  Out-of-range loads
+// return 0 without touching memory.  Per member the sums are row_dot's: entries in order, FP64 fma.
+template <typename T, int NM>
+__device__ __forceinline__ void row_dot_members(const T* sv, const int* sc, const __amdgpu_buffer_rsrc_t (&rx)[kWaveMembers],
+                                                int lo, int hi, int cs, int end, double (&acc)[kWaveMembers]) {
+  constexpr int MF = NM < 2 ? NM : 2;  // members in flight: four FP32 members' gathers spill at 5 waves
+  for (int pg = lo; pg < hi; pg += kGather) {
+    T av[kGather];
+    int bo[kGather];
+#pragma unroll
+    for (int q = 0; q < kGather; ++q) {
+      const int p = pg + q;
+      const int pc = min(p, hi - 1) - cs;  // an entry of this row in the chunk (pg < hi)
+      const T a = sv[pc];
+      const int c = sc[pc];
+      av[q] = (p < hi) ? a : T(0);
+      bo[q] = (p < hi) ? c * (int)sizeof(T) : end;
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < NM; u0 += MF) {
+      T xv[MF][kGather];
+#pragma unroll
+      for (int v = 0; v < MF; ++v)
+#pragma unroll
+        for (int q = 0; q < kGather; ++q) xv[v][q] = buf_load<0>(rx[u0 + v], bo[q], T());
+#pragma unroll
+      for (int v = 0; v < MF; ++v)
+#pragma unroll
+        for (int q = 0; q < kGather; ++q) acc[u0 + v] = fma((double)av[q], (double)xv[v][q], acc[u0 + v]);
+    }
+  }
 }
 
 template <typename T, int MODE, int ZMAX>
@@ -462,6 +508,7 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
   T* ys[kWaveMembers];
   int gs[kWaveMembers];
   bool own[kWaveMembers];
+  __amdgpu_buffer_rsrc_t rx[kWaveMembers];  // the members' x as buffers (n es < 2^31: see the launcher)
 #pragma unroll
   for (int u = 0; u < kWaveMembers; ++u) {
     const int g = wv * per_wave + u;
@@ -469,6 +516,7 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
     gs[u] = g;
     xs[u] = bat(x, bs, r0 + (own[u] ? g : 0));
     ys[u] = bat(y, bs, r0 + (own[u] ? g : 0));
+    rx[u] = buf_rsrc(xs[u], own[u] ? n * (int)sizeof(T) : 0);
   }
   const double dscale = (double)scale;
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -527,10 +575,21 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
       for (int u = 0; u < kWaveMembers; ++u) acc[u] = 0.0;
       if (MODE == 0) {
         const int lo = live ? rowptr[row] : 0, hi = live ? rowptr[row + 1] : 0;
-        if (one_chunk) {
+        // the shared gathers for FP32 values and tables of up to 8 rows: wider tables leave no
+        // registers for them, and FP64 buffer loads issue as two 32-bit loads each (measured 8 - 10%
+        // slower than one global load per member and entry on 16 FP64 members of 512^2)
+        if (one_chunk && (ZMAX > 8 || sizeof(T) == 8)) {
 #pragma unroll
           for (int u = 0; u < kWaveMembers; ++u)
             if (own[u]) acc[u] = row_dot(sv, sc, 0, xs[u], lo, hi, p0, 0.0);
+        } else if (one_chunk) {
+          const int end = n * (int)sizeof(T);
+          if (per_wave == 4)  // uniform over the block
+            row_dot_members<T, 4>(sv, sc, rx, lo, hi, p0, end, acc);
+          else if (per_wave == 2)
+            row_dot_members<T, 2>(sv, sc, rx, lo, hi, p0, end, acc);
+          else
+            row_dot_members<T, 1>(sv, sc, rx, lo, hi, p0, end, acc);
         } else {  // a tile with more than kChunk nonzeros: its chunks in turn, for this row group
           for (int cs = p0; cs < p1; cs += kChunk) {
             const int len = min(kChunk, p1 - cs);
@@ -546,20 +605,37 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
           if (own[u]) acc[u] = (double)xs[u][row];
       }
       if (live) {
-        uint16_t rows[ZMAX];
-#pragma unroll
-        for (int l = 0; l < ZMAX; ++l) rows[l] = trow[lr * ZMAX + l];
+        // the row's bin offsets and sign bits, formed once for all members and before the member
+        // branches (formed inside them, every branch join waited for the table's LDS reads again,
+        // and with them for all scatter atomics issued so far); for ZMAX > 8 the 2 ZMAX registers
+        // would spill, and they are formed per member instead
+        constexpr int ZH = ZMAX <= 8 ? ZMAX : 1;
+        uint32_t boff[ZH], sgn[ZH];
         const uint32_t sb = tsgn[lr];
+        if (ZMAX <= 8) {
+#pragma unroll
+          for (int l = 0; l < ZH; ++l) {
+            boff[l] = (uint32_t)trow[lr * ZMAX + l] * 8u;
+            sgn[l] = ((sb >> l) & 1u) << 31;
+          }
+        }
 #pragma unroll
         for (int u = 0; u < kWaveMembers; ++u) {
           if (!own[u]) continue;  // uniform over the wavefront
           const T z = (T)acc[u];
           if (MODE == 0) ys[u][row] = z;
           const double zs = (double)z * dscale;
-          double* mb = bins + (size_t)gs[u] * d;
+          const uint32_t zlo = (uint32_t)__double_as_longlong(zs);
+          const uint32_t zhi = (uint32_t)((uint64_t)__double_as_longlong(zs) >> 32);
+          unsigned char* mb = reinterpret_cast<unsigned char*>(bins + (size_t)gs[u] * d);
 #pragma unroll
           for (int l = 0; l < ZMAX; ++l)
-            if (l < zeta) unsafeAtomicAdd(&mb[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+            if (l < zeta) {  // -zs for a set sign bit: the same value as negation
+              const uint32_t bo = ZMAX <= 8 ? boff[l % ZH] : (uint32_t)trow[lr * ZMAX + l] * 8u;
+              const uint32_t sg = ZMAX <= 8 ? sgn[l % ZH] : ((sb >> l) & 1u) << 31;
+              unsafeAtomicAdd(reinterpret_cast<double*>(mb + bo),
+                              __longlong_as_double((long long)(((uint64_t)(zhi ^ sg) << 32) | zlo)));
+            }
         }
       }
     }
@@ -1313,7 +1389,8 @@ static hipError_t launch_spmv_sketch_t(hipStream_t s, int mode, int grid, int n,
                                        hipEvent_t e0, hipEvent_t e1) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T scale = (T)(1.0 / sqrt((double)zeta));
-  if (G > 1 && (mode == 2 || G % kWaves != 0 || G > kGroupMax)) return hipErrorInvalidValue;
+  if (G > 1 && (mode == 2 || G % kWaves != 0 || G > kGroupMax || (int64_t)n * (int64_t)sizeof(T) > INT32_MAX))
+    return hipErrorInvalidValue;
   const size_t lds = spmv_sketch_lds(sizeof(T) == 8 ? 0 : 1, mode, d, G, zeta, cr != nullptr);
   const dim3 g2(grid, (nb + G - 1) / G);
   const bool c16 = cr != nullptr && mode != 1;  // the sketch-only mode stages no CSR chunk
