@@ -432,14 +432,17 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int off, flo
 
 // row_dot for the NM members a wavefront owns in the grouped kernel (NM = G / 4).  Each pass reads
 // its kGather LDS entries once (entries past the row's end read its last entry, with value 0 and
-// the byte offset `end`, one past every member's resource) and forms their byte offsets once;
-// every member's gathers are then buffer loads at those offsets (rx[u]: member u's x, of `end`
-// bytes; a size-0 resource for a member that has finished), with no address arithmetic and no
-// branch per member, two members' gathers issued before their products.  Out-of-range loads
-// return 0 without touching memory.  Per member the sums are row_dot's: entries in order, FP64 fma.
+// the byte offset `end`, one past every member's buffer) and forms their byte offsets once; every
+// member's gathers are then buffer loads at those offsets (member u's x as a buffer of `end` bytes,
+// of 0 bytes for a member that has finished), with no address arithmetic and no branch per member,
+// two members' gathers issued before their products.  Out-of-range loads return 0 without
+// touching memory.  Per member the sums are row_dot's: entries in order, FP64 fma.  The buffer
+// resources are formed at each use: held across the kernel, their scalar registers pushed other
+// values into vector registers, and those into scratch.
 template <typename T, int NM>
-__device__ __forceinline__ void row_dot_members(const T* sv, const int* sc, const __amdgpu_buffer_rsrc_t (&rx)[kWaveMembers],
-                                                int lo, int hi, int cs, int end, double (&acc)[kWaveMembers]) {
+__device__ __forceinline__ void row_dot_members(const T* sv, const int* sc, const T* const (&xs)[kWaveMembers],
+                                                const bool (&own)[kWaveMembers], int lo, int hi, int cs, int end,
+                                                double (&acc)[kWaveMembers]) {
   constexpr int MF = NM < 2 ? NM : 2;  // members in flight: four FP32 members' gathers spill at 5 waves
   for (int pg = lo; pg < hi; pg += kGather) {
     T av[kGather];
@@ -457,9 +460,11 @@ __device__ __forceinline__ void row_dot_members(const T* sv, const int* sc, cons
     for (int u0 = 0; u0 < NM; u0 += MF) {
       T xv[MF][kGather];
 #pragma unroll
-      for (int v = 0; v < MF; ++v)
+      for (int v = 0; v < MF; ++v) {
+        const __amdgpu_buffer_rsrc_t rx = buf_rsrc(xs[u0 + v], own[u0 + v] ? end : 0);
 #pragma unroll
-        for (int q = 0; q < kGather; ++q) xv[v][q] = buf_load<0>(rx[u0 + v], bo[q], T());
+        for (int q = 0; q < kGather; ++q) xv[v][q] = buf_load<0>(rx, bo[q], T());
+      }
 #pragma unroll
       for (int v = 0; v < MF; ++v)
 #pragma unroll
@@ -508,7 +513,6 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
   T* ys[kWaveMembers];
   int gs[kWaveMembers];
   bool own[kWaveMembers];
-  __amdgpu_buffer_rsrc_t rx[kWaveMembers];  // the members' x as buffers (n es < 2^31: see the launcher)
 #pragma unroll
   for (int u = 0; u < kWaveMembers; ++u) {
     const int g = wv * per_wave + u;
@@ -516,7 +520,6 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
     gs[u] = g;
     xs[u] = bat(x, bs, r0 + (own[u] ? g : 0));
     ys[u] = bat(y, bs, r0 + (own[u] ? g : 0));
-    rx[u] = buf_rsrc(xs[u], own[u] ? n * (int)sizeof(T) : 0);
   }
   const double dscale = (double)scale;
   const int ntiles = (n + kThreads - 1) / kThreads;
@@ -533,36 +536,50 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
       one_chunk = (p1 - p0) <= kChunk;
     }
     __syncthreads();  // the previous tile's chunk and table have been read (and the bins zeroed)
-    T tv[kChunk / kThreads];
-    int tc[kChunk / kThreads];
-    if (MODE == 0 && one_chunk) {
+    // The tile's CSR chunk staged in LDS and the table rows of S generated.  FP64: the table while
+    // the chunk's loads are in flight.  FP32 (whose row loop holds more registers): the chunk in two
+    // halves, then the table; staged whole, with the table in between, the loaded values were
+    // spilled to scratch one load at a time.
+    {
+      constexpr int kParts = sizeof(T) == 4 ? 2 : 1;
+      constexpr int kPer = kChunk / kThreads / kParts;
+      const bool stage = MODE == 0 && one_chunk;
+      auto gen_table = [&]() {
+        const int row = row0 + threadIdx.x;
+        int rows[ZMAX];
+        uint32_t sb = 0;
+        if (row < n) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
 #pragma unroll
-      for (int q = 0; q < kChunk / kThreads; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        if (e < p1 - p0) {
-          tv[q] = vals[p0 + e];
-          tc[q] = colrel ? row0 + (int)colrel[p0 + e] : colind[p0 + e];
+        for (int l = 0; l < ZMAX; ++l) trow[threadIdx.x * ZMAX + l] = (row < n) ? (uint16_t)rows[l] : (uint16_t)0;
+        tsgn[threadIdx.x] = sb;
+      };
+#pragma unroll
+      for (int h = 0; h < kParts; ++h) {
+        T tv[kPer];
+        int tc[kPer];
+        if (stage) {
+#pragma unroll
+          for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + (h * kPer + q) * kThreads;
+            if (e < p1 - p0) {
+              tv[q] = vals[p0 + e];
+              tc[q] = colrel ? row0 + (int)colrel[p0 + e] : colind[p0 + e];
+            }
+          }
+        }
+        if (sizeof(T) == 8) gen_table();
+        if (stage) {
+#pragma unroll
+          for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + (h * kPer + q) * kThreads;
+            if (e < p1 - p0) {
+              sv[e] = tv[q];
+              sc[e] = tc[q];
+            }
+          }
         }
       }
-    }
-    {  // the table row of this thread's row, generated while the chunk's loads are in flight
-      const int row = row0 + threadIdx.x;
-      int rows[ZMAX];
-      uint32_t sb = 0;
-      if (row < n) sketch_column<ZMAX>((uint64_t)row, d, zeta, k0, k1, rows, sb);
-#pragma unroll
-      for (int l = 0; l < ZMAX; ++l) trow[threadIdx.x * ZMAX + l] = (row < n) ? (uint16_t)rows[l] : (uint16_t)0;
-      tsgn[threadIdx.x] = sb;
-    }
-    if (MODE == 0 && one_chunk) {
-#pragma unroll
-      for (int q = 0; q < kChunk / kThreads; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        if (e < p1 - p0) {
-          sv[e] = tv[q];
-          sc[e] = tc[q];
-        }
-      }
+      if (sizeof(T) == 4) gen_table();
     }
     __syncthreads();
 #pragma unroll 1
@@ -585,11 +602,11 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
         } else if (one_chunk) {
           const int end = n * (int)sizeof(T);
           if (per_wave == 4)  // uniform over the block
-            row_dot_members<T, 4>(sv, sc, rx, lo, hi, p0, end, acc);
+            row_dot_members<T, 4>(sv, sc, xs, own, lo, hi, p0, end, acc);
           else if (per_wave == 2)
-            row_dot_members<T, 2>(sv, sc, rx, lo, hi, p0, end, acc);
+            row_dot_members<T, 2>(sv, sc, xs, own, lo, hi, p0, end, acc);
           else
-            row_dot_members<T, 1>(sv, sc, rx, lo, hi, p0, end, acc);
+            row_dot_members<T, 1>(sv, sc, xs, own, lo, hi, p0, end, acc);
         } else {  // a tile with more than kChunk nonzeros: its chunks in turn, for this row group
           for (int cs = p0; cs < p1; cs += kChunk) {
             const int len = min(kChunk, p1 - cs);
@@ -605,37 +622,51 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
           if (own[u]) acc[u] = (double)xs[u][row];
       }
       if (live) {
-        // the row's bin offsets and sign bits, formed once for all members and before the member
-        // branches (formed inside them, every branch join waited for the table's LDS reads again,
-        // and with them for all scatter atomics issued so far); for ZMAX > 8 the 2 ZMAX registers
-        // would spill, and they are formed per member instead
-        constexpr int ZH = ZMAX <= 8 ? ZMAX : 1;
-        uint32_t boff[ZH], sgn[ZH];
-        const uint32_t sb = tsgn[lr];
-        if (ZMAX <= 8) {
+        // FP32 values and tables of up to 8 rows: the row's bin offsets and sign bits formed once
+        // for all members and before the member branches (formed inside them, every branch join
+        // waited for the table's LDS reads again, and with them for all scatter atomics issued so
+        // far).  Wider tables would spill their 2 ZMAX registers; FP64 members measured 7% slower
+        // with them (16 members of 512^2).
+        if (ZMAX <= 8 && sizeof(T) == 4) {
+          constexpr int ZH = ZMAX <= 8 ? ZMAX : 1;
+          uint32_t boff[ZH], sgn[ZH];
+          const uint32_t sb = tsgn[lr];
 #pragma unroll
           for (int l = 0; l < ZH; ++l) {
             boff[l] = (uint32_t)trow[lr * ZMAX + l] * 8u;
             sgn[l] = ((sb >> l) & 1u) << 31;
           }
-        }
 #pragma unroll
-        for (int u = 0; u < kWaveMembers; ++u) {
-          if (!own[u]) continue;  // uniform over the wavefront
-          const T z = (T)acc[u];
-          if (MODE == 0) ys[u][row] = z;
-          const double zs = (double)z * dscale;
-          const uint32_t zlo = (uint32_t)__double_as_longlong(zs);
-          const uint32_t zhi = (uint32_t)((uint64_t)__double_as_longlong(zs) >> 32);
-          unsigned char* mb = reinterpret_cast<unsigned char*>(bins + (size_t)gs[u] * d);
+          for (int u = 0; u < kWaveMembers; ++u) {
+            if (!own[u]) continue;  // uniform over the wavefront
+            const T z = (T)acc[u];
+            if (MODE == 0) ys[u][row] = z;
+            const double zs = (double)z * dscale;
+            const uint32_t zlo = (uint32_t)__double_as_longlong(zs);
+            const uint32_t zhi = (uint32_t)((uint64_t)__double_as_longlong(zs) >> 32);
+            unsigned char* mb = reinterpret_cast<unsigned char*>(bins + (size_t)gs[u] * d);
 #pragma unroll
-          for (int l = 0; l < ZMAX; ++l)
-            if (l < zeta) {  // -zs for a set sign bit: the same value as negation
-              const uint32_t bo = ZMAX <= 8 ? boff[l % ZH] : (uint32_t)trow[lr * ZMAX + l] * 8u;
-              const uint32_t sg = ZMAX <= 8 ? sgn[l % ZH] : ((sb >> l) & 1u) << 31;
-              unsafeAtomicAdd(reinterpret_cast<double*>(mb + bo),
-                              __longlong_as_double((long long)(((uint64_t)(zhi ^ sg) << 32) | zlo)));
-            }
+            for (int l = 0; l < ZH; ++l)
+              if (l < zeta)  // -zs for a set sign bit: the same value as negation
+                unsafeAtomicAdd(reinterpret_cast<double*>(mb + boff[l]),
+                                __longlong_as_double((long long)(((uint64_t)(zhi ^ sgn[l]) << 32) | zlo)));
+          }
+        } else {
+          uint16_t rows[ZMAX];
+#pragma unroll
+          for (int l = 0; l < ZMAX; ++l) rows[l] = trow[lr * ZMAX + l];
+          const uint32_t sb = tsgn[lr];
+#pragma unroll
+          for (int u = 0; u < kWaveMembers; ++u) {
+            if (!own[u]) continue;  // uniform over the wavefront
+            const T z = (T)acc[u];
+            if (MODE == 0) ys[u][row] = z;
+            const double zs = (double)z * dscale;
+            double* mb = bins + (size_t)gs[u] * d;
+#pragma unroll
+            for (int l = 0; l < ZMAX; ++l)
+              if (l < zeta) unsafeAtomicAdd(&mb[rows[l]], ((sb >> l) & 1u) ? -zs : zs);
+          }
         }
       }
     }
