@@ -593,8 +593,9 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
       if (MODE == 0) {
         const int lo = live ? rowptr[row] : 0, hi = live ? rowptr[row + 1] : 0;
         // the shared gathers for FP32 values and tables of up to 8 rows: wider tables leave no
-        // registers for them, and FP64 buffer loads issue as two 32-bit loads each (measured 8 - 10%
-        // slower than one global load per member and entry on 16 FP64 members of 512^2)
+        // registers for them, and the FP64 instantiations keep the previous form (with the shared
+        // gathers, the scatter below and the staging above they measured 7 - 10% slower on 16 and
+        // on 4 FP64 members of 512^2)
         if (one_chunk && (ZMAX > 8 || sizeof(T) == 8)) {
 #pragma unroll
           for (int u = 0; u < kWaveMembers; ++u)
@@ -625,8 +626,7 @@ __global__ __launch_bounds__(kThreads, (grp_min_waves<T>())) void k_spmv_sketch_
         // FP32 values and tables of up to 8 rows: the row's bin offsets and sign bits formed once
         // for all members and before the member branches (formed inside them, every branch join
         // waited for the table's LDS reads again, and with them for all scatter atomics issued so
-        // far).  Wider tables would spill their 2 ZMAX registers; FP64 members measured 7% slower
-        // with them (16 members of 512^2).
+        // far).  Wider tables would spill their 2 ZMAX registers; FP64 keeps the previous form.
         if (ZMAX <= 8 && sizeof(T) == 4) {
           constexpr int ZH = ZMAX <= 8 ? ZMAX : 1;
           uint32_t boff[ZH], sgn[ZH];
