@@ -234,7 +234,11 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
  * pointers.  Every operator runs the method of fab_solve in its own part of work
  * (fab_workspace_size_ragged bytes); the cycles of all operators are captured into one graph
  * (operators spread over 8 concurrent branches) that is replayed once per cycle until every
- * operator has finished.  h_info has nops entries; the return value is the most severe status.
+ * operator has finished.  A context keeps the graph of its first ragged call and replays it for
+ * later calls with the same operators, outputs, workspace, function, time count and parameters;
+ * a call that differs runs the same cycles uncaptured, one operator after another (same results,
+ * no concurrency between operators).  h_info has nops entries; the return value is the most
+ * severe status.
  * 1 <= nops <= 1024; FAB_PLAIN_RESTART is not supported (FAB_E_UNSUPPORTED). */
 fab_status fab_workspace_size_ragged(int32_t nops, const fab_op* const* ops, const fab_params* p, int32_t nt,
                                      size_t* h_bytes);

@@ -1142,11 +1142,13 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
     B.ldx = ops[i]->n;
     return enqueue_cycle(ctx, st, ops[i], p, fun, nt, L[i], q[i], x[i], ctx->h_rep + i, true, nullptr, B);
   };
-  if (!ctx->timing && (key != ctx->ragged_key || !ctx->ragged_exec)) {
-    if (ctx->ragged_exec) {
-      (void)hipGraphExecDestroy(ctx->ragged_exec);
-      ctx->ragged_exec = nullptr;
-    }
+  // The context's first ragged call captures its graph, and calls with the same key replay it.
+  // A call with another key does not replace it: its cycles run uncaptured, one operator after
+  // another on the work stream, as in timing mode.  (Replacing the graph, a new capture over the
+  // same branch streams and fork/join events, is the call in which a host segmentation fault was
+  // seen once, with its cause not found; that path is switched off.)
+  const bool eager = ctx->timing || (ctx->ragged_exec && key != ctx->ragged_key);
+  if (!eager && !ctx->ragged_exec) {
     FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     fab_status es = FAB_OK;
     hipError_t he = hipEventRecord(ctx->fork, s);
@@ -1178,7 +1180,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   std::vector<Track> tr(nops);
   int remaining = nops;
   for (int c = 0; c < p->max_cycles && remaining > 0; ++c) {
-    if (ctx->timing) {  // timing mode: the same cycles enqueued one operator after another
+    if (eager) {  // the same cycles enqueued one operator after another
       for (int i = 0; i < nops; ++i) {
         const fab_status es = cycle_of(i, s);
         if (es != FAB_OK) return es;

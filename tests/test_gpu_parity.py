@@ -1136,8 +1136,9 @@ def test_ragged_mixed_types_and_zero_rhs(fab):
     """One ragged solve over operators of uneven size and type: FP64 and FP32 Laplacians of four
     grid sizes, the anisotropic operator, and a zero right-hand side (x = 0 exactly); each against
     the closed form and against its own single solve.  It runs in a context of its own, whose first
-    ragged call it is (a second call with other outputs, which re-captures the ragged graph, is the
-    skipped case above)."""
+    ragged call it is (a second call that re-captured the ragged graph is the skipped case above).
+    Then a call on three of the operators, which runs uncaptured, and the first call again, which
+    replays its graph: both repeat the first call's bits."""
     own = fab.Context()
     ops = []
     try:
@@ -1165,6 +1166,17 @@ def test_ragged_mixed_types_and_zero_rhs(fab):
             xs1, info1 = fab.solve(ops[i], bs[i], "exp", t=1e-3, **kw)
             assert info1["cycles"] == infos[i]["cycles"]
             assert _rel(got, xs1[:, 0].cpu().numpy()) <= (1e-6 if dts[i] == torch.float32 else 1e-12), i
+        # a second ragged call on other operators (a different graph key) runs uncaptured, leaving
+        # the context's graph in place: the same bits and cycle counts as the captured call
+        first = [v.cpu().clone() for v in xs]
+        sub, sub_infos = fab.solve_ragged(ops[1:4], bs[1:4], "exp", t=1e-3, **kw)
+        for j, i in enumerate(range(1, 4)):
+            assert sub_infos[j]["cycles"] == infos[i]["cycles"], i
+            assert torch.equal(sub[j].cpu(), first[i]), i
+        # and the first key again replays the captured graph into the first outputs
+        again, again_infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, xs=xs, **kw)
+        assert [i["cycles"] for i in again_infos] == [i["cycles"] for i in infos]
+        assert all(torch.equal(a.cpu(), b) for a, b in zip(again, first))
     finally:
         torch.cuda.synchronize()
         for op in ops:
