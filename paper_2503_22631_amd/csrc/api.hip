@@ -123,12 +123,12 @@ struct fab_ctx {
   std::vector<Tuned> tuned;
   int force_group = 0;  // fab_batch_group: 0 = autotune
   double div_limit = kDivergedEst;  // fab_divergence_limit: relative increment that abandons a solve
-  // ragged solves: branch streams and fork/join events of the captured graph, and its cache
+  // ragged solves: branch streams, the fork/join events around the branch graphs, and their cache
   std::vector<hipStream_t> branch;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   std::vector<uintptr_t> ragged_key;
-  hipGraphExec_t ragged_exec = nullptr;
+  std::vector<hipGraphExec_t> ragged_execs;  // one per branch stream
   std::vector<Cached> graphs;
 };
 
@@ -566,7 +566,7 @@ fab_status fab_create(fab_ctx** ctx, void* hip_stream) {
 fab_status fab_destroy(fab_ctx* c) {
   if (!c) return FAB_E_INVALID;
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-  if (c->ragged_exec) (void)hipGraphExecDestroy(c->ragged_exec);
+  for (auto& g : c->ragged_execs) (void)hipGraphExecDestroy(g);
   for (auto& st : c->branch) (void)hipStreamDestroy(st);
   for (auto& e : c->join) (void)hipEventDestroy(e);
   if (c->fork) (void)hipEventDestroy(c->fork);
@@ -1142,39 +1142,46 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
     B.ldx = ops[i]->n;
     return enqueue_cycle(ctx, st, ops[i], p, fun, nt, L[i], q[i], x[i], ctx->h_rep + i, true, nullptr, B);
   };
-  // The context's first ragged call captures its graph, and calls with the same key replay it.
-  // A call with another key does not replace it: its cycles run uncaptured, one operator after
-  // another on the work stream, as in timing mode.  (Replacing the graph, a new capture over the
-  // same branch streams and fork/join events, is the call in which a host segmentation fault was
-  // seen once, with its cause not found; that path is switched off.)
-  const bool eager = ctx->timing || (ctx->ragged_exec && key != ctx->ragged_key);
-  if (!eager && !ctx->ragged_exec) {
-    FAB_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    fab_status es = FAB_OK;
-    hipError_t he = hipEventRecord(ctx->fork, s);
-    for (int j = 0; j < nbr && he == hipSuccess; ++j) he = hipStreamWaitEvent(ctx->branch[j], ctx->fork, 0);
-    for (int i = 0; i < nops && he == hipSuccess && es == FAB_OK; ++i) es = cycle_of(i, ctx->branch[i % nbr]);
-    for (int j = 0; j < nbr && he == hipSuccess && es == FAB_OK; ++j) {
-      he = hipEventRecord(ctx->join[j], ctx->branch[j]);
-      if (he == hipSuccess) he = hipStreamWaitEvent(s, ctx->join[j], 0);
+  // The context's first ragged call captures its graphs, one per branch stream (branch j: the
+  // cycles of operators j, j + nbr, ... in turn), and calls with the same key replay them, each
+  // branch on its own stream between a fork and a join event.  (One graph whose branches were
+  // forked inside it ran its nodes one after another on this runtime: 32 operators' kernels never
+  // overlapped.)  A call with another key does not replace the graphs: its cycles run uncaptured,
+  // one operator after another on the work stream, as in timing mode.  (Replacing the graph, a new
+  // capture over the same branch streams and fork/join events, is the call in which a host
+  // segmentation fault was seen once, with its cause not found; that path is switched off.)
+  const bool eager = ctx->timing || (!ctx->ragged_execs.empty() && key != ctx->ragged_key);
+  if (!eager && ctx->ragged_execs.empty()) {
+    std::vector<hipGraphExec_t> execs;
+    auto drop = [&execs]() {
+      for (auto& g : execs) (void)hipGraphExecDestroy(g);
+    };
+    for (int j = 0; j < nbr; ++j) {
+      hipStream_t bst = ctx->branch[j];
+      const hipError_t be = hipStreamBeginCapture(bst, hipStreamCaptureModeThreadLocal);
+      if (be != hipSuccess) {
+        drop();
+        return hip_fail(be, "hipStreamBeginCapture", __LINE__);
+      }
+      fab_status es = FAB_OK;
+      for (int i = j; i < nops && es == FAB_OK; i += nbr) es = cycle_of(i, bst);
+      hipGraph_t graph = nullptr;
+      const hipError_t ce = hipStreamEndCapture(bst, &graph);  // always end the capture
+      if (es != FAB_OK || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        drop();
+        return es != FAB_OK ? es : hip_fail(ce, "hipStreamEndCapture", __LINE__);
+      }
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        drop();
+        return hip_fail(ie, "hipGraphInstantiate", __LINE__);
+      }
+      execs.push_back(ex);
     }
-    hipGraph_t graph = nullptr;
-    const hipError_t ce = hipStreamEndCapture(s, &graph);  // always end the capture
-    if (es != FAB_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return es;
-    }
-    if (he != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return hip_fail(he, "ragged capture", __LINE__);
-    }
-    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture", __LINE__);
-    const hipError_t ie = hipGraphInstantiate(&ctx->ragged_exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-      ctx->ragged_exec = nullptr;
-      return hip_fail(ie, "hipGraphInstantiate", __LINE__);
-    }
+    ctx->ragged_execs = std::move(execs);
     ctx->ragged_key = key;
   }
   std::vector<Track> tr(nops);
@@ -1186,7 +1193,13 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
         if (es != FAB_OK) return es;
       }
     } else {
-      FAB_TRY(hipGraphLaunch(ctx->ragged_exec, s));
+      FAB_TRY(hipEventRecord(ctx->fork, s));
+      for (int j = 0; j < nbr; ++j) {
+        FAB_TRY(hipStreamWaitEvent(ctx->branch[j], ctx->fork, 0));
+        FAB_TRY(hipGraphLaunch(ctx->ragged_execs[j], ctx->branch[j]));
+        FAB_TRY(hipEventRecord(ctx->join[j], ctx->branch[j]));
+        FAB_TRY(hipStreamWaitEvent(s, ctx->join[j], 0));
+      }
     }
     FAB_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < nops; ++i)
