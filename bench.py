@@ -199,6 +199,71 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_json: str = TRAFFIC_FILE, 
     print(json.dumps(rec))
 
 
+def profile_ragged():
+    """A short run for rocprofv3 --kernel-trace: the ragged workload (32 FP32 Laplacians, 64^2 ..
+    512^2, exp t = 1e-3, m = 20, k = 2, d = 80), a first call (capture and replay), a one-element
+    fill as a marker, then one replay of the branch graphs into the first call's outputs."""
+    import numpy as np
+    import torch
+
+    import paper_2503_22631_amd as fab
+    import workloads as wl
+
+    ctx = fab.Context()
+    Ns = [int(round(64 * 8 ** (i / 31))) for i in range(32)]
+    ops, bs = [], []
+    for i, Ng in enumerate(Ns):
+        Ag = wl.laplacian_2d(Ng)
+        ops.append(fab.CSROperator.from_arrays(ctx, Ag.rowptr, Ag.colind, Ag.vals, dtype=torch.float32))
+        bs.append(torch.as_tensor(wl.gaussian_vector(Ag.n, 1000 + i).astype(np.float32), device="cuda"))
+    kw = dict(m=20, k=2, d=80, zeta=8, seed=1, tol=1e-6, max_cycles=300)
+    xs = fab.solve_ragged(ops, bs, "exp", t=1e-3, **kw)[0]
+    torch.cuda.synchronize()
+    torch.zeros(1, device="cuda")  # marker between the two calls in the trace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = fab.solve_ragged(ops, bs, "exp", t=1e-3, xs=xs, **kw)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_ragged": True, "operators": len(ops), "replay_seconds": time.perf_counter() - t0,
+                      "cycles": max(i["cycles"] for i in infos)}))
+    return 0
+
+
+def summarize_overlap(trace_dir: str, out_md: str, command: str):
+    """How much the library's kernels after the last non-library kernel (the marker of
+    --profile-ragged) overlap in time: span, sum of durations, union of intervals, most at once."""
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = sorted(csv.DictReader(open(f)), key=lambda r: int(r["Start_Timestamp"]))
+    last = max(i for i, r in enumerate(rows) if "fab::" not in r["Kernel_Name"])
+    iv = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows[last + 1:] if "fab::" in r["Kernel_Name"]]
+    total = sum(e - s for s, e in iv)
+    union, cs, ce = 0, None, None
+    for s, e in iv:
+        if cs is None or s > ce:
+            union += (ce - cs) if cs is not None else 0
+            cs, ce = s, e
+        else:
+            ce = max(ce, e)
+    union += ce - cs
+    ev = sorted([(s, 1) for s, _ in iv] + [(e, -1) for _, e in iv])
+    cur = most = 0
+    for _, dlt in ev:
+        cur += dlt
+        most = max(most, cur)
+    span = max(e for _, e in iv) - iv[0][0]
+    lines = ["# Kernel overlap of one ragged solve (32 FP32 Laplacians, 64^2 .. 512^2)", "",
+             "Command (from the repository root, on the MI355X machine):", "", "```", command, "```", "",
+             "| quantity | value |", "|---|---|",
+             f"| kernels of the replayed solve | {len(iv)} |",
+             f"| span, first start to last end | {span / 1e6:.2f} ms |",
+             f"| sum of kernel durations | {total / 1e6:.2f} ms |",
+             f"| union of kernel intervals | {union / 1e6:.2f} ms |",
+             f"| sum / union (average kernels running at once) | {total / union:.2f} |",
+             f"| most kernels running at once | {most} |", ""]
+    open(out_md, "w").write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def summarize_trace(trace_dir: str, out_md: str, command: str, workload: str = None):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
@@ -525,6 +590,9 @@ def main():
                     help="short batched 1024^2 x 64 run for rocprofv3 (grouped kernel)")
     ap.add_argument("--profile-256", choices=("f32", "f64"),
                     help="a short 256^3 z^(-1/2) run (FP32 or FP64 values and basis) for rocprofv3")
+    ap.add_argument("--profile-ragged", action="store_true",
+                    help="the ragged 32-operator solve, replayed once after a marker, for rocprofv3 --kernel-trace")
+    ap.add_argument("--summarize-overlap", nargs=3, metavar=("TRACE_DIR", "OUT_MD", "COMMAND"))
     ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
                     help="FETCH_DIR WRITE_DIR [OUT_JSON WORKLOAD KERNEL_LABEL KERNEL_REGEX]")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG", help="TRACE_DIR OUT_MD COMMAND [WORKLOAD]")
@@ -535,6 +603,11 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return 0
+    if args.summarize_overlap:
+        summarize_overlap(*args.summarize_overlap)
+        return 0
+    if args.profile_ragged:
+        return profile_ragged()
     if args.profile_256:
         return profile_256(args.profile_256)
     if args.profile_batched:
