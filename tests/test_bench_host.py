@@ -40,3 +40,24 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_overlap_summary_counts_only_the_library_kernels_after_the_marker(bench, tmp_path):
+    """summarize_overlap takes the library's kernels after the last other kernel (the marker) and
+    reports their summed durations, the union of their intervals and the most running at once:
+    here two overlapping kernels [0, 10) and [5, 15), then one [20, 30), in ns."""
+    import csv
+    rows = [("fab::k_before", 0, 100), ("at::native::fill", 200, 210),
+            ("fab::k_a", 1000, 1010), ("fab::k_b", 1005, 1015), ("fab::k_c", 1020, 1030)]
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for r in rows:
+            w.writerow(r)
+    out = tmp_path / "overlap.md"
+    bench.summarize_overlap(str(tmp_path), str(out), "cmd")
+    text = out.read_text()
+    assert "| kernels of the replayed solve | 3 |" in text
+    assert "| sum of kernel durations | 0.00 ms |" in text  # 30 ns
+    assert "| sum / union (average kernels running at once) | 1.20 |" in text  # 30 / 25
+    assert "| most kernels running at once | 2 |" in text
