@@ -300,7 +300,8 @@ fab_status fab_cycle_debug(fab_ctx* ctx, const fab_op* A, const void* v, const f
 fab_status fab_divergence_limit(fab_ctx* ctx, double limit);
 
 /* Members per block of the batched product + sketch kernel: 1, 4, 8 or 16 (a group that does not
- * fit the grouped kernel's LDS falls back to 1); 0 (the default) times every candidate on the
+ * fit the grouped kernel's LDS, or an operator whose vectors reach 2^31 bytes, n times the value
+ * size, falls back to 1); 0 (the default) times every candidate on the
  * first batched solve of each operator and batch shape and keeps the fastest.  Test hook: pins a
  * path.  Errors: FAB_E_INVALID (ctx NULL or another G). */
 fab_status fab_batch_group(fab_ctx* ctx, int32_t G);
