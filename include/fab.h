@@ -232,7 +232,7 @@ fab_status fab_solve_batched(fab_ctx* ctx, const fab_op* A, int32_t fun, const d
  * nops operators of uneven size (any mix of n, nnz and dtype), one right-hand
  * side each: x[i] (n_i x nt FP64) = f(A_i) b[i].  b and x are host arrays of nops device
  * pointers.  Every operator runs the method of fab_solve in its own part of work
- * (fab_workspace_size_ragged bytes); the operators are spread over 8 branch streams, the cycles
+ * (fab_workspace_size_ragged bytes); the operators are spread over 16 branch streams, the cycles
  * of each branch's operators are captured into one graph per branch, and the branch graphs are
  * launched together once per cycle until every operator has finished.  A context keeps the
  * graphs of its first ragged call and replays them for later calls with the same operators,

@@ -1045,7 +1045,8 @@ static fab_status solve_batch(fab_ctx* ctx, const fab_op* A, int32_t fun, const 
 }
 
 // ----------------------------------------------------------------------------- ragged batches
-constexpr int kBranches = 8;  // branch streams of the captured ragged graph
+constexpr int kBranches = 16;  // branch streams of the ragged graphs (one replayed solve of 32
+                                // operators: 50 ms with 4, 37 with 8, 31 with 16 and with 32)
 
 fab_status fab_workspace_size_ragged(int32_t nops, const fab_op* const* ops, const fab_params* p, int32_t nt,
                                      size_t* h_bytes) {
@@ -1145,7 +1146,7 @@ fab_status fab_solve_ragged(fab_ctx* ctx, int32_t nops, const fab_op* const* ops
   // The context's first ragged call captures its graphs, one per branch stream (branch j: the
   // cycles of operators j, j + nbr, ... in turn), and calls with the same key replay them, each
   // branch on its own stream between a fork and a join event.  (One graph whose branches were
-  // forked inside it took 67 ms per solve of 32 operators, these graphs take 36 ms.)  A call with
+  // forked inside it took 67 ms per solve of 32 operators, these graphs 31 ms on 16 streams.)  A call with
   // another key does not replace the graphs: its cycles run uncaptured,
   // one operator after another on the work stream, as in timing mode.  (Replacing the graph, a new
   // capture over the same branch streams and fork/join events, is the call in which a host
